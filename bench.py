@@ -1,0 +1,204 @@
+"""Throughput of the exact O(mM) BP message update on one MI355X.
+
+One step = the whole single-grid hot path on the 480x640 synthetic stereo MRF
+(M=64, T=4, alpha=0.5): set the potential, reset messages to 1/M, 100
+synchronous sum-product iterations of the sparse update (Eq. 7), beliefs
+(Eq. 3) and MAP labels.  Inputs are resident in HBM before timing starts.
+
+value = directed-edge x label message updates per second over the timed
+steps.  Beside it: max-product and checkerboard legs, the dense O(M^2)
+comparison kernel, the dominant kernel's roofline (algorithmic bytes per
+launch / HIP-event-timed average launch duration, against 8 TB/s), and the
+FP64 oracle timed on a bounded sample on the host CPU.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edge·label msg updates/s, sparse O(mM) vs dense O(M²), % HBM peak; fwd+bwd it/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_sync_iter(cfg):
+    """Each live message entry read once and written once, unary read once:
+    4 * M * (2E + N) bytes per synchronous iteration."""
+    return 4 * cfg.M * (2 * cfg.n_directed_edges + cfg.n_pixels)
+
+
+def time_launches(grid, mode, n, schedule, dense, reps):
+    """Average duration of one update launch, from HIP events on the stream
+    the library launches on (torch's current stream)."""
+    import torch
+    s = torch.cuda.current_stream()
+    grid.reset()
+    grid.iterate(mode, 2, schedule, dense=dense)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    total = 0.0
+    for _ in range(reps):
+        grid.reset()
+        e0.record(s)
+        grid.iterate(mode, n, schedule, dense=dense)
+        e1.record(s)
+        e1.synchronize()
+        total += e0.elapsed_time(e1)
+    return total / (reps * n)  # ms per launch
+
+
+def cpu_baseline(cfg, g32):
+    """The FP64 oracle's sparse (Eq. 7) synchronous iteration on the full grid,
+    one BLAS thread, timed on this host: a bounded sample of the workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import grid_bp as gb
+    pot = gb.truncated_linear(cfg.M, cfg.T, cfg.alpha)
+    g = g32.astype(np.float64)
+    state = gb.init_messages(cfg.H, cfg.W, cfg.M)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        gb.sync_step(g, state, pot, gb.SUM, gb.SPARSE)
+        dt = time.perf_counter() - t0
+    updates = cfg.n_directed_edges * cfg.M
+    return {"value": updates / dt, "unit": "edge·label updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 synchronous sum-product iteration of the full {cfg.H}x{cfg.W} grid, "
+                      f"M={cfg.M}, sparse Eq. 7 form, FP64 NumPy, 1 thread ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--legs", action="store_true", help="also time max/checkerboard/dense legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this library has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import CONFIGS, make_config
+
+    cfg = CONFIGS["stereo480x640"]
+    g32, _ = make_config(cfg)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g = torch.from_numpy(g32).to(dev)
+    grid = Grid(cfg.H, cfg.W)
+    grid.set_potential(cfg.M, cfg.T, cfg.alpha)
+    grid.set_unary(g)
+    beliefs = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device=dev)
+    labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device=dev)
+    updates_per_iter = cfg.n_directed_edges * cfg.M
+
+    def step(mode="sum", schedule="sync", dense=False):
+        grid.set_potential(cfg.M, cfg.T, cfg.alpha)
+        grid.reset()
+        n = cfg.iters if schedule == "sync" else 2 * cfg.iters
+        grid.iterate(mode, n, schedule, dense=dense)
+        grid.beliefs(beliefs)
+        grid.map_labels(labels)
+
+    log(f"bench: {cfg.name} {cfg.H}x{cfg.W} M={cfg.M} T={cfg.T} iters={cfg.iters}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = updates_per_iter * cfg.iters * args.steps / dt
+    log(f"bench: sum sync {ms_per_step:.3f} ms/step, {value:.4e} updates/s")
+
+    # dominant kernel: the sparse sum-product update launch
+    reps = max(2, args.steps)
+    ms_launch = time_launches(grid, "sum", cfg.iters, "sync", False, reps)
+    bytes_launch = alg_bytes_per_sync_iter(cfg)
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "sparse_update_kernel<LPL=4,K=1,sum>",
+                "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3}
+    log(f"bench: sparse sum launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+
+    extra = {"sparse_sum_sync_launch_us": ms_launch * 1e3}
+    if args.legs:
+        for mode, sched, dense in (("max", "sync", False), ("sum", "checkerboard", False),
+                                   ("max", "checkerboard", False), ("sum", "sync", True),
+                                   ("max", "sync", True)):
+            n = cfg.iters if sched == "sync" else 2 * cfg.iters
+            ms = time_launches(grid, mode, n, sched, dense, 2)
+            per_iter = ms * (1 if sched == "sync" else 2)
+            key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
+            extra[key + "_updates_per_s"] = updates_per_iter / (per_iter * 1e-3)
+            extra[key + "_launch_us"] = ms * 1e3
+            log(f"bench: {key}: {ms * 1e3:.1f} us/launch, {updates_per_iter / (per_iter * 1e-3):.4e} updates/s")
+        for mode in ("sum", "max"):
+            sp = extra.get(f"sparse_{mode}_sync_updates_per_s", value if mode == "sum" else None)
+            dn = extra.get(f"dense_{mode}_sync_updates_per_s")
+            if sp and dn:
+                extra[f"sparse_over_dense_{mode}"] = sp / dn
+        extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
+    # copy-kernel ceiling on this GPU (torch device-to-device copy)
+    big = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(big)
+    dst.copy_(big)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(big)
+    e1.record()
+    e1.synchronize()
+    extra["copy_GBs"] = 2 * big.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del big, dst
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: timing the FP64 oracle on the host (bounded sample)")
+        cpu = cpu_baseline(cfg, g32)
+        log(f"bench: cpu oracle {cpu['value']:.3e} updates/s")
+
+    grid.close()
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge·label updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.H}x{cfg.W} grid, M={cfg.M}, T={cfg.T}, "
+                               f"alpha={cfg.alpha}, {cfg.iters} synchronous sum-product iterations "
+                               f"(sparse O(mM) update) + beliefs + MAP",
+                   "H": cfg.H, "W": cfg.W, "M": cfg.M, "T": cfg.T, "iters": cfg.iters,
+                   "mode": "sum", "schedule": "sync", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * bp.h -- C ABI of the MI355X (gfx950) exact O(mM) belief-propagation library.
+ *
+ * Method: Coughlan & Shen, "An Embarrassingly Simple Speed-Up of Belief
+ * Propagation with Robust Potentials".  For a pairwise MRF on a 4-connected
+ * H x W grid (Sec. 1, Eq. 1) with M labels and the truncated-linear robust
+ * potential f(x_i, x_j) = exp(-alpha |x_i - x_j|) for |x_i - x_j| <= T and a
+ * constant fbar otherwise (Sec. 1, Sec. 6), each message update
+ *   sum-product (Sec. 4, Eq. 7):
+ *     m(x_j) = fbar * sum_x h(x) + sum_{|x - x_j| <= T} (f(x, x_j) - fbar) h(x)
+ *   max-product (Sec. 5, Eq. 11, product domain):
+ *     m(x_j) = max(fbar * max_x h(x), max_{|x - x_j| <= T} f(x, x_j) h(x))
+ * costs O(mM) with m = 2T + 1 instead of the O(M^2) of Eq. 2 / Eq. 9, with
+ * h(x) = g(x) * product of the incoming messages except the target's (Eq. 5).
+ * Every message is normalised to sum 1 after it is computed (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: every int-returning call returns BP_OK (0) or a negative
+ *   bp_status.  bp_status_string() names a code; bp_last_error() returns a
+ *   thread-local description of the most recent failure on this thread.
+ * - Memory: the caller owns all device memory (unary, outputs, workspace);
+ *   pointers marked "device" must be device (HBM) pointers of the GPU that
+ *   was current at bp_init_grid.  The library keeps only host-side state.
+ *   Borrowed pointers must stay valid until they are replaced or the handle
+ *   is destroyed.
+ * - Asynchrony: device work is enqueued on the handle's HIP stream and the
+ *   call returns before it runs; the caller synchronises that stream.
+ *   Argument and call-order errors are detected synchronously, before any
+ *   work is enqueued.  Launch failures are reported as BP_EHIP.
+ * - Threads: a handle must not be used by two threads at once.
+ * - Layouts (row-major, float32, labels contiguous):
+ *     unary g        [H][W][M]      g >= 0, finite, every pixel's row nonzero
+ *     beliefs        [H][W][M]      each row sums to 1
+ *     labels         [H][W]         int32 in [0, M)
+ *     messages       [4][H][W][M]   inbox planes: plane k at pixel p holds the
+ *                                   message into p from its neighbour in
+ *                                   direction k = 0 left, 1 right, 2 up,
+ *                                   3 down.  Slots whose neighbour is off the
+ *                                   grid are never read nor written by an
+ *                                   update; bp_reset_messages sets them to 1/M.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bp_grid bp_grid;   /* opaque single-grid handle */
+typedef struct bp_batch bp_batch; /* opaque handle for many independent grids */
+
+enum bp_status {
+    BP_OK = 0,
+    BP_EINVAL = -1,       /* bad argument (null pointer, size, range, alignment) */
+    BP_ESTATE = -2,       /* call out of order (e.g. iterate before set_unary) */
+    BP_ENOMEM = -3,       /* workspace too small or host allocation failed */
+    BP_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    BP_EUNSUPPORTED = -5  /* valid request this library does not implement */
+};
+
+enum bp_mode { BP_SUM_PRODUCT = 0, BP_MAX_PRODUCT = 1 };
+
+enum bp_schedule {
+    BP_SCHED_SYNC = 0,        /* Jacobi: every message from the previous state */
+    BP_SCHED_CHECKERBOARD = 1 /* bipartite: pass t updates messages sent by
+                                 pixels with (row + col) % 2 == t % 2, in place */
+};
+
+#define BP_MAX_LABELS 256     /* largest M this library accepts */
+#define BP_FBAR_TIED (-1.0f)  /* bp_set_potential: fbar := f(T) = exp(-alpha T) */
+
+/* Create a handle for an H x W grid (H, W >= 1, H*W < 2^31 / 4).
+ * hip_stream: a hipStream_t, or NULL for the default stream.  The GPU that is
+ * current on the calling thread becomes the handle's device.
+ * Errors: BP_EINVAL (sizes, null out), BP_EHIP (no usable device). */
+int bp_init_grid(bp_grid** out, int32_t H, int32_t W, void* hip_stream);
+
+/* Change the stream later work is enqueued on. */
+int bp_set_stream(bp_grid* grid, void* hip_stream);
+
+/* Set the truncated-linear potential (Sec. 1, Sec. 6; sparse compatibility
+ * Sec. 4): f(d) = exp(-alpha |d|) for |d| <= T, fbar for |d| > T, where
+ * Nbd(x_j) = {x : |x - x_j| <= T, 0 <= x < M} (clipped at the label range).
+ * fbar = exp(-alpha T) gives exp(-alpha min(|d|, T)); fbar = 0 gives Eq. 8.
+ * fbar = BP_FBAR_TIED ties fbar to f(T): fbar := exp(-alpha T) rounded to
+ * float32, the same value as the table's f(T), so the potential is exactly
+ * exp(-alpha min(|d|, T)) in float32 and d fbar / d alpha = -T fbar.
+ * The table is built in double on the host and rounded to float32.
+ * Requires 1 <= M <= BP_MAX_LABELS, 0 <= T < M, alpha finite, fbar finite
+ * and >= 0 or BP_FBAR_TIED (else BP_EINVAL).  Changing M invalidates the workspace and the
+ * unary (attach and set them again); changing only T, alpha or fbar keeps
+ * the messages. */
+int bp_set_potential(bp_grid* grid, int32_t M, int32_t T, float alpha, float fbar);
+
+/* Bytes of device workspace needed after bp_set_potential (two message
+ * buffers for the synchronous ping-pong plus small tables), or a negative
+ * status. */
+int64_t bp_workspace_bytes(const bp_grid* grid);
+
+/* Attach caller-owned device workspace (>= bp_workspace_bytes, 256-byte
+ * aligned); resets the messages to 1/M.  Errors: BP_ESTATE before
+ * set_potential, BP_ENOMEM if too small, BP_EINVAL on misalignment. */
+int bp_attach_workspace(bp_grid* grid, void* dev_ptr, int64_t bytes);
+
+/* Borrow the unary table g (device, [H][W][M], 16-byte aligned) until the
+ * next bp_set_unary, a change of M, or bp_destroy. */
+int bp_set_unary(bp_grid* grid, const float* g_dev);
+
+/* All messages := 1/M (the usual uniform start). */
+int bp_reset_messages(bp_grid* grid);
+
+/* Run n_iters >= 0 iterations of the O(mM) update (Eq. 7 for sum-product,
+ * Eq. 11 for max-product) with the given schedule.  For the checkerboard
+ * schedule n_iters counts passes (two passes update every message once) and
+ * the pass parity continues across calls until the next reset.
+ * Max-product requires f >= fbar on every compatible pair (Sec. 5: Eq. 11
+ * equals Eq. 9 only then), i.e. fbar <= f(T) as rounded to float32;
+ * otherwise BP_EUNSUPPORTED.  Sum-product accepts any fbar >= 0. */
+int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
+
+/* Same contract as bp_iterate, but each message is the plain O(M^2) sum or
+ * max over all sender labels (Eq. 2 / Eq. 9) with the same float32 potential
+ * table.  The comparison point for the sparse update; requires M <= 128. */
+int bp_iterate_dense(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
+
+/* Beliefs (Eq. 3) from the current messages into out_dev (device,
+ * [H][W][M]); rows sum to 1.  For max-product they are sum-normalised
+ * max-marginals. */
+int bp_beliefs(bp_grid* grid, float* out_dev);
+
+/* MAP labels: argmax over labels of the float32 beliefs bp_beliefs would
+ * return, lowest label on ties, into out_dev (device, [H][W] int32). */
+int bp_map_labels(bp_grid* grid, int32_t* out_dev);
+
+/* Copy the current message state out of / into the handle (device,
+ * [4][H][W][M] layout above); for checkpoints and warm starts.  set_messages
+ * keeps the checkerboard pass parity. */
+int bp_get_messages(const bp_grid* grid, float* dst_dev);
+int bp_set_messages(bp_grid* grid, const float* src_dev);
+
+/* Free the handle (host memory only; the caller frees its device memory
+ * after its stream has drained). */
+int bp_destroy(bp_grid* grid);
+
+const char* bp_status_string(int status);
+const char* bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BP_H */

@@ -324,6 +324,8 @@ def map_labels(b):
 
 def top2_margin(b):
     """Difference between the largest and second-largest belief per pixel."""
+    if b.shape[-1] < 2:
+        return np.full(b.shape[:-1], np.inf)
     s = np.sort(b, axis=-1)
     return s[..., -1] - s[..., -2]
 

@@ -1,0 +1,172 @@
+"""ctypes binding of libbp_hip.so: one Python function per C entry point,
+same names, argument marshalling only.
+
+Device buffers are passed as torch CUDA tensors (or raw integer device
+addresses); the HIP stream defaults to torch's current stream on the handle's
+device.  Every status < 0 raises BPError with the library's message.  There is
+no CPU fallback: if the shared library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libbp_hip.so")
+HEADER = os.path.join(os.path.dirname(PKG_DIR), "include", "bp.h")
+
+BP_OK, BP_EINVAL, BP_ESTATE, BP_ENOMEM, BP_EHIP, BP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+BP_SUM_PRODUCT, BP_MAX_PRODUCT = 0, 1
+BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD = 0, 1
+BP_MAX_LABELS = 256
+BP_FBAR_TIED = -1.0
+
+_c_int, _c_i32, _c_i64, _c_f, _vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
+
+
+class BPError(RuntimeError):
+    def __init__(self, status, func, msg):
+        super().__init__(f"{func} -> {status}: {msg}")
+        self.status = status
+        self.func = func
+
+
+# name: (restype, argtypes)
+_PROTOS = {
+    "bp_init_grid": (_c_int, [ctypes.POINTER(_vp), _c_i32, _c_i32, _vp]),
+    "bp_set_stream": (_c_int, [_vp, _vp]),
+    "bp_set_potential": (_c_int, [_vp, _c_i32, _c_i32, _c_f, _c_f]),
+    "bp_workspace_bytes": (_c_i64, [_vp]),
+    "bp_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
+    "bp_set_unary": (_c_int, [_vp, _vp]),
+    "bp_reset_messages": (_c_int, [_vp]),
+    "bp_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
+    "bp_iterate_dense": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
+    "bp_beliefs": (_c_int, [_vp, _vp]),
+    "bp_map_labels": (_c_int, [_vp, _vp]),
+    "bp_get_messages": (_c_int, [_vp, _vp]),
+    "bp_set_messages": (_c_int, [_vp, _vp]),
+    "bp_destroy": (_c_int, [_vp]),
+    "bp_status_string": (ctypes.c_char_p, [_c_int]),
+    "bp_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def header_symbols(path=HEADER):
+    """Names of the functions include/bp.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bp_\w+)\s*\(", text)))
+
+
+def lib():
+    """Load libbp_hip.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    """Device address of a torch tensor (or an int address / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream, device=None):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream(device).cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status, func):
+    if status < 0:
+        raise BPError(status, func, lib().bp_last_error().decode())
+    return status
+
+
+# ------------------------------------------------------------------ ABI ----
+
+def bp_init_grid(H, W, stream=None):
+    h = _vp()
+    _check(lib().bp_init_grid(ctypes.byref(h), H, W, _stream(stream)), "bp_init_grid")
+    return h.value
+
+
+def bp_set_stream(handle, stream=None):
+    _check(lib().bp_set_stream(handle, _stream(stream)), "bp_set_stream")
+
+
+def bp_set_potential(handle, M, T, alpha, fbar):
+    _check(lib().bp_set_potential(handle, M, T, alpha, fbar), "bp_set_potential")
+
+
+def bp_workspace_bytes(handle):
+    return _check(lib().bp_workspace_bytes(handle), "bp_workspace_bytes")
+
+
+def bp_attach_workspace(handle, ws, nbytes=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    _check(lib().bp_attach_workspace(handle, _ptr(ws), nbytes), "bp_attach_workspace")
+
+
+def bp_set_unary(handle, g):
+    _check(lib().bp_set_unary(handle, _ptr(g)), "bp_set_unary")
+
+
+def bp_reset_messages(handle):
+    _check(lib().bp_reset_messages(handle), "bp_reset_messages")
+
+
+def bp_iterate(handle, mode, n_iters, schedule):
+    _check(lib().bp_iterate(handle, mode, n_iters, schedule), "bp_iterate")
+
+
+def bp_iterate_dense(handle, mode, n_iters, schedule):
+    _check(lib().bp_iterate_dense(handle, mode, n_iters, schedule), "bp_iterate_dense")
+
+
+def bp_beliefs(handle, out):
+    _check(lib().bp_beliefs(handle, _ptr(out)), "bp_beliefs")
+
+
+def bp_map_labels(handle, out):
+    _check(lib().bp_map_labels(handle, _ptr(out)), "bp_map_labels")
+
+
+def bp_get_messages(handle, dst):
+    _check(lib().bp_get_messages(handle, _ptr(dst)), "bp_get_messages")
+
+
+def bp_set_messages(handle, src):
+    _check(lib().bp_set_messages(handle, _ptr(src)), "bp_set_messages")
+
+
+def bp_destroy(handle):
+    _check(lib().bp_destroy(handle), "bp_destroy")
+
+
+def bp_status_string(status):
+    return lib().bp_status_string(status).decode()
+
+
+def bp_last_error():
+    return lib().bp_last_error().decode()

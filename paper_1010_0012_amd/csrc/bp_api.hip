@@ -1,0 +1,291 @@
+// C ABI of the grid BP library: handle state, argument and call-order checks,
+// potential tables, workspace carving and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/bp.h"
+#include "bp_internal.hpp"
+#include "bp_launch.hpp"
+
+using bpk::UpdateArgs;
+
+namespace bpi {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(BP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// f(d) = exp(-alpha d) in double, rounded to float32.
+void build_tables(bp_grid* G) {
+    for (int d = 0; d < bpk::kMaxTab; ++d) {
+        const bool in = d <= G->T;
+        const double f = std::exp(-(double)G->alpha * d);
+        G->tab_f[d] = in ? (float)f : 0.0f;
+        G->tab_w[d] = in ? (float)(f - (double)G->fbar) : 0.0f;
+    }
+}
+
+bool max_product_ok(const bp_grid* G) {
+    for (int d = 0; d <= G->T; ++d)
+        if (!(G->tab_f[d] >= G->fbar)) return false;
+    return true;
+}
+
+UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int colour) {
+    UpdateArgs a;
+    memset(&a, 0, sizeof a);
+    a.g = G->g;
+    a.in = in;
+    a.out = out;
+    a.H = G->H;
+    a.W = G->W;
+    a.M = G->M;
+    a.N = G->N;
+    a.colour = colour;
+    a.half_w = (G->W + 1) / 2;
+    a.n_slots = colour < 0 ? G->N : G->H * a.half_w;
+    a.T = G->T;
+    a.fbar = G->fbar;
+    return a;
+}
+
+int check_ready(const bp_grid* G) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
+    if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
+    if (!G->g) return fail(BP_ESTATE, "bp_set_unary has not been called");
+    return BP_OK;
+}
+
+int with_device(const bp_grid* G) {
+    hipError_t e = hipSetDevice(G->dev);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "hipSetDevice");
+}
+
+// One sweep-worth of launches: n synchronous iterations (ping-pong) or n
+// checkerboard passes (in place) of the sparse or dense update.
+int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
+    int st = check_ready(G);
+    if (st) return st;
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD)
+        return fail(BP_EINVAL, "bad schedule %d", schedule);
+    if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
+    if (mode == BP_MAX_PRODUCT && !max_product_ok(G))
+        return fail(BP_EUNSUPPORTED,
+                    "max-product needs f(d) >= fbar for |d| <= T (Eq. 11); fbar=%g exceeds f", G->fbar);
+    if (dense && G->M > 128) return fail(BP_EUNSUPPORTED, "dense kernel supports M <= 128");
+    if ((st = with_device(G))) return st;
+    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+    // sparse sum uses w(d) = f(d) - fbar; sparse max and dense use f(d)
+    const float* tab = (!dense && kmode == bpk::kSum) ? G->tab_w : G->tab_f;
+    for (int t = 0; t < n; ++t) {
+        UpdateArgs a;
+        if (schedule == BP_SCHED_SYNC) {
+            a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
+        } else {
+            a = base_args(G, G->msg[G->cur], G->msg[G->cur], (int)(G->cb_pass & 1));
+        }
+        memcpy(a.tab, tab, sizeof a.tab);
+        hipError_t e = dense ? bpk::launch_dense(a, kmode, G->stream)
+                             : bpk::launch_sparse(a, kmode, G->stream);
+        if (e != hipSuccess) return hip_fail(e, dense ? "dense update launch" : "sparse update launch");
+        if (schedule == BP_SCHED_SYNC) G->cur ^= 1;
+        else G->cb_pass++;
+    }
+    return BP_OK;
+}
+
+}  // namespace bpi
+
+using namespace bpi;
+
+extern "C" {
+
+int bp_init_grid(bp_grid** out, int32_t H, int32_t W, void* hip_stream) {
+    if (!out) return fail(BP_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (H < 1 || W < 1) return fail(BP_EINVAL, "grid %d x %d: both sides must be >= 1", H, W);
+    if ((int64_t)H * W >= (int64_t(1) << 29)) return fail(BP_EINVAL, "grid too large");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int count = 0;
+    e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) return fail(BP_EHIP, "no HIP device available");
+    bp_grid* G = new (std::nothrow) bp_grid();
+    if (!G) return fail(BP_ENOMEM, "host allocation failed");
+    G->dev = dev;
+    G->stream = static_cast<hipStream_t>(hip_stream);
+    G->H = H;
+    G->W = W;
+    G->N = H * W;
+    *out = G;
+    return BP_OK;
+}
+
+int bp_set_stream(bp_grid* G, void* hip_stream) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    G->stream = static_cast<hipStream_t>(hip_stream);
+    return BP_OK;
+}
+
+int bp_set_potential(bp_grid* G, int32_t M, int32_t T, float alpha, float fbar) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (M < 1 || M > BP_MAX_LABELS) return fail(BP_EINVAL, "M=%d outside [1, %d]", M, BP_MAX_LABELS);
+    if (T < 0 || T >= M) return fail(BP_EINVAL, "T=%d outside [0, M-1]", T);
+    if (!std::isfinite(alpha)) return fail(BP_EINVAL, "alpha not finite");
+    const bool tied = fbar == BP_FBAR_TIED;
+    if (tied) fbar = (float)std::exp(-(double)alpha * T);
+    if (!std::isfinite(fbar) || fbar < 0.0f)
+        return fail(BP_EINVAL, "fbar must be finite and >= 0 (or BP_FBAR_TIED)");
+    if (M != G->M) {
+        G->ws = nullptr;
+        G->ws_bytes = 0;
+        G->msg[0] = G->msg[1] = nullptr;
+        G->g = nullptr;
+    }
+    G->M = M;
+    G->T = T;
+    G->alpha = alpha;
+    G->fbar = fbar;
+    G->fbar_tied = tied;
+    build_tables(G);
+    G->pot_set = true;
+    return BP_OK;
+}
+
+int64_t bp_workspace_bytes(const bp_grid* G) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
+    return (int64_t)(2 * align_up(G->msg_floats() * sizeof(float), 256));
+}
+
+int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
+    if (!dev_ptr) return fail(BP_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(BP_EINVAL, "workspace not 256-byte aligned");
+    const int64_t need = bp_workspace_bytes(G);
+    if (bytes < need) return fail(BP_ENOMEM, "workspace %lld bytes < %lld needed", (long long)bytes, (long long)need);
+    G->ws = dev_ptr;
+    G->ws_bytes = bytes;
+    const size_t buf = align_up(G->msg_floats() * sizeof(float), 256);
+    G->msg[0] = static_cast<float*>(dev_ptr);
+    G->msg[1] = reinterpret_cast<float*>(static_cast<char*>(dev_ptr) + buf);
+    return bp_reset_messages(G);
+}
+
+int bp_set_unary(bp_grid* G, const float* g_dev) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
+    if (!g_dev) return fail(BP_EINVAL, "null unary");
+    if (reinterpret_cast<uintptr_t>(g_dev) % 16) return fail(BP_EINVAL, "unary not 16-byte aligned");
+    G->g = g_dev;
+    return BP_OK;
+}
+
+int bp_reset_messages(bp_grid* G) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
+    int st = with_device(G);
+    if (st) return st;
+    G->cur = 0;
+    G->cb_pass = 0;
+    // both ping-pong buffers, so slots no update writes (off-grid neighbours)
+    // read 1/M whichever buffer is current
+    for (int b = 0; b < 2; ++b) {
+        hipError_t e = bpk::launch_fill(G->msg[b], G->msg_floats(), 1.0f / (float)G->M, G->stream);
+        if (e != hipSuccess) return hip_fail(e, "message reset");
+    }
+    return BP_OK;
+}
+
+int bp_iterate(bp_grid* G, int32_t mode, int32_t n_iters, int32_t schedule) {
+    return iterate(G, mode, n_iters, schedule, false);
+}
+
+int bp_iterate_dense(bp_grid* G, int32_t mode, int32_t n_iters, int32_t schedule) {
+    return iterate(G, mode, n_iters, schedule, true);
+}
+
+static int readout(bp_grid* G, float* beliefs, int32_t* labels) {
+    int st = check_ready(G);
+    if (st) return st;
+    if ((st = with_device(G))) return st;
+    UpdateArgs a = base_args(G, G->msg[G->cur], nullptr, -1);
+    hipError_t e = bpk::launch_readout(a, beliefs, labels, G->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "readout launch");
+}
+
+int bp_beliefs(bp_grid* G, float* out_dev) {
+    if (!out_dev) return fail(BP_EINVAL, "null beliefs output");
+    if (reinterpret_cast<uintptr_t>(out_dev) % 16) return fail(BP_EINVAL, "beliefs output not 16-byte aligned");
+    return readout(G, out_dev, nullptr);
+}
+
+int bp_map_labels(bp_grid* G, int32_t* out_dev) {
+    if (!out_dev) return fail(BP_EINVAL, "null labels output");
+    return readout(G, nullptr, out_dev);
+}
+
+int bp_get_messages(const bp_grid* G, float* dst_dev) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
+    if (!dst_dev) return fail(BP_EINVAL, "null destination");
+    int st = with_device(G);
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(dst_dev, G->msg[G->cur], G->msg_floats() * sizeof(float),
+                                  hipMemcpyDeviceToDevice, G->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "hipMemcpyAsync (get messages)");
+}
+
+int bp_set_messages(bp_grid* G, const float* src_dev) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
+    if (!src_dev) return fail(BP_EINVAL, "null source");
+    if (reinterpret_cast<uintptr_t>(src_dev) % 16) return fail(BP_EINVAL, "source not 16-byte aligned");
+    int st = with_device(G);
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(G->msg[G->cur], src_dev, G->msg_floats() * sizeof(float),
+                                  hipMemcpyDeviceToDevice, G->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "hipMemcpyAsync (set messages)");
+}
+
+int bp_destroy(bp_grid* G) {
+    delete G;
+    return BP_OK;
+}
+
+const char* bp_status_string(int status) {
+    switch (status) {
+        case BP_OK: return "BP_OK";
+        case BP_EINVAL: return "BP_EINVAL: invalid argument";
+        case BP_ESTATE: return "BP_ESTATE: call out of order";
+        case BP_ENOMEM: return "BP_ENOMEM: workspace too small or allocation failed";
+        case BP_EHIP: return "BP_EHIP: HIP runtime error";
+        case BP_EUNSUPPORTED: return "BP_EUNSUPPORTED: not supported";
+        default: return "unknown status";
+    }
+}
+
+const char* bp_last_error(void) { return g_last_error; }
+
+}  // extern "C"

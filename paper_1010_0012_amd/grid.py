@@ -1,0 +1,117 @@
+"""Convenience wrapper over one bp_grid handle.
+
+torch owns every device buffer (workspace, unary, outputs); the wrapper keeps
+references so borrowed pointers stay valid, and enqueues on torch's current
+stream of the grid's device.  All compute happens in libbp_hip.so.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _lib as L
+
+MODES = {"sum": L.BP_SUM_PRODUCT, "max": L.BP_MAX_PRODUCT}
+SCHEDULES = {"sync": L.BP_SCHED_SYNC, "checkerboard": L.BP_SCHED_CHECKERBOARD}
+
+
+def _as_code(v, table):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+class Grid:
+    """An H x W grid MRF with the truncated-linear potential.
+
+    >>> grid = Grid(H, W); grid.set_potential(M, T, alpha)
+    >>> grid.set_unary(g_cuda); grid.iterate("sum", 50, "sync")
+    >>> b = grid.beliefs(); lab = grid.map_labels()
+    """
+
+    def __init__(self, H, W, device=None, stream=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self._stream = stream
+            self.handle = L.bp_init_grid(H, W, self._stream_ptr())
+        self.H, self.W = H, W
+        self.M = None
+        self._ws = None
+        self._g = None
+
+    def _stream_ptr(self):
+        if self._stream is not None:
+            return self._stream.cuda_stream
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _sync_stream(self):
+        L.bp_set_stream(self.handle, self._stream_ptr())
+
+    def set_potential(self, M, T, alpha, fbar=None):
+        """fbar=None ties fbar to f(T) = exp(-alpha T) (the library rounds it
+        once, so f = exp(-alpha min(|d|, T)) exactly in float32)."""
+        tied = fbar is None
+        L.bp_set_potential(self.handle, M, T, float(alpha), L.BP_FBAR_TIED if tied else float(fbar))
+        self.T, self.alpha = T, float(alpha)
+        self.fbar = math.exp(-alpha * T) if tied else float(fbar)
+        self.fbar_tied = tied
+        if M != self.M:
+            self.M = M
+            nbytes = L.bp_workspace_bytes(self.handle)
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws.data_ptr()) % 256
+            self._sync_stream()
+            L.bp_attach_workspace(self.handle, self._ws.data_ptr() + off, nbytes)
+            self._g = None
+
+    def set_unary(self, g):
+        assert g.is_cuda and g.dtype == torch.float32 and g.is_contiguous()
+        assert tuple(g.shape) == (self.H, self.W, self.M), (tuple(g.shape), (self.H, self.W, self.M))
+        self._g = g
+        L.bp_set_unary(self.handle, g)
+
+    def reset(self):
+        self._sync_stream()
+        L.bp_reset_messages(self.handle)
+
+    def iterate(self, mode="sum", n_iters=1, schedule="sync", dense=False):
+        self._sync_stream()
+        fn = L.bp_iterate_dense if dense else L.bp_iterate
+        fn(self.handle, _as_code(mode, MODES), n_iters, _as_code(schedule, SCHEDULES))
+
+    def beliefs(self, out=None):
+        if out is None:
+            out = torch.empty((self.H, self.W, self.M), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        L.bp_beliefs(self.handle, out)
+        return out
+
+    def map_labels(self, out=None):
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        L.bp_map_labels(self.handle, out)
+        return out
+
+    def get_messages(self, out=None):
+        if out is None:
+            out = torch.empty((4, self.H, self.W, self.M), dtype=torch.float32, device=self.device)
+        self._sync_stream()
+        L.bp_get_messages(self.handle, out)
+        return out
+
+    def set_messages(self, src):
+        assert src.is_cuda and src.dtype == torch.float32 and src.is_contiguous()
+        assert tuple(src.shape) == (4, self.H, self.W, self.M)
+        self._sync_stream()
+        L.bp_set_messages(self.handle, src)
+
+    def close(self):
+        if self.handle:
+            L.bp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,73 @@
+"""Helpers for the GPU parity tests: run the HIP path through the C ABI and
+the FP64 oracle on the same seeded inputs, and compare them."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import grid_bp as gb
+
+BELIEF_TOL = 1e-5      # max |b_gpu - b_oracle| after normalisation
+MAP_MARGIN = 1e-6      # MAP must match where the oracle's top-2 margin exceeds this
+MSG_TOL = 1e-5         # live message entries
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, dense=False,
+            init=None, want_messages=True):
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H, W, _ = g32.shape
+    grid = Grid(H, W)
+    grid.set_potential(M, T, alpha, fbar)
+    g = torch.from_numpy(np.ascontiguousarray(g32)).cuda()
+    grid.set_unary(g)
+    if init is not None:
+        grid.set_messages(torch.from_numpy(np.ascontiguousarray(init, dtype=np.float32)).cuda())
+    grid.iterate(mode, n_iters, schedule, dense=dense)
+    b = grid.beliefs().cpu().numpy()
+    lab = grid.map_labels().cpu().numpy()
+    msgs = grid.get_messages().cpu().numpy() if want_messages else None
+    torch.cuda.synchronize()
+    grid.close()
+    return msgs, b, lab
+
+
+def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, impl=gb.SPARSE,
+               init=None):
+    pot = gb.truncated_linear(M, T, alpha, fbar)
+    g = g32.astype(np.float64)
+    state = gb.run(g, pot, mode, n_iters, schedule, impl,
+                   inbox=None if init is None else init.astype(np.float64))
+    b = gb.beliefs(g, state)
+    return state, b, gb.map_labels(b)
+
+
+def compare(tag, gpu, ref, belief_tol=BELIEF_TOL, msg_tol=MSG_TOL, check_msgs=True):
+    """Assert the GPU result (msgs, beliefs, labels) matches the oracle's."""
+    msgs, b, lab = gpu
+    state, b_ref, lab_ref = ref
+    H, W, M = b_ref.shape
+    err_b = float(np.max(np.abs(b - b_ref)))
+    sure = gb.top2_margin(b_ref) > MAP_MARGIN
+    bad = (lab != lab_ref) & sure
+    line = f"{tag}: max|db|={err_b:.2e} MAP mismatches={int(bad.sum())}/{int(sure.sum())}"
+    if check_msgs and msgs is not None:
+        has = gb.has_neighbor(H, W)
+        err_m = float(np.max(np.abs(msgs - state)[has])) if has.any() else 0.0
+        line += f" max|dm|={err_m:.2e}"
+        assert err_m <= msg_tol, line
+    say(line)
+    assert err_b <= belief_tol, line
+    if bad.any():
+        idx = np.argwhere(bad)[:5]
+        detail = [(tuple(i), int(lab[tuple(i)]), int(lab_ref[tuple(i)]),
+                   float(gb.top2_margin(b_ref)[tuple(i)])) for i in idx]
+        raise AssertionError(f"{line}; first mismatches (pixel, gpu, oracle, margin): {detail}")
+    # labels are the argmax of the returned float32 beliefs (lowest index on ties)
+    np.testing.assert_array_equal(lab, np.argmax(b, axis=-1))

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar: beliefs within 1e-5 (max abs, after normalisation) and live messages
+within 1e-5; MAP labels equal wherever the oracle's top-two belief margin
+exceeds 1e-6; max-product sparse and dense GPU kernels bit-identical; sum-product
+sparse and dense within 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from bp_gpu_util import compare, run_gpu, run_oracle, say
+from oracle import grid_bp as gb
+from synth_mrf import CONFIGS, make_config, random_unary
+
+pytestmark = pytest.mark.gpu
+
+# (H, W, M, T, alpha, fbar): every labels-per-lane class (M <= 16, 32, 64,
+# 128, 256), full and partial label rows, each register-window width and the
+# runtime-window fallback, T = 0, fbar = 0, chains, a single pixel, and a
+# multi-workgroup grid with a ragged tail and odd width.
+SHAPES = [
+    (5, 7, 5, 1, 0.8, None),
+    (1, 9, 3, 1, 1.0, None),
+    (9, 1, 4, 2, 0.5, None),
+    (1, 1, 6, 2, 1.0, None),
+    (2, 2, 1, 0, 1.0, None),
+    (6, 5, 16, 0, 1.0, 0.2),
+    (7, 9, 16, 15, 0.3, None),
+    (4, 6, 16, 9, 0.4, None),
+    (5, 6, 32, 3, 0.7, None),
+    (3, 11, 20, 5, 0.6, None),
+    (6, 7, 64, 4, 0.5, None),
+    (5, 5, 48, 7, 0.5, None),
+    (4, 5, 64, 20, 0.2, None),
+    (3, 4, 100, 6, 0.4, None),
+    (3, 4, 128, 8, 0.3, None),
+    (3, 3, 128, 30, 0.1, None),
+    (2, 3, 200, 10, 0.3, None),
+    (2, 3, 256, 16, 0.2, None),
+    (2, 2, 256, 100, 0.05, None),
+    (5, 6, 16, 2, 1.0, 0.0),
+    (4, 5, 16, 2, -0.1, 0.5),
+    (33, 17, 16, 2, 1.0, None),
+]
+
+
+def _id(s):
+    return "H{}W{}M{}T{}a{}f{}".format(*s)
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("shape", SHAPES, ids=_id)
+def test_sparse_shapes(shape, mode, schedule):
+    H, W, M, T, alpha, fbar = shape
+    seed = SHAPES.index(shape)
+    g32 = random_unary(H, W, M, seed)
+    n = 5 if schedule == "sync" else 6
+    tag = f"sparse {mode} {schedule} {_id(shape)}"
+    say(tag)
+    gpu = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n)
+    ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n, gb.SPARSE)
+    compare(tag, gpu, ref)
+
+
+DENSE_SHAPES = [s for s in SHAPES if s[2] <= 128]
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("shape", DENSE_SHAPES, ids=_id)
+def test_dense_kernel(shape, mode, schedule):
+    """The O(M^2) comparison kernel against the oracle's dense form, and
+    against the sparse kernel (bitwise for max-product)."""
+    H, W, M, T, alpha, fbar = shape
+    g32 = random_unary(H, W, M, 77)
+    n = 5 if schedule == "sync" else 6
+    tag = f"dense {mode} {schedule} {_id(shape)}"
+    say(tag)
+    gd = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, dense=True)
+    compare(tag, gd, run_oracle(g32, M, T, alpha, fbar, mode, schedule, n, gb.DENSE))
+    gs = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n)
+    if mode == "max":
+        np.testing.assert_array_equal(gd[0], gs[0])
+        np.testing.assert_array_equal(gd[1], gs[1])
+    else:
+        assert np.max(np.abs(gd[0] - gs[0])) <= 1e-6
+        assert np.max(np.abs(gd[1] - gs[1])) <= 1e-6
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_stereo16_full(mode, schedule):
+    cfg = CONFIGS["stereo16"]
+    g32, _ = make_config(cfg)
+    n = cfg.iters if schedule == "sync" else 2 * cfg.iters
+    tag = f"stereo16 {mode} {schedule} x{n}"
+    say(tag)
+    gpu = run_gpu(g32, cfg.M, cfg.T, cfg.alpha, None, mode, schedule, n)
+    for impl in (gb.SPARSE, gb.DENSE):
+        compare(tag + f" vs oracle-{impl}", gpu,
+                run_oracle(g32, cfg.M, cfg.T, cfg.alpha, None, mode, schedule, n, impl))
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_checkerboard_interleaves_sync_bitwise(mode):
+    """After n passes, messages sent by colour (n-1) mod 2 equal the sync state
+    m^n and the rest m^(n-1), bit for bit (same kernel arithmetic)."""
+    H, W, M, T = 13, 10, 16, 2
+    g32 = random_unary(H, W, M, 5)
+    n = 5
+    sync_n = run_gpu(g32, M, T, 0.9, None, mode, "sync", n)[0]
+    sync_n1 = run_gpu(g32, M, T, 0.9, None, mode, "sync", n - 1)[0]
+    cb = run_gpu(g32, M, T, 0.9, None, mode, "checkerboard", n)[0]
+    has = gb.has_neighbor(H, W)
+    for k in gb.DIRS:
+        dr, dc = gb.OFFSETS[k]
+        r, c = np.mgrid[0:H, 0:W]
+        sender_colour = (r + dr + c + dc) % 2
+        newer = has[k] & (sender_colour == (n - 1) % 2)
+        older = has[k] & (sender_colour != (n - 1) % 2)
+        np.testing.assert_array_equal(cb[k][newer], sync_n[k][newer])
+        np.testing.assert_array_equal(cb[k][older], sync_n1[k][older])
+
+
+def test_deterministic():
+    g32 = random_unary(31, 29, 64, 9)
+    a = run_gpu(g32, 64, 4, 0.5, None, "sum", "sync", 7)
+    b = run_gpu(g32, 64, 4, 0.5, None, "sum", "sync", 7)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_zero_iterations_and_isolated_pixel():
+    g32 = random_unary(3, 4, 8, 1)
+    _, b, _ = run_gpu(g32, 8, 2, 1.0, None, "sum", "sync", 0)
+    np.testing.assert_allclose(b, g32 / g32.sum(-1, keepdims=True), atol=1e-7)
+    g1 = random_unary(1, 1, 8, 2)
+    _, b1, _ = run_gpu(g1, 8, 2, 1.0, None, "max", "checkerboard", 3)
+    np.testing.assert_allclose(b1, g1 / g1.sum(-1, keepdims=True), atol=1e-7)
+
+
+def test_warm_start_messages():
+    """set_messages followed by iterate equals the oracle started from the
+    same (float32) state."""
+    H, W, M, T = 6, 8, 16, 2
+    g32 = random_unary(H, W, M, 3)
+    pot = gb.truncated_linear(M, T, 0.7)
+    init = gb.run(g32.astype(np.float64), pot, gb.SUM, 3).astype(np.float32)
+    gpu = run_gpu(g32, M, T, 0.7, None, "sum", "sync", 4, init=init)
+    ref = run_oracle(g32, M, T, 0.7, None, "sum", "sync", 4, init=init)
+    compare("warm start", gpu, ref)
+
+
+def test_api_errors():
+    import torch
+    from paper_1010_0012_amd import _lib as L
+    h = L.bp_init_grid(4, 4)
+    with pytest.raises(L.BPError) as e:
+        L.bp_iterate(h, 0, 1, 0)
+    assert e.value.status == L.BP_ESTATE
+    with pytest.raises(L.BPError) as e:
+        L.bp_set_potential(h, 8, 8, 1.0, 0.1)          # T must be < M
+    assert e.value.status == L.BP_EINVAL
+    with pytest.raises(L.BPError) as e:
+        L.bp_set_potential(h, 8, 2, 1.0, -0.1)
+    assert e.value.status == L.BP_EINVAL
+    L.bp_set_potential(h, 8, 2, 1.0, 0.9)              # fbar above f(2): sum only
+    nbytes = L.bp_workspace_bytes(h)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.BPError) as e:
+        L.bp_attach_workspace(h, ws, nbytes - 1)
+    assert e.value.status == L.BP_ENOMEM
+    L.bp_attach_workspace(h, ws, nbytes)
+    with pytest.raises(L.BPError) as e:
+        L.bp_iterate(h, 0, 1, 0)                       # no unary yet
+    assert e.value.status == L.BP_ESTATE
+    g = torch.rand(4, 4, 8, device="cuda") + 0.1
+    L.bp_set_unary(h, g)
+    L.bp_iterate(h, L.BP_SUM_PRODUCT, 2, L.BP_SCHED_SYNC)
+    with pytest.raises(L.BPError) as e:
+        L.bp_iterate(h, L.BP_MAX_PRODUCT, 2, L.BP_SCHED_SYNC)
+    assert e.value.status == L.BP_EUNSUPPORTED
+    with pytest.raises(L.BPError) as e:
+        L.bp_iterate(h, 7, 1, 0)
+    assert e.value.status == L.BP_EINVAL
+    L.bp_set_potential(h, 200, 2, 1.0, math.exp(-2.0))
+    with pytest.raises(L.BPError) as e:                # M changed: workspace dropped
+        L.bp_iterate(h, 0, 1, 0)
+    assert e.value.status == L.BP_ESTATE
+    torch.cuda.synchronize()
+    L.bp_destroy(h)
+
+
+# ----------------------------------------------------- full-size workloads ----
+
+def _sampled_one_step(cfg, g32, mode, schedule, n, n_samples=160, seed=0):
+    """Full-size check in the benchmark's launch configuration: run n-1
+    iterations, take the state, run one more; every sampled message of the
+    last step must equal the oracle's single update from the GPU's previous
+    state, and sampled beliefs the oracle's Eq. 3 on the final state."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M = g32.shape
+    grid = Grid(H, W)
+    grid.set_potential(M, cfg.T, cfg.alpha)
+    g = torch.from_numpy(g32).cuda()
+    grid.set_unary(g)
+    grid.iterate(mode, n - 1, schedule)
+    prev = grid.get_messages().cpu().numpy().astype(np.float64)
+    grid.iterate(mode, 1, schedule)
+    last = grid.get_messages().cpu().numpy()
+    b = grid.beliefs().cpu().numpy()
+    lab = grid.map_labels().cpu().numpy()
+    torch.cuda.synchronize()
+    grid.close()
+    pot = gb.truncated_linear(M, cfg.T, cfg.alpha)
+    g64 = g32.astype(np.float64)
+    rng = np.random.default_rng(seed)
+    colour = (n - 1) % 2
+    worst_m = 0.0
+    checked = 0
+    while checked < n_samples:
+        r, c, o = int(rng.integers(0, H)), int(rng.integers(0, W)), int(rng.integers(0, 4))
+        dr, dc = gb.OFFSETS[o]
+        if not (0 <= r + dr < H and 0 <= c + dc < W):
+            continue
+        if schedule == "checkerboard" and (r + c) % 2 != colour:
+            continue
+        ref = gb.single_update(g64, prev, pot, mode, r, c, o)
+        got = last[gb.OPPOSITE[o], r + dr, c + dc]
+        worst_m = max(worst_m, float(np.max(np.abs(got - ref))))
+        checked += 1
+    worst_b = 0.0
+    for _ in range(n_samples):
+        r, c = int(rng.integers(0, H)), int(rng.integers(0, W))
+        worst_b = max(worst_b, float(np.max(np.abs(b[r, c] - gb.single_belief(g64, last.astype(np.float64), r, c)))))
+    has = gb.has_neighbor(H, W)
+    sums = last.sum(axis=-1)[has]
+    say(f"{cfg.name} {mode} {schedule} x{n}: one-step max|dm|={worst_m:.2e} "
+        f"belief max|db|={worst_b:.2e} |sum m - 1|<={np.max(np.abs(sums - 1)):.2e} "
+        f"min m={last[has].min():.3e} (fbar/M={pot.fbar / M:.3e})")
+    assert worst_m <= 1e-6
+    assert worst_b <= 1e-6
+    assert np.max(np.abs(sums - 1.0)) <= 1e-5
+    assert last[has].min() >= pot.fbar / M * (1 - 1e-5)
+    np.testing.assert_array_equal(lab, np.argmax(b, axis=-1))
+    return last
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_stereo480x640_sampled(mode, schedule):
+    cfg = CONFIGS["stereo480x640"]
+    g32, _ = make_config(cfg)
+    n = cfg.iters if schedule == "sync" else 2 * cfg.iters
+    say(f"stereo480x640 {mode} {schedule} x{n}")
+    _sampled_one_step(cfg, g32, mode, schedule, n)
+
+
+def test_stereo480x640_max_dense_equals_sparse():
+    cfg = CONFIGS["stereo480x640"]
+    g32, _ = make_config(cfg)
+    say("stereo480x640 max dense vs sparse x20")
+    a = run_gpu(g32, cfg.M, cfg.T, cfg.alpha, None, "max", "sync", 20)
+    b = run_gpu(g32, cfg.M, cfg.T, cfg.alpha, None, "max", "sync", 20, dense=True)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+def test_stereo288x384_sum_full(schedule):
+    cfg = CONFIGS["stereo288x384"]
+    g32, _ = make_config(cfg)
+    n = cfg.iters if schedule == "sync" else 2 * cfg.iters
+    tag = f"stereo288x384 sum {schedule} x{n}"
+    say(tag)
+    gpu = run_gpu(g32, cfg.M, cfg.T, cfg.alpha, None, "sum", schedule, n)
+    ref = run_oracle(g32, cfg.M, cfg.T, cfg.alpha, None, "sum", schedule, n, gb.DENSE)
+    compare(tag, gpu, ref)
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+def test_stereo288x384_max_sampled(schedule):
+    cfg = CONFIGS["stereo288x384"]
+    g32, _ = make_config(cfg)
+    n = cfg.iters if schedule == "sync" else 2 * cfg.iters
+    say(f"stereo288x384 max {schedule} x{n}")
+    _sampled_one_step(cfg, g32, "max", schedule, n)
