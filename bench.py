@@ -11,7 +11,7 @@ comparison kernel, the dominant kernel's roofline (algorithmic bytes per
 launch / HIP-event-timed average launch duration, against 8 TB/s), and the
 FP64 oracle timed on a bounded sample on the host CPU.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-legs]
 """
 from __future__ import annotations
 
@@ -38,6 +38,26 @@ def alg_bytes_per_sync_iter(cfg):
     """Each live message entry read once and written once, unary read once:
     4 * M * (2E + N) bytes per synchronous iteration."""
     return 4 * cfg.M * (2 * cfg.n_directed_edges + cfg.n_pixels)
+
+
+KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
+                  "paper_1010_0012_amd/csrc/bp_launch_sparse.hip"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update_stereo480x640.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (each scaled by the same counter on a plain
+    256 MiB copy), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(PMC_SUMMARY))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes"] if rec.get("source_sha256") == h.hexdigest() else None
 
 
 def time_launches(grid, mode, n, schedule, dense, reps):
@@ -86,7 +106,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--legs", action="store_true", help="also time max/checkerboard/dense legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the max/checkerboard/dense legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this library has no multi-GPU path "
@@ -138,14 +158,14 @@ def main():
     bytes_launch = alg_bytes_per_sync_iter(cfg)
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                 "kernel": "sparse_update_kernel<LPL=4,K=1,sum>",
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3}
     log(f"bench: sparse sum launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
     extra = {"sparse_sum_sync_launch_us": ms_launch * 1e3}
-    if args.legs:
+    if not args.no_legs:
         for mode, sched, dense in (("max", "sync", False), ("sum", "checkerboard", False),
                                    ("max", "checkerboard", False), ("sum", "sync", True),
                                    ("max", "sync", True)):
