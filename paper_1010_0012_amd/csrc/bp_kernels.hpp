@@ -63,24 +63,42 @@ __device__ __forceinline__ void sparse_message(const float (&h)[LPL], const Upda
     }
 }
 
-// Grid-wide update, register window.  One 16-lane row per sending pixel.
-template <int LPL, int K, int MODE>
+// Grid-wide update, register window.  One 16-lane row per sending pixel;
+// each row handles P pixels, loading all of them before computing so that
+// P times the bytes are in flight per wave.  Within a wave the four rows take
+// consecutive pixels for each j, so every load and store stays contiguous.
+template <int LPL, int K, int MODE, int P>
 __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
+    constexpr int RPB = kBlock / kRow;  // rows per block
     const int lane = threadIdx.x & (kRow - 1);
-    const int slot = (blockIdx.x * kBlock + threadIdx.x) / kRow;
-    const Pixel px = map_slot(slot, a);
-    if (!px.ok) return;  // whole rows only: DPP never reads a retired lane
+    const int base = blockIdx.x * RPB * P + threadIdx.x / kRow;
     const int x0 = lane * LPL;
     const bool full = a.M == kRow * LPL;
-    PixelInputs<LPL> in;
-    load_pixel<LPL>(a, px, x0, full, in);
-    float h[4][LPL];
-    make_h<LPL>(in, h);
+    Pixel px[P];
+    PixelInputs<LPL> in[P];
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        float u[LPL];
-        sparse_message<LPL, K, MODE>(h[o], a, u);
-        normalise_store<LPL>(a, px, o, x0, full, u);
+    for (int j = 0; j < P; ++j) {
+        px[j] = map_slot(base + j * RPB, a);
+        if (px[j].ok) {
+            load_pixel<LPL>(a, px[j], x0, full, in[j]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < LPL; ++i) {
+                in[j].g[i] = 1.0f;
+                in[j].m[0][i] = in[j].m[1][i] = in[j].m[2][i] = in[j].m[3][i] = 1.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        float h[4][LPL];
+        make_h<LPL>(in[j], h);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float u[LPL];
+            sparse_message<LPL, K, MODE>(h[o], a, u);
+            normalise_store<LPL>(a, px[j], o, x0, full, u);
+        }
     }
 }
 
@@ -245,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void readout_kernel(UpdateArgs a, float* be
         b[i] *= inv;
         if (x0 + i < a.M && b[i] > best) { best = b[i]; arg = x0 + i; }
     }
-    if (beliefs) store_labels<LPL>(beliefs + (size_t)px.p * a.M, x0, a.M, full, b);
+    if (beliefs) store_labels<LPL, false>(beliefs + (size_t)px.p * a.M, x0, a.M, full, b);
     if (labels) {
         // (value, index) tournament across the row: larger value wins, the
         // lower index breaks ties; the result is the same on every lane.

@@ -25,10 +25,15 @@ inline unsigned blocks_for(int n_slots) {
     return (unsigned)((n_slots + (kBlock / kRow) - 1) / (kBlock / kRow));
 }
 
+#ifndef BP_PIX_PER_ROW
+#define BP_PIX_PER_ROW 1
+#endif
+
 template <int LPL, int K, int MODE>
 hipError_t go(const UpdateArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((sparse_update_kernel<LPL, K, MODE>), dim3(blocks_for(a.n_slots)),
-                       dim3(kBlock), 0, s, a);
+    constexpr int P = LPL <= 4 ? BP_PIX_PER_ROW : 1;
+    const unsigned blocks = (unsigned)((a.n_slots + (kBlock / kRow) * P - 1) / ((kBlock / kRow) * P));
+    hipLaunchKernelGGL((sparse_update_kernel<LPL, K, MODE, P>), dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
