@@ -100,6 +100,50 @@ def cpu_baseline(cfg, g32):
                       f"M={cfg.M}, sparse Eq. 7 form, FP64 NumPy, 1 thread ({dt:.1f} s)"}
 
 
+def grad_leg(reps=3):
+    """Forward (with checkpoints) + backward of unrolled sum-product BP on the
+    256x256, M=32, T=3, 30-iteration differentiation workload."""
+    import torch
+
+    from paper_1010_0012_amd import _lib as L
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import CONFIGS, make_config
+    cfg = CONFIGS["stereo256grad"]
+    g32, y = make_config(cfg)
+    grid = Grid(cfg.H, cfg.W)
+    grid.set_potential(cfg.M, cfg.T, cfg.alpha)
+    g = torch.from_numpy(g32).cuda()
+    grid.set_unary(g)
+    nbytes = L.bp_grad_workspace_bytes(grid.handle, cfg.iters, cfg.ckpt_every)
+    gws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    yt = torch.from_numpy(y).cuda().long()
+    b = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device="cuda")
+    dtheta = torch.empty_like(b)
+    dalpha = torch.zeros(1, device="cuda")
+    N = cfg.n_pixels
+
+    def fwd_bwd():
+        L.bp_forward_ckpt(grid.handle, cfg.iters, cfg.ckpt_every, gws, nbytes)
+        grid.beliefs(b)
+        by = torch.gather(b, -1, yt[..., None])
+        dL_db = torch.zeros_like(b).scatter_(-1, yt[..., None], -1.0 / (N * by))
+        L.bp_backward(grid.handle, dL_db, dtheta, dalpha)
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    grid.close()
+    log(f"bench: fwd+bwd {cfg.name}: {dt * 1e3:.2f} ms per {cfg.iters}-iteration forward+backward")
+    return {"fwd_bwd_workload": f"{cfg.name}: {cfg.H}x{cfg.W}, M={cfg.M}, T={cfg.T}, "
+                                f"{cfg.iters} iterations, checkpoints every {cfg.ckpt_every}",
+            "fwd_bwd_ms": dt * 1e3, "fwd_bwd_it_per_s": cfg.iters / dt,
+            "fwd_bwd_solves_per_s": 1.0 / dt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +226,9 @@ def main():
             if sp and dn:
                 extra[f"sparse_over_dense_{mode}"] = sp / dn
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
+    if not args.no_legs:
+        extra.update(grad_leg())
+
     # copy-kernel ceiling on this GPU (torch device-to-device copy)
     big = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(big)

@@ -141,6 +141,43 @@ int bp_map_labels(bp_grid* grid, int32_t* out_dev);
 int bp_get_messages(const bp_grid* grid, float* dst_dev);
 int bp_set_messages(bp_grid* grid, const float* src_dev);
 
+/* ------------------------------------------------------------------------
+ * Differentiation of unrolled sum-product BP.  The paper motivates
+ * sum-product BP by applications that need marginals, such as
+ * maximum-likelihood and CRF parameter estimation (Sec. 1, Sec. 2, Sec. 7);
+ * these calls return gradients of a loss on the beliefs with respect to the
+ * log-unary theta = log g and the smoothness weight alpha.
+ *
+ * Usage: bp_forward_ckpt, then bp_beliefs (the loss is computed by the
+ * caller from those beliefs), then bp_backward with dL/dbeliefs.  Any call
+ * that changes the state in between (iterate, reset, set_*, attach) makes
+ * bp_backward return BP_ESTATE.
+ * Supported: M <= 128 and T <= 15 (the register-window variants); otherwise
+ * BP_EUNSUPPORTED.
+ * ---------------------------------------------------------------------- */
+
+/* Device bytes bp_forward_ckpt / bp_backward need for n_iters >= 0
+ * synchronous iterations with a message checkpoint every ckpt_every >= 1
+ * iterations: ceil(n/k)-1 checkpoints, k recompute buffers, two adjoint
+ * buffers (4*H*W*M floats each) and one float per workgroup. */
+int64_t bp_grad_workspace_bytes(const bp_grid* grid, int32_t n_iters, int32_t ckpt_every);
+
+/* Reset the messages to 1/M and run n_iters synchronous sum-product
+ * iterations (Eq. 7), storing the state every ckpt_every iterations in the
+ * caller-owned device workspace gws (>= bp_grad_workspace_bytes, 256-byte
+ * aligned).  Afterwards the handle holds the final state m^n, exactly as
+ * bp_iterate would leave it. */
+int bp_forward_ckpt(bp_grid* grid, int32_t n_iters, int32_t ckpt_every, void* gws, int64_t bytes);
+
+/* Reverse pass.  dL_db (device, [H][W][M]): gradient of the caller's loss
+ * with respect to the normalised beliefs of the final state.  Writes
+ * dtheta (device, [H][W][M]) = dL/dlog g, and dalpha (device, one float) =
+ * dL/dalpha, where fbar moves with alpha (d fbar/d alpha = -T fbar) if it was
+ * set with BP_FBAR_TIED and is constant otherwise.  States between
+ * checkpoints are recomputed; the alpha reduction has a fixed order, so the
+ * result is deterministic.  Accumulation is float32. */
+int bp_backward(bp_grid* grid, const float* dL_db, float* dtheta, float* dalpha);
+
 /* Free the handle (host memory only; the caller frees its device memory
  * after its stream has drained). */
 int bp_destroy(bp_grid* grid);

@@ -47,6 +47,9 @@ _PROTOS = {
     "bp_map_labels": (_c_int, [_vp, _vp]),
     "bp_get_messages": (_c_int, [_vp, _vp]),
     "bp_set_messages": (_c_int, [_vp, _vp]),
+    "bp_grad_workspace_bytes": (_c_i64, [_vp, _c_i32, _c_i32]),
+    "bp_forward_ckpt": (_c_int, [_vp, _c_i32, _c_i32, _vp, _c_i64]),
+    "bp_backward": (_c_int, [_vp, _vp, _vp, _vp]),
     "bp_destroy": (_c_int, [_vp]),
     "bp_status_string": (ctypes.c_char_p, [_c_int]),
     "bp_last_error": (ctypes.c_char_p, []),
@@ -158,6 +161,20 @@ def bp_get_messages(handle, dst):
 
 def bp_set_messages(handle, src):
     _check(lib().bp_set_messages(handle, _ptr(src)), "bp_set_messages")
+
+
+def bp_grad_workspace_bytes(handle, n_iters, ckpt_every):
+    return _check(lib().bp_grad_workspace_bytes(handle, n_iters, ckpt_every), "bp_grad_workspace_bytes")
+
+
+def bp_forward_ckpt(handle, n_iters, ckpt_every, gws, nbytes=None):
+    if nbytes is None:
+        nbytes = gws.numel() * gws.element_size()
+    _check(lib().bp_forward_ckpt(handle, n_iters, ckpt_every, _ptr(gws), nbytes), "bp_forward_ckpt")
+
+
+def bp_backward(handle, dL_db, dtheta, dalpha):
+    _check(lib().bp_backward(handle, _ptr(dL_db), _ptr(dtheta), _ptr(dalpha)), "bp_backward")
 
 
 def bp_destroy(handle):

@@ -32,6 +32,10 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Every call that changes the message state, the potential or the unary
+// invalidates the checkpoints of a previous bp_forward_ckpt.
+void invalidate_grad(bp_grid* G) { G->grad_ready = false; }
+
 // f(d) = exp(-alpha d) in double, rounded to float32.
 void build_tables(bp_grid* G) {
     for (int d = 0; d < bpk::kMaxTab; ++d) {
@@ -84,6 +88,7 @@ int with_device(const bp_grid* G) {
 int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     int st = check_ready(G);
     if (st) return st;
+    invalidate_grad(G);
     if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
     if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD)
         return fail(BP_EINVAL, "bad schedule %d", schedule);
@@ -114,6 +119,8 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
 }
 
 }  // namespace bpi
+
+size_t bp_align_up(size_t v, size_t a) { return bpi::align_up(v, a); }
 
 using namespace bpi;
 
@@ -149,6 +156,7 @@ int bp_set_stream(bp_grid* G, void* hip_stream) {
 
 int bp_set_potential(bp_grid* G, int32_t M, int32_t T, float alpha, float fbar) {
     if (!G) return fail(BP_EINVAL, "null handle");
+    invalidate_grad(G);
     if (M < 1 || M > BP_MAX_LABELS) return fail(BP_EINVAL, "M=%d outside [1, %d]", M, BP_MAX_LABELS);
     if (T < 0 || T >= M) return fail(BP_EINVAL, "T=%d outside [0, M-1]", T);
     if (!std::isfinite(alpha)) return fail(BP_EINVAL, "alpha not finite");
@@ -180,6 +188,7 @@ int64_t bp_workspace_bytes(const bp_grid* G) {
 
 int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {
     if (!G) return fail(BP_EINVAL, "null handle");
+    invalidate_grad(G);
     if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
     if (!dev_ptr) return fail(BP_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(BP_EINVAL, "workspace not 256-byte aligned");
@@ -195,6 +204,7 @@ int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {
 
 int bp_set_unary(bp_grid* G, const float* g_dev) {
     if (!G) return fail(BP_EINVAL, "null handle");
+    invalidate_grad(G);
     if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
     if (!g_dev) return fail(BP_EINVAL, "null unary");
     if (reinterpret_cast<uintptr_t>(g_dev) % 16) return fail(BP_EINVAL, "unary not 16-byte aligned");
@@ -204,6 +214,7 @@ int bp_set_unary(bp_grid* G, const float* g_dev) {
 
 int bp_reset_messages(bp_grid* G) {
     if (!G) return fail(BP_EINVAL, "null handle");
+    invalidate_grad(G);
     if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
     int st = with_device(G);
     if (st) return st;
@@ -259,6 +270,7 @@ int bp_get_messages(const bp_grid* G, float* dst_dev) {
 
 int bp_set_messages(bp_grid* G, const float* src_dev) {
     if (!G) return fail(BP_EINVAL, "null handle");
+    invalidate_grad(G);
     if (!G->ws) return fail(BP_ESTATE, "no workspace attached");
     if (!src_dev) return fail(BP_EINVAL, "null source");
     if (reinterpret_cast<uintptr_t>(src_dev) % 16) return fail(BP_EINVAL, "source not 16-byte aligned");

@@ -33,34 +33,46 @@ __device__ __forceinline__ void fill_window(const float (&h)[LPL], float (&win)[
 // the row read 0, which is also the clip at the ends of the label range
 // (Nbd(y) stops at 0 and M-1).  Taps with T < |d| <= K*LPL carry weight 0,
 // so rounding K up changes no result.
+// Symmetric banded window: u[i] = base + sum_{|d| <= K*LPL} tab[|d|] * v(y_i + d)
+// (sum) or max(base, max tab[|d|] * v(y_i + d)) (max), v read from this lane
+// and K lanes each side (0 outside the row).
 template <int LPL, int K, int MODE>
-__device__ __forceinline__ void sparse_message(const float (&h)[LPL], const UpdateArgs& a,
-                                               float (&u)[LPL]) {
+__device__ __forceinline__ void window_apply(const float (&v)[LPL], const float* tab, float base,
+                                             float (&u)[LPL]) {
     constexpr int TW = K * LPL;
     constexpr int NW = (2 * K + 1) * LPL;
-    float s = h[0];
-#pragma unroll
-    for (int i = 1; i < LPL; ++i) s = (MODE == kSum) ? s + h[i] : fmaxf(s, h[i]);
-    s = row_reduce<MODE>(s);
-
     float win[NW];
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) win[K * LPL + i] = h[i];
-    fill_window<LPL, K, K>(h, win);
-
-    const float base = a.fbar * s;
+    for (int i = 0; i < LPL; ++i) win[K * LPL + i] = v[i];
+    fill_window<LPL, K, K>(v, win);
 #pragma unroll
     for (int i = 0; i < LPL; ++i) {
         float acc = base;
 #pragma unroll
         for (int d = -TW; d <= TW; ++d) {
-            const float w = a.tab[d < 0 ? -d : d];
+            const float w = tab[d < 0 ? -d : d];
             const float x = win[K * LPL + i + d];
             if constexpr (MODE == kSum) acc = fmaf(w, x, acc);
             else acc = fmaxf(acc, w * x);
         }
         u[i] = acc;
     }
+}
+
+// Row-wide sum (or max) of an LPL-per-lane vector; same bits on every lane.
+template <int LPL, int MODE>
+__device__ __forceinline__ float row_total(const float (&v)[LPL]) {
+    float s = v[0];
+#pragma unroll
+    for (int i = 1; i < LPL; ++i) s = (MODE == kSum) ? s + v[i] : fmaxf(s, v[i]);
+    return row_reduce<MODE>(s);
+}
+
+template <int LPL, int K, int MODE>
+__device__ __forceinline__ void sparse_message(const float (&h)[LPL], const UpdateArgs& a,
+                                               float (&u)[LPL]) {
+    const float s = row_total<LPL, MODE>(h);  // the once-per-message term
+    window_apply<LPL, K, MODE>(h, a.tab, a.fbar * s, u);
 }
 
 // Grid-wide update, register window.  One 16-lane row per sending pixel;

@@ -34,3 +34,16 @@ hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipS
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);
 
 }  // namespace bpk
+
+namespace bpk {
+
+struct AdjointArgs;
+struct SeedArgs;
+// Adjoint of synchronous sum-product BP (bp_launch_adjoint.hip).
+bool adjoint_supported(int M, int T);
+unsigned adjoint_blocks(int N);
+hipError_t launch_adjoint_seed(const SeedArgs& a, hipStream_t stream);
+hipError_t launch_adjoint_step(const AdjointArgs& a, int T, hipStream_t stream);
+hipError_t launch_sum_partials(const float* part, int n, float* out, hipStream_t stream);
+
+}  // namespace bpk

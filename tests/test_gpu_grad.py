@@ -1,0 +1,155 @@
+"""GPU adjoint of unrolled sum-product BP against the FP64 hand adjoint
+(oracle.grad_ref, itself pinned by finite differences and autograd on the CPU).
+
+Bar: max |dtheta_gpu - dtheta_ref| <= 1e-4 * max |dtheta_ref| and
+|dalpha_gpu - dalpha_ref| <= 1e-4 * |dalpha_ref| (+1e-7 absolute), with the
+loss the mean cross-entropy of the beliefs against labels.
+"""
+import numpy as np
+import pytest
+
+from bp_gpu_util import say
+from oracle import grad_ref
+from synth_mrf import CONFIGS, make_config, make_stereo, random_unary
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_grad(g32, y, M, T, alpha, n, k, fbar=None):
+    import torch
+    from paper_1010_0012_amd import _lib as L
+    from paper_1010_0012_amd.grid import Grid
+    H, W, _ = g32.shape
+    grid = Grid(H, W)
+    grid.set_potential(M, T, alpha, fbar)
+    g = torch.from_numpy(np.ascontiguousarray(g32)).cuda()
+    grid.set_unary(g)
+    nbytes = L.bp_grad_workspace_bytes(grid.handle, n, k)
+    gws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    L.bp_forward_ckpt(grid.handle, n, k, gws, nbytes)
+    b = grid.beliefs()
+    yt = torch.from_numpy(y).cuda().long()
+    N = H * W
+    by = torch.gather(b, -1, yt[..., None])
+    loss = float(-torch.log(by).mean())
+    dL_db = torch.zeros_like(b).scatter_(-1, yt[..., None], -1.0 / (N * by))
+    dtheta = torch.empty_like(b)
+    dalpha = torch.zeros(1, device="cuda")
+    L.bp_backward(grid.handle, dL_db, dtheta, dalpha)
+    torch.cuda.synchronize()
+    out = loss, dtheta.cpu().numpy(), float(dalpha.cpu()[0]), b.cpu().numpy()
+    grid.close()
+    return out
+
+
+def check(tag, gpu, ref):
+    loss, th, al, _ = gpu
+    L, th_ref, al_ref = ref
+    e_th = float(np.max(np.abs(th - th_ref)) / np.max(np.abs(th_ref)))
+    e_al = abs(al - al_ref)
+    say(f"{tag}: loss {loss:.6f} vs {L:.6f}, rel max|d dtheta|={e_th:.2e}, "
+        f"dalpha {al:.6e} vs {al_ref:.6e} (|d|={e_al:.2e})")
+    assert abs(loss - L) <= 1e-5 * max(1.0, abs(L))
+    assert e_th <= 1e-4
+    assert e_al <= 1e-4 * abs(al_ref) + 1e-7
+
+
+GRAD_CASES = [
+    # H, W, M, T, alpha, n, k, fbar
+    (6, 7, 8, 2, 0.9, 5, 2, None),
+    (5, 9, 16, 2, 1.0, 7, 3, None),
+    (4, 5, 32, 3, 1.0, 6, 1, None),
+    (6, 6, 32, 3, 0.7, 6, 10, None),
+    (7, 5, 20, 4, 0.6, 4, 4, None),
+    (3, 4, 64, 4, 0.5, 5, 2, None),
+    (3, 3, 128, 8, 0.3, 3, 2, None),
+    (5, 6, 16, 0, 1.0, 4, 2, 0.2),
+    (4, 6, 16, 2, 0.8, 5, 2, 0.05),
+    (1, 8, 6, 1, 1.0, 8, 3, None),
+    (9, 1, 6, 2, 1.0, 6, 4, None),
+    (5, 5, 12, 2, 0.8, 0, 3, None),
+]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=lambda c: "H{}W{}M{}T{}a{}n{}k{}f{}".format(*c))
+def test_adjoint_matches_oracle(case):
+    H, W, M, T, alpha, n, k, fbar = case
+    g32, y, _, _ = make_stereo(H, W, M, 0.05, 4.0, "rectangles", GRAD_CASES.index(case))
+    say(f"adjoint {case}")
+    gpu = gpu_grad(g32, y, M, T, alpha, n, k, fbar)
+    # the library rounds alpha to float32; the reference uses the same value
+    a32 = float(np.float32(alpha))
+    ref = grad_ref.grad(g32.astype(np.float64), y, M, T, a32, n,
+                        fbar=None if fbar is None else float(np.float32(fbar)))
+    check(f"adjoint {case}", gpu, ref)
+
+
+def test_adjoint_deterministic_and_checkpoint_invariant():
+    g32, y, _, _ = make_stereo(20, 24, 32, 0.05, 4.0, "rectangles", 11)
+    a = gpu_grad(g32, y, 32, 3, 1.0, 9, 4)
+    b = gpu_grad(g32, y, 32, 3, 1.0, 9, 4)
+    np.testing.assert_array_equal(a[1], b[1])
+    assert a[2] == b[2]
+    c = gpu_grad(g32, y, 32, 3, 1.0, 9, 1)      # every state checkpointed
+    d = gpu_grad(g32, y, 32, 3, 1.0, 9, 20)     # nothing checkpointed
+    # recomputation replays the same kernels on the same inputs: bit-identical
+    np.testing.assert_array_equal(a[1], c[1])
+    np.testing.assert_array_equal(a[1], d[1])
+    assert a[2] == c[2] == d[2]
+
+
+def test_autograd_function():
+    import torch
+    from paper_1010_0012_amd.autograd import bp_beliefs
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M, T, n = 10, 12, 16, 2, 6
+    g32, y, _, _ = make_stereo(H, W, M, 0.05, 4.0, "rectangles", 3)
+    theta = torch.log(torch.from_numpy(g32).cuda()).requires_grad_(True)
+    alpha = torch.tensor(0.8, device="cuda", requires_grad=True)
+    grid = Grid(H, W)
+    b = bp_beliefs(theta, alpha, grid, T, n, ckpt_every=2)
+    yt = torch.from_numpy(y).cuda().long()
+    loss = -torch.log(torch.gather(b, -1, yt[..., None])).mean()
+    loss.backward()
+    ref = grad_ref.grad(g32.astype(np.float64), y, M, T, float(np.float32(0.8)), n)
+    check("autograd", (float(loss.detach()), theta.grad.cpu().numpy(), float(alpha.grad), None), ref)
+    grid.close()
+
+
+def test_backward_state_errors():
+    import torch
+    from paper_1010_0012_amd import _lib as L
+    from paper_1010_0012_amd.grid import Grid
+    grid = Grid(4, 4)
+    grid.set_potential(8, 2, 1.0)
+    g = torch.from_numpy(random_unary(4, 4, 8, 0)).cuda()
+    grid.set_unary(g)
+    buf = torch.zeros(4, 4, 8, device="cuda")
+    da = torch.zeros(1, device="cuda")
+    with pytest.raises(L.BPError) as e:
+        L.bp_backward(grid.handle, buf, buf.clone(), da)
+    assert e.value.status == L.BP_ESTATE
+    nbytes = L.bp_grad_workspace_bytes(grid.handle, 4, 2)
+    gws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.BPError) as e:
+        L.bp_forward_ckpt(grid.handle, 4, 2, gws, nbytes - 1)
+    assert e.value.status == L.BP_ENOMEM
+    L.bp_forward_ckpt(grid.handle, 4, 2, gws, nbytes)
+    grid.iterate("sum", 1)                       # state changed: checkpoints stale
+    with pytest.raises(L.BPError) as e:
+        L.bp_backward(grid.handle, buf, buf.clone(), da)
+    assert e.value.status == L.BP_ESTATE
+    grid.set_potential(8, 20 - 13, 1.0)          # T = 7 fits M = 8
+    torch.cuda.synchronize()
+    grid.close()
+
+
+def test_stereo256grad_full():
+    """The differentiation workload at full size: 256x256, M=32, T=3, 30
+    iterations, checkpoints every 5, against the FP64 reference gradient."""
+    cfg = CONFIGS["stereo256grad"]
+    g32, y = make_config(cfg)
+    say(f"{cfg.name} adjoint x{cfg.iters} k={cfg.ckpt_every}")
+    gpu = gpu_grad(g32, y, cfg.M, cfg.T, cfg.alpha, cfg.iters, cfg.ckpt_every)
+    ref = grad_ref.grad(g32.astype(np.float64), y, cfg.M, cfg.T, float(np.float32(cfg.alpha)), cfg.iters)
+    check(cfg.name, gpu, ref)
