@@ -182,6 +182,71 @@ int bp_backward(bp_grid* grid, const float* dL_db, float* dtheta, float* dalpha)
  * after its stream has drained). */
 int bp_destroy(bp_grid* grid);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent grid MRFs, each with its own H, W, M, T, alpha,
+ * fbar and unary (the Sec. 6 stereo model on images of different sizes and
+ * disparity ranges), advanced together by the same synchronous O(mM) update
+ * (Eq. 7 / Eq. 11).  Each iteration is one persistent kernel launch that
+ * walks a precomputed work queue of (instance, pixel range) items, longest
+ * first; the n launches of bp_batch_iterate are captured once into a HIP
+ * graph (per mode, n and buffer parity) on a private stream of default
+ * priority and replayed on the batch's stream.
+ * Per instance: H, W >= 1; 1 <= M <= 128; 0 <= T <= 8; T < M (else
+ * BP_EUNSUPPORTED for M or T out of range, BP_EINVAL for bad values).
+ * Outputs are concatenated in instance order: instance j's beliefs start at
+ * float offset sum_{i<j} H_i*W_i*M_i, its labels at sum_{i<j} H_i*W_i.
+ * ---------------------------------------------------------------------- */
+typedef struct bp_grid_desc {
+    int32_t H, W, M, T;
+    float alpha;
+    float fbar;            /* >= 0, or BP_FBAR_TIED */
+    const float* unary;    /* device [H][W][M], 16-byte aligned, borrowed */
+} bp_grid_desc;
+
+/* Copy n >= 1 descriptors into a new batch handle on the current device. */
+int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hip_stream);
+int bp_batch_set_stream(bp_batch* batch, void* hip_stream);
+
+/* Device bytes for the descriptor table, the work queue and every
+ * instance's two message buffers. */
+int64_t bp_batch_workspace_bytes(const bp_batch* batch);
+
+/* Attach caller-owned workspace (256-byte aligned), upload descriptors and
+ * the work queue, and reset all messages to 1/M.  Blocks until the upload
+ * has completed. */
+int bp_batch_attach_workspace(bp_batch* batch, void* dev_ptr, int64_t bytes);
+
+int bp_batch_reset_messages(bp_batch* batch);
+
+/* n_iters synchronous iterations of every instance (mode: BP_SUM_PRODUCT or
+ * BP_MAX_PRODUCT; max-product requires f >= fbar for each instance, as for
+ * bp_iterate). */
+int bp_batch_iterate(bp_batch* batch, int32_t mode, int32_t n_iters);
+
+/* enable = 0: launch the kernels directly on every call instead of
+ * replaying captured graphs (results are identical). */
+int bp_batch_set_graphs(bp_batch* batch, int32_t enable);
+
+/* Work plan: passes[c] = 16-pixel passes per work item for instances of
+ * labels-per-lane class c (M <= 16, 32, 64, 128), grid_blocks = persistent
+ * workgroups per launch (>= 1).  Rebuilds and uploads the work queue
+ * (blocking), keeps the messages, drops captured graphs. */
+int bp_batch_set_plan(bp_batch* batch, const int32_t passes[4], int32_t grid_blocks);
+int bp_batch_get_plan(const bp_batch* batch, int32_t passes[4], int32_t* grid_blocks);
+
+/* Time a fixed family of candidate plans (item sizes x grid sizes) for
+ * trial_iters >= 1 iterations each on this batch and keep the fastest.
+ * Blocks; resets the messages afterwards.  best_us (optional, host) receives
+ * the best time per iteration in microseconds. */
+int bp_batch_autotune(bp_batch* batch, int32_t mode, int32_t trial_iters, float* best_us);
+
+/* Beliefs (Eq. 3) / MAP labels of every instance (device, concatenated). */
+int bp_batch_beliefs(bp_batch* batch, float* out_dev);
+int bp_batch_map_labels(bp_batch* batch, int32_t* out_dev);
+
+/* Free the handle and its captured graphs and private stream. */
+int bp_batch_destroy(bp_batch* batch);
+
 const char* bp_status_string(int status);
 const char* bp_last_error(void);
 

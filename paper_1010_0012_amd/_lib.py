@@ -25,6 +25,13 @@ BP_FBAR_TIED = -1.0
 _c_int, _c_i32, _c_i64, _c_f, _vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
 
 
+class bp_grid_desc(ctypes.Structure):
+    """struct bp_grid_desc (include/bp.h)."""
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("alpha", ctypes.c_float), ("fbar", ctypes.c_float),
+                ("unary", ctypes.c_void_p)]
+
+
 class BPError(RuntimeError):
     def __init__(self, status, func, msg):
         super().__init__(f"{func} -> {status}: {msg}")
@@ -51,6 +58,19 @@ _PROTOS = {
     "bp_forward_ckpt": (_c_int, [_vp, _c_i32, _c_i32, _vp, _c_i64]),
     "bp_backward": (_c_int, [_vp, _vp, _vp, _vp]),
     "bp_destroy": (_c_int, [_vp]),
+    "bp_batch_init": (_c_int, [ctypes.POINTER(_vp), _c_i32, ctypes.POINTER(bp_grid_desc), _vp]),
+    "bp_batch_set_stream": (_c_int, [_vp, _vp]),
+    "bp_batch_workspace_bytes": (_c_i64, [_vp]),
+    "bp_batch_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
+    "bp_batch_reset_messages": (_c_int, [_vp]),
+    "bp_batch_iterate": (_c_int, [_vp, _c_i32, _c_i32]),
+    "bp_batch_set_graphs": (_c_int, [_vp, _c_i32]),
+    "bp_batch_set_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), _c_i32]),
+    "bp_batch_get_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "bp_batch_autotune": (_c_int, [_vp, _c_i32, _c_i32, ctypes.POINTER(_c_f)]),
+    "bp_batch_beliefs": (_c_int, [_vp, _vp]),
+    "bp_batch_map_labels": (_c_int, [_vp, _vp]),
+    "bp_batch_destroy": (_c_int, [_vp]),
     "bp_status_string": (ctypes.c_char_p, [_c_int]),
     "bp_last_error": (ctypes.c_char_p, []),
 }
@@ -187,3 +207,69 @@ def bp_status_string(status):
 
 def bp_last_error():
     return lib().bp_last_error().decode()
+
+
+# ---------------------------------------------------------------- batch ----
+
+def bp_batch_init(descs, stream=None):
+    """descs: sequence of bp_grid_desc (unary = device address)."""
+    arr = (bp_grid_desc * len(descs))(*descs)
+    h = _vp()
+    _check(lib().bp_batch_init(ctypes.byref(h), len(descs), arr, _stream(stream)), "bp_batch_init")
+    return h.value
+
+
+def bp_batch_set_stream(handle, stream=None):
+    _check(lib().bp_batch_set_stream(handle, _stream(stream)), "bp_batch_set_stream")
+
+
+def bp_batch_workspace_bytes(handle):
+    return _check(lib().bp_batch_workspace_bytes(handle), "bp_batch_workspace_bytes")
+
+
+def bp_batch_attach_workspace(handle, ws, nbytes=None):
+    if nbytes is None:
+        nbytes = ws.numel() * ws.element_size()
+    _check(lib().bp_batch_attach_workspace(handle, _ptr(ws), nbytes), "bp_batch_attach_workspace")
+
+
+def bp_batch_reset_messages(handle):
+    _check(lib().bp_batch_reset_messages(handle), "bp_batch_reset_messages")
+
+
+def bp_batch_iterate(handle, mode, n_iters):
+    _check(lib().bp_batch_iterate(handle, mode, n_iters), "bp_batch_iterate")
+
+
+def bp_batch_set_graphs(handle, enable):
+    _check(lib().bp_batch_set_graphs(handle, int(bool(enable))), "bp_batch_set_graphs")
+
+
+def bp_batch_set_plan(handle, passes, grid_blocks):
+    arr = (_c_i32 * 4)(*passes)
+    _check(lib().bp_batch_set_plan(handle, arr, grid_blocks), "bp_batch_set_plan")
+
+
+def bp_batch_get_plan(handle):
+    arr = (_c_i32 * 4)()
+    g = _c_i32()
+    _check(lib().bp_batch_get_plan(handle, arr, ctypes.byref(g)), "bp_batch_get_plan")
+    return list(arr), g.value
+
+
+def bp_batch_autotune(handle, mode, trial_iters):
+    best = _c_f()
+    _check(lib().bp_batch_autotune(handle, mode, trial_iters, ctypes.byref(best)), "bp_batch_autotune")
+    return best.value
+
+
+def bp_batch_beliefs(handle, out):
+    _check(lib().bp_batch_beliefs(handle, _ptr(out)), "bp_batch_beliefs")
+
+
+def bp_batch_map_labels(handle, out):
+    _check(lib().bp_batch_map_labels(handle, _ptr(out)), "bp_batch_map_labels")
+
+
+def bp_batch_destroy(handle):
+    _check(lib().bp_batch_destroy(handle), "bp_batch_destroy")

@@ -22,6 +22,9 @@ ARCH = "gfx950"
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # every fused multiply-add in the kernels is an explicit fmaf: no implicit
+    # contraction, so two kernels running the same source round the same way
+    "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),

@@ -47,19 +47,6 @@ struct SeedArgs {
     int H, W, M, N;
 };
 
-__device__ __forceinline__ Pixel sync_pixel(int slot, int H, int W, int N) {
-    Pixel px;
-    px.r = slot / W;
-    px.c = slot - px.r * W;
-    px.ok = slot < N;
-    px.p = px.r * W + px.c;
-    px.has[kLeft] = px.c > 0;
-    px.has[kRight] = px.c + 1 < W;
-    px.has[kUp] = px.r > 0;
-    px.has[kDown] = px.r + 1 < H;
-    return px;
-}
-
 template <int LPL>
 __device__ __forceinline__ void load_pixel_at(const float* g, const float* m, int N, int M,
                                               const Pixel& px, int x0, bool full,

@@ -1,0 +1,412 @@
+// Host driver of the batched path: instance descriptors, work queue
+// planning, persistent launches, HIP graph capture and the plan autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/bp.h"
+#include "bp_batch.hpp"
+#include "bp_internal.hpp"
+#include "bp_launch.hpp"
+
+using namespace bpi;
+
+struct bp_batch {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    int n = 0;
+    std::vector<bp_grid_desc> desc;
+    std::vector<int> arm;
+    std::vector<float> fbar;
+    // plan
+    int passes[4] = {4, 2, 1, 1};
+    int grid_blocks = 0;
+    // device memory
+    char* ws = nullptr;
+    int64_t ws_bytes = 0;
+    size_t desc_off = 0, item_off = 0, msg_off = 0, total = 0;
+    size_t max_items = 0;
+    std::vector<size_t> msg_bytes_off;        // per instance, first of its two buffers
+    std::vector<bpk::InstDesc> hdesc;
+    std::vector<bpk::Item> hitems;
+    int parity = 0;
+    bool use_graphs = true;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (mode, n, parity)
+
+    size_t msg_floats(int j) const { return (size_t)4 * desc[j].H * desc[j].W * desc[j].M; }
+};
+
+namespace {
+
+int lpl_class(int M) {
+    const int l = bpk::pick_lpl(M);
+    return l == 1 ? 0 : l == 2 ? 1 : l == 4 ? 2 : 3;
+}
+
+// Smallest compiled code path whose window reaches T (see kArmLpl/kArmK).
+int pick_arm(int M, int T) {
+    const int lpl = bpk::pick_lpl(M);
+    const int k = std::max(1, bpk::window_lanes(T, lpl));
+    for (int a = 0; a < bpk::kBatchArms; ++a)
+        if (bpk::kArmLpl[a] == lpl && bpk::kArmK[a] >= k) return a;
+    return -1;
+}
+
+void drop_graphs(bp_batch* B) {
+    for (auto& kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+    B->graphs.clear();
+}
+
+// Work queue: every instance cut into items of 16*passes pixels, sorted by
+// bytes moved (passes * 16 * M), longest first, ties by instance then pixel.
+void build_items(bp_batch* B) {
+    B->hitems.clear();
+    for (int j = 0; j < B->n; ++j) {
+        const int N = B->desc[j].H * B->desc[j].W;
+        const int P = B->passes[lpl_class(B->desc[j].M)];
+        const int chunk = 16 * P;
+        for (int first = 0; first < N; first += chunk) {
+            const int left = N - first;
+            bpk::Item it;
+            it.inst = j;
+            it.first = first;
+            it.passes = std::min(P, (left + 15) / 16);
+            it.pad = 0;
+            B->hitems.push_back(it);
+        }
+    }
+    std::stable_sort(B->hitems.begin(), B->hitems.end(), [&](const bpk::Item& a, const bpk::Item& b) {
+        const long long ca = (long long)a.passes * B->desc[a.inst].M;
+        const long long cb = (long long)b.passes * B->desc[b.inst].M;
+        return ca > cb;
+    });
+}
+
+int upload(bp_batch* B) {
+    hipError_t e = hipMemcpyAsync(B->ws + B->item_off, B->hitems.data(), B->hitems.size() * sizeof(bpk::Item),
+                                  hipMemcpyHostToDevice, B->stream);
+    if (e != hipSuccess) return hip_fail(e, "work queue upload");
+    e = hipMemcpyAsync(B->ws + B->desc_off, B->hdesc.data(), B->hdesc.size() * sizeof(bpk::InstDesc),
+                       hipMemcpyHostToDevice, B->stream);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    // the host vectors are the copy sources: wait before they may change
+    e = hipStreamSynchronize(B->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "upload synchronize");
+}
+
+hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s) {
+    const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
+    const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
+    const int n_items = (int)B->hitems.size();
+    const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, n_items));
+    for (int t = 0; t < n; ++t) {
+        const int par = (parity0 + t) & 1;
+        if (mode == bpk::kSum)
+            hipLaunchKernelGGL(bpk::batch_update_kernel<bpk::kSum>, dim3(grid), dim3(bpk::kBlock), 0, s,
+                               inst, items, n_items, par);
+        else
+            hipLaunchKernelGGL(bpk::batch_update_kernel<bpk::kMax>, dim3(grid), dim3(bpk::kBlock), 0, s,
+                               inst, items, n_items, par);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int ready(const bp_batch* B) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    if (!B->ws) return fail(BP_ESTATE, "no workspace attached to the batch");
+    return BP_OK;
+}
+
+int set_device(const bp_batch* B) {
+    hipError_t e = hipSetDevice(B->dev);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "hipSetDevice");
+}
+
+}  // namespace
+
+extern "C" {
+
+int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hip_stream) {
+    if (!out) return fail(BP_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (n < 1 || !descs) return fail(BP_EINVAL, "need n >= 1 descriptors");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    std::vector<int> arms(n);
+    std::vector<float> fbars(n);
+    for (int j = 0; j < n; ++j) {
+        const bp_grid_desc& d = descs[j];
+        if (d.H < 1 || d.W < 1 || (int64_t)d.H * d.W >= (int64_t(1) << 29))
+            return fail(BP_EINVAL, "instance %d: bad grid %d x %d", j, d.H, d.W);
+        if (d.M < 1 || d.T < 0 || d.T >= d.M) return fail(BP_EINVAL, "instance %d: need 1 <= M and 0 <= T < M", j);
+        if (d.M > 128 || d.T > 8) return fail(BP_EUNSUPPORTED, "instance %d: batches support M <= 128, T <= 8", j);
+        if (!std::isfinite(d.alpha)) return fail(BP_EINVAL, "instance %d: alpha not finite", j);
+        float fb = d.fbar;
+        if (fb == BP_FBAR_TIED) fb = (float)std::exp(-(double)d.alpha * d.T);
+        if (!std::isfinite(fb) || fb < 0.0f) return fail(BP_EINVAL, "instance %d: bad fbar", j);
+        if (!d.unary || reinterpret_cast<uintptr_t>(d.unary) % 16)
+            return fail(BP_EINVAL, "instance %d: unary null or not 16-byte aligned", j);
+        arms[j] = pick_arm(d.M, d.T);
+        if (arms[j] < 0) return fail(BP_EUNSUPPORTED, "instance %d: no compiled window for M=%d T=%d", j, d.M, d.T);
+        fbars[j] = fb;
+    }
+    bp_batch* B = new (std::nothrow) bp_batch();
+    if (!B) return fail(BP_ENOMEM, "host allocation failed");
+    B->dev = dev;
+    B->stream = static_cast<hipStream_t>(hip_stream);
+    B->n = n;
+    B->desc.assign(descs, descs + n);
+    B->arm = arms;
+    B->fbar = fbars;
+    B->grid_blocks = std::max(1, cus) * 8;
+    // layout: descriptors, work queue (sized for one pass per item), messages
+    for (int j = 0; j < n; ++j) B->max_items += (size_t)(descs[j].H * descs[j].W + 15) / 16;
+    B->desc_off = 0;
+    B->item_off = bp_align_up(n * sizeof(bpk::InstDesc), 256);
+    B->msg_off = B->item_off + bp_align_up(B->max_items * sizeof(bpk::Item), 256);
+    size_t off = B->msg_off;
+    for (int j = 0; j < n; ++j) {
+        B->msg_bytes_off.push_back(off);
+        off += 2 * bp_align_up(B->msg_floats(j) * sizeof(float), 256);
+    }
+    B->total = off;
+    *out = B;
+    return BP_OK;
+}
+
+int bp_batch_set_stream(bp_batch* B, void* hip_stream) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    B->stream = static_cast<hipStream_t>(hip_stream);
+    return BP_OK;
+}
+
+int64_t bp_batch_workspace_bytes(const bp_batch* B) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    return (int64_t)B->total;
+}
+
+int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    if (!dev_ptr) return fail(BP_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(BP_EINVAL, "workspace not 256-byte aligned");
+    if (bytes < (int64_t)B->total)
+        return fail(BP_ENOMEM, "workspace %lld bytes < %zu needed", (long long)bytes, B->total);
+    int st = set_device(B);
+    if (st) return st;
+    drop_graphs(B);
+    B->ws = static_cast<char*>(dev_ptr);
+    B->ws_bytes = bytes;
+    B->hdesc.assign(B->n, bpk::InstDesc{});
+    long long boff = 0, loff = 0;
+    for (int j = 0; j < B->n; ++j) {
+        const bp_grid_desc& d = B->desc[j];
+        bpk::InstDesc& h = B->hdesc[j];
+        memset(&h, 0, sizeof h);
+        h.g = d.unary;
+        const size_t buf = bp_align_up(B->msg_floats(j) * sizeof(float), 256);
+        h.msg[0] = reinterpret_cast<float*>(B->ws + B->msg_bytes_off[j]);
+        h.msg[1] = reinterpret_cast<float*>(B->ws + B->msg_bytes_off[j] + buf);
+        h.belief_off = boff;
+        h.label_off = loff;
+        h.H = d.H; h.W = d.W; h.M = d.M; h.N = d.H * d.W; h.T = d.T;
+        h.arm = B->arm[j];
+        h.fbar = B->fbar[j];
+        for (int k = 0; k < bpk::kBatchTab; ++k) {
+            const bool in = k <= d.T;
+            const double f = std::exp(-(double)d.alpha * k);
+            h.tab_f[k] = in ? (float)f : 0.0f;
+            h.tab_w[k] = in ? (float)(f - (double)h.fbar) : 0.0f;
+        }
+        boff += (long long)h.N * d.M;
+        loff += h.N;
+    }
+    build_items(B);
+    if ((st = upload(B))) return st;
+    return bp_batch_reset_messages(B);
+}
+
+int bp_batch_reset_messages(bp_batch* B) {
+    int st = ready(B);
+    if (st) return st;
+    if ((st = set_device(B))) return st;
+    for (int j = 0; j < B->n; ++j)
+        for (int b = 0; b < 2; ++b) {
+            hipError_t e = bpk::launch_fill(B->hdesc[j].msg[b], B->msg_floats(j), 1.0f / (float)B->desc[j].M, B->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch message reset");
+        }
+    B->parity = 0;
+    return BP_OK;
+}
+
+int bp_batch_iterate(bp_batch* B, int32_t mode, int32_t n_iters) {
+    int st = ready(B);
+    if (st) return st;
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (n_iters < 0) return fail(BP_EINVAL, "n_iters < 0");
+    if (mode == BP_MAX_PRODUCT)
+        for (int j = 0; j < B->n; ++j)
+            for (int d = 0; d <= B->desc[j].T; ++d)
+                if (!(B->hdesc[j].tab_f[d] >= B->hdesc[j].fbar))
+                    return fail(BP_EUNSUPPORTED, "instance %d: max-product needs f >= fbar (Eq. 11)", j);
+    if (n_iters == 0) return BP_OK;
+    if ((st = set_device(B))) return st;
+    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+    hipError_t e;
+    if (!B->use_graphs) {
+        e = launch_iters(B, kmode, n_iters, B->parity, B->stream);
+        if (e != hipSuccess) return hip_fail(e, "batch update launch");
+    } else {
+        const auto key = std::make_tuple(kmode, (int)n_iters, B->parity);
+        auto it = B->graphs.find(key);
+        if (it == B->graphs.end()) {
+            if (!B->cap_stream) {
+                // default priority, like every stream this library touches
+                e = hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_fail(e, "capture stream");
+            }
+            e = hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = launch_iters(B, kmode, n_iters, B->parity, B->cap_stream);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(B->cap_stream, &graph);
+            if (le != hipSuccess) return hip_fail(le, "batch update capture");
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            it = B->graphs.emplace(key, exec).first;
+        }
+        e = hipGraphLaunch(it->second, B->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    B->parity ^= (n_iters & 1);
+    return BP_OK;
+}
+
+int bp_batch_set_graphs(bp_batch* B, int32_t enable) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    B->use_graphs = enable != 0;
+    return BP_OK;
+}
+
+int bp_batch_set_plan(bp_batch* B, const int32_t passes[4], int32_t grid_blocks) {
+    int st = ready(B);
+    if (st) return st;
+    if (!passes || grid_blocks < 1) return fail(BP_EINVAL, "bad plan");
+    for (int c = 0; c < 4; ++c)
+        if (passes[c] < 1 || passes[c] > 4096) return fail(BP_EINVAL, "passes[%d] out of range", c);
+    if ((st = set_device(B))) return st;
+    // the previous queue may still be read by queued launches
+    hipError_t e = hipStreamSynchronize(B->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    drop_graphs(B);
+    for (int c = 0; c < 4; ++c) B->passes[c] = passes[c];
+    B->grid_blocks = grid_blocks;
+    build_items(B);
+    return upload(B);
+}
+
+int bp_batch_get_plan(const bp_batch* B, int32_t passes[4], int32_t* grid_blocks) {
+    if (!B || !passes || !grid_blocks) return fail(BP_EINVAL, "null argument");
+    for (int c = 0; c < 4; ++c) passes[c] = B->passes[c];
+    *grid_blocks = B->grid_blocks;
+    return BP_OK;
+}
+
+int bp_batch_autotune(bp_batch* B, int32_t mode, int32_t trial_iters, float* best_us) {
+    int st = ready(B);
+    if (st) return st;
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (trial_iters < 1) return fail(BP_EINVAL, "trial_iters must be >= 1");
+    if ((st = set_device(B))) return st;
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, B->dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
+    // Candidates: item sizes that move about the same bytes per item across
+    // the labels-per-lane classes (scaled 1x/2x/4x/8x), times persistent grid
+    // sizes of 2..16 workgroups per CU.
+    const int base[4] = {4, 2, 1, 1};
+    float best = 1e30f;
+    int best_passes[4] = {4, 2, 1, 1}, best_grid = std::max(1, cus) * 8;
+    for (int scale : {1, 2, 4, 8}) {
+        for (int per_cu : {2, 4, 8, 16}) {
+            int32_t pl[4];
+            for (int c = 0; c < 4; ++c) pl[c] = base[c] * scale;
+            if ((st = bp_batch_set_plan(B, pl, std::max(1, cus) * per_cu))) break;
+            e = launch_iters(B, kmode, 1, B->parity, B->stream);  // warm
+            if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
+            if (e == hipSuccess) e = launch_iters(B, kmode, trial_iters, B->parity ^ 1, B->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, B->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = hip_fail(e, "autotune trial"); break; }
+            B->parity ^= (trial_iters + 1) & 1;
+            const float us = ms * 1000.0f / trial_iters;
+            if (us < best) {
+                best = us;
+                for (int c = 0; c < 4; ++c) best_passes[c] = pl[c];
+                best_grid = std::max(1, cus) * per_cu;
+            }
+        }
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    if ((st = bp_batch_set_plan(B, best_passes, best_grid))) return st;
+    if (best_us) *best_us = best;
+    return bp_batch_reset_messages(B);
+}
+
+static int batch_readout(bp_batch* B, float* beliefs, int32_t* labels) {
+    int st = ready(B);
+    if (st) return st;
+    if ((st = set_device(B))) return st;
+    const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
+    const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
+    const int n_items = (int)B->hitems.size();
+    const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, n_items));
+    hipLaunchKernelGGL(bpk::batch_readout_kernel, dim3(grid), dim3(bpk::kBlock), 0, B->stream, inst, items,
+                       n_items, B->parity, beliefs, labels);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BP_OK : hip_fail(e, "batch readout launch");
+}
+
+int bp_batch_beliefs(bp_batch* B, float* out_dev) {
+    if (!out_dev || reinterpret_cast<uintptr_t>(out_dev) % 16) return fail(BP_EINVAL, "beliefs output null or misaligned");
+    return batch_readout(B, out_dev, nullptr);
+}
+
+int bp_batch_map_labels(bp_batch* B, int32_t* out_dev) {
+    if (!out_dev) return fail(BP_EINVAL, "null labels output");
+    return batch_readout(B, nullptr, out_dev);
+}
+
+int bp_batch_destroy(bp_batch* B) {
+    if (!B) return BP_OK;
+    drop_graphs(B);
+    if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    delete B;
+    return BP_OK;
+}
+
+}  // extern "C"

@@ -201,21 +201,43 @@ struct PixelInputs {
     float m[4][LPL];
 };
 
+// Load the unary and the inbox of one pixel from explicit pointers (plane =
+// N*M floats between inbox planes); off-grid neighbours read as 1.
 template <int LPL>
-__device__ __forceinline__ void load_pixel(const UpdateArgs& a, const Pixel& px, int x0, bool full,
-                                           PixelInputs<LPL>& in) {
-    const size_t plane = (size_t)a.N * a.M;
-    const size_t off = (size_t)px.p * a.M;
-    load_labels<LPL, kUnaryNT>(a.g + off, x0, a.M, full, in.g, 0.0f);
+__device__ __forceinline__ void load_pixel_ptr(const float* g, const float* in, size_t plane, int M,
+                                               const Pixel& px, int x0, bool full,
+                                               PixelInputs<LPL>& r) {
+    const size_t off = (size_t)px.p * M;
+    load_labels<LPL, kUnaryNT>(g + off, x0, M, full, r.g, 0.0f);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (px.has[k]) {
-            load_labels<LPL, kMsgNT>(a.in + k * plane + off, x0, a.M, full, in.m[k], 1.0f);
+            load_labels<LPL, kMsgNT>(in + k * plane + off, x0, M, full, r.m[k], 1.0f);
         } else {
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) in.m[k][i] = 1.0f;
+            for (int i = 0; i < LPL; ++i) r.m[k][i] = 1.0f;
         }
     }
+}
+
+template <int LPL>
+__device__ __forceinline__ void load_pixel(const UpdateArgs& a, const Pixel& px, int x0, bool full,
+                                           PixelInputs<LPL>& in) {
+    load_pixel_ptr<LPL>(a.g, a.in, (size_t)a.N * a.M, a.M, px, x0, full, in);
+}
+
+// Synchronous slot -> pixel (row-major).
+__device__ __forceinline__ Pixel sync_pixel(int slot, int H, int W, int N) {
+    Pixel px;
+    px.r = slot / W;
+    px.c = slot - px.r * W;
+    px.ok = slot < N;
+    px.p = px.r * W + px.c;
+    px.has[kLeft] = px.c > 0;
+    px.has[kRight] = px.c + 1 < W;
+    px.has[kUp] = px.r > 0;
+    px.has[kDown] = px.r + 1 < H;
+    return px;
 }
 
 // Eq. 5 for the four outgoing messages: h_o = g * product of the inbox
@@ -239,12 +261,13 @@ __device__ __forceinline__ void make_h(const PixelInputs<LPL>& in, float (&h)[4]
 // Normalise u (Sec. 3: explicit normalisation after each update) with one
 // IEEE division per message, then store into the receiver's inbox slot.
 template <int LPL>
-__device__ __forceinline__ void normalise_store(const UpdateArgs& a, const Pixel& px, int dir,
-                                                int x0, bool full, float (&u)[LPL]) {
+__device__ __forceinline__ void normalise_store_ptr(float* out, size_t plane, int M, int W,
+                                                    const Pixel& px, int dir, int x0, bool full,
+                                                    float (&u)[LPL]) {
     float z = 0.0f;
 #pragma unroll
     for (int i = 0; i < LPL; ++i) {
-        if (!full && x0 + i >= a.M) u[i] = 0.0f;
+        if (!full && x0 + i >= M) u[i] = 0.0f;
         z += u[i];
     }
     z = row_sum(z);
@@ -252,10 +275,15 @@ __device__ __forceinline__ void normalise_store(const UpdateArgs& a, const Pixel
 #pragma unroll
     for (int i = 0; i < LPL; ++i) u[i] *= inv;
     if (px.ok && px.has[dir]) {
-        const size_t plane = (size_t)a.N * a.M;
-        const int q = neighbour(px, dir, a.W);
-        store_labels<LPL, kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, u);
+        const int q = neighbour(px, dir, W);
+        store_labels<LPL, kMsgNT>(out + opposite(dir) * plane + (size_t)q * M, x0, M, full, u);
     }
+}
+
+template <int LPL>
+__device__ __forceinline__ void normalise_store(const UpdateArgs& a, const Pixel& px, int dir,
+                                                int x0, bool full, float (&u)[LPL]) {
+    normalise_store_ptr<LPL>(a.out, (size_t)a.N * a.M, a.M, a.W, px, dir, x0, full, u);
 }
 
 }  // namespace bpk
