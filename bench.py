@@ -41,7 +41,8 @@ def alg_bytes_per_sync_iter(cfg):
 
 
 KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
-                  "paper_1010_0012_amd/csrc/bp_launch_sparse.hip"]
+                  "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp",
+                  "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update_stereo480x640.json")
 
 
@@ -55,8 +56,11 @@ def measured_traffic():
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    try:
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
     return rec["traffic_bytes"] if rec.get("source_sha256") == h.hexdigest() else None
 
 
@@ -144,6 +148,61 @@ def grad_leg(reps=3):
             "fwd_bwd_solves_per_s": 1.0 / dt}
 
 
+def batch_leg(n_iters=30, reps=3):
+    """The 32-instance batch (H, W in [64, 512], M in {16, 32, 64, 128}, T in
+    [1, 8]): autotuned plan, n_iters sum-product iterations per graph replay;
+    and the same instances run one grid at a time for comparison."""
+    import torch
+
+    from paper_1010_0012_amd.batch import Batch
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import make_batch_configs, make_batch_instance
+    insts = make_batch_configs()
+    gs = [torch.from_numpy(make_batch_instance(i)[0]).cuda() for i in insts]
+    batch = Batch([(g, i.T, i.alpha) for g, i in zip(gs, insts)])
+    best_us = batch.autotune("sum", 2)
+    plan = batch.get_plan()
+    updates = sum(2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) * i.M for i in insts) * n_iters
+    alg_bytes = sum(4 * i.M * (2 * 2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) + i.H * i.W)
+                    for i in insts) * n_iters
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    batch.reset()
+    batch.iterate("sum", n_iters)          # captures the graph
+    torch.cuda.synchronize()
+    ms = 1e30
+    for _ in range(reps):
+        batch.reset()
+        e0.record(s)
+        batch.iterate("sum", n_iters)
+        e1.record(s)
+        e1.synchronize()
+        ms = min(ms, e0.elapsed_time(e1))
+    batch.close()
+    # one grid at a time
+    t_single = 0.0
+    for g, i in zip(gs, insts):
+        grid = Grid(i.H, i.W)
+        grid.set_potential(i.M, i.T, i.alpha)
+        grid.set_unary(g)
+        grid.iterate("sum", 2)
+        e0.record(s)
+        grid.iterate("sum", n_iters)
+        e1.record(s)
+        e1.synchronize()
+        t_single += e0.elapsed_time(e1)
+        grid.close()
+    log(f"bench: batch32 x{n_iters}: {ms:.2f} ms ({updates / (ms * 1e-3):.4e} updates/s, "
+        f"{alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic), plan {plan}; one grid at a time "
+        f"{t_single:.2f} ms")
+    return {"batch_workload": f"32 grids, H,W in [64,512], M in {{16,32,64,128}}, T in [1,8], "
+                              f"{n_iters} sum-product iterations, one graph replay",
+            "batch_ms": ms, "batch_updates_per_s": updates / (ms * 1e-3),
+            "batch_alg_GBs": alg_bytes / (ms * 1e-3) / 1e9,
+            "batch_plan": {"passes": plan[0], "grid_blocks": plan[1], "autotune_best_us": best_us},
+            "batch_one_grid_at_a_time_ms": t_single}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +287,7 @@ def main():
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
     if not args.no_legs:
         extra.update(grad_leg())
+        extra.update(batch_leg())
 
     # copy-kernel ceiling on this GPU (torch device-to-device copy)
     big = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)

@@ -152,8 +152,8 @@ int bp_set_messages(bp_grid* grid, const float* src_dev);
  * caller from those beliefs), then bp_backward with dL/dbeliefs.  Any call
  * that changes the state in between (iterate, reset, set_*, attach) makes
  * bp_backward return BP_ESTATE.
- * Supported: M <= 128 and T <= 15 (the register-window variants); otherwise
- * BP_EUNSUPPORTED.
+ * Supported: T <= 16 (T <= 12 when M <= 16), the compiled register-window
+ * variants; otherwise BP_EUNSUPPORTED.
  * ---------------------------------------------------------------------- */
 
 /* Device bytes bp_forward_ckpt / bp_backward need for n_iters >= 0
@@ -191,8 +191,8 @@ int bp_destroy(bp_grid* grid);
  * first; the n launches of bp_batch_iterate are captured once into a HIP
  * graph (per mode, n and buffer parity) on a private stream of default
  * priority and replayed on the batch's stream.
- * Per instance: H, W >= 1; 1 <= M <= 128; 0 <= T <= 8; T < M (else
- * BP_EUNSUPPORTED for M or T out of range, BP_EINVAL for bad values).
+ * Per instance: H, W >= 1; 1 <= M <= BP_MAX_LABELS; 0 <= T <= 8; T < M
+ * (else BP_EUNSUPPORTED for T > 8, BP_EINVAL for bad values).
  * Outputs are concatenated in instance order: instance j's beliefs start at
  * float offset sum_{i<j} H_i*W_i*M_i, its labels at sum_{i<j} H_i*W_i.
  * ---------------------------------------------------------------------- */
@@ -227,12 +227,14 @@ int bp_batch_iterate(bp_batch* batch, int32_t mode, int32_t n_iters);
  * replaying captured graphs (results are identical). */
 int bp_batch_set_graphs(bp_batch* batch, int32_t enable);
 
-/* Work plan: passes[c] = 16-pixel passes per work item for instances of
- * labels-per-lane class c (M <= 16, 32, 64, 128), grid_blocks = persistent
- * workgroups per launch (>= 1).  Rebuilds and uploads the work queue
+/* Work plan: passes[c] = passes per work item for instances of lane class c
+ * (M <= 16, 32, 64, 128, 256; a pass covers one workgroup's worth of pixels,
+ * 256 threads over 4, 8, 16, 32 or 64 lanes per pixel), grid_blocks =
+ * persistent workgroups per launch (>= 1; more than the number of items
+ * means one item per workgroup).  Rebuilds and uploads the work queue
  * (blocking), keeps the messages, drops captured graphs. */
-int bp_batch_set_plan(bp_batch* batch, const int32_t passes[4], int32_t grid_blocks);
-int bp_batch_get_plan(const bp_batch* batch, int32_t passes[4], int32_t* grid_blocks);
+int bp_batch_set_plan(bp_batch* batch, const int32_t passes[5], int32_t grid_blocks);
+int bp_batch_get_plan(const bp_batch* batch, int32_t passes[5], int32_t* grid_blocks);
 
 /* Time a fixed family of candidate plans (item sizes x grid sizes) for
  * trial_iters >= 1 iterations each on this batch and keep the fastest.

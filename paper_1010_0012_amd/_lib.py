@@ -245,13 +245,16 @@ def bp_batch_set_graphs(handle, enable):
     _check(lib().bp_batch_set_graphs(handle, int(bool(enable))), "bp_batch_set_graphs")
 
 
+BP_BATCH_CLASSES = 5
+
+
 def bp_batch_set_plan(handle, passes, grid_blocks):
-    arr = (_c_i32 * 4)(*passes)
+    arr = (_c_i32 * BP_BATCH_CLASSES)(*passes)
     _check(lib().bp_batch_set_plan(handle, arr, grid_blocks), "bp_batch_set_plan")
 
 
 def bp_batch_get_plan(handle):
-    arr = (_c_i32 * 4)()
+    arr = (_c_i32 * BP_BATCH_CLASSES)()
     g = _c_i32()
     _check(lib().bp_batch_get_plan(handle, arr, ctypes.byref(g)), "bp_batch_get_plan")
     return list(arr), g.value

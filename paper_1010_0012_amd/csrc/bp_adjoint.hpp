@@ -34,8 +34,10 @@ struct AdjointArgs {
     int H, W, M, N;
     float fbar;
     float dfbar;            // d fbar / d alpha
-    float w[kAdjTab];       // f(d) - fbar for |d| <= T, 0 beyond
+    float w[kAdjTab];       // f(d) - fbar for |d| <= T, 0 beyond (float32, the transposed window)
     float dw[kAdjTab];      // f'(d) - fbar' for |d| <= T, 0 beyond
+    double fbar_d;          // forward recompute in double, as in the forward update
+    double wd[kAdjTab];     // f(d) - fbar in double
 };
 
 struct SeedArgs {
@@ -47,155 +49,137 @@ struct SeedArgs {
     int H, W, M, N;
 };
 
-template <int LPL>
 __device__ __forceinline__ void load_pixel_at(const float* g, const float* m, int N, int M,
-                                              const Pixel& px, int x0, bool full,
-                                              PixelInputs<LPL>& in) {
-    if (!px.ok) {
-#pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            in.g[i] = 1.0f;
-            in.m[0][i] = in.m[1][i] = in.m[2][i] = in.m[3][i] = 1.0f;
-        }
-        return;
-    }
-    const size_t plane = (size_t)N * M;
-    const size_t off = (size_t)px.p * M;
-    load_labels<LPL, true>(g + off, x0, M, full, in.g, 0.0f);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (px.has[k]) {
-            load_labels<LPL, true>(m + k * plane + off, x0, M, full, in.m[k], 1.0f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) in.m[k][i] = 1.0f;
-        }
-    }
+                                              const Pixel& px, int x0, bool full, PixelInputs& in) {
+    if (px.ok) load_pixel_ptr(g, m, (size_t)N * M, M, px, x0, full, in);
+    else dummy_pixel(in);
 }
 
 // lambda^n and the direct theta term from the loss gradient on the beliefs:
 // with b = softmax of the log-belief, dL/dlogit = b * (dL/db - sum b dL/db).
-template <int LPL>
+template <int G>
 __global__ __launch_bounds__(kBlock) void adjoint_seed_kernel(SeedArgs a) {
-    const int lane = threadIdx.x & (kRow - 1);
-    const int slot = (blockIdx.x * kBlock + threadIdx.x) / kRow;
+    const int pos = threadIdx.x & (G - 1);
+    const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
     const Pixel px = sync_pixel(slot, a.H, a.W, a.N);
     if (!px.ok) return;
-    const int x0 = lane * LPL;
-    const bool full = a.M == kRow * LPL;
-    PixelInputs<LPL> in;
-    load_pixel_at<LPL>(a.g, a.m, a.N, a.M, px, x0, full, in);
-    float b[LPL], gb[LPL];
+    const int x0 = pos * kLpl;
+    const bool full = a.M == G * kLpl;
+    PixelInputs in;
+    load_pixel_at(a.g, a.m, a.N, a.M, px, x0, full, in);
+    float b[kLpl], gb[kLpl];
+    make_belief(in, b);  // same product order and normalisation as the readout
     float z = 0.0f;
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) {
-        // same product order and normalisation as the readout kernel
-        b[i] = (((in.g[i] * in.m[kLeft][i]) * in.m[kRight][i]) * in.m[kUp][i]) * in.m[kDown][i];
-        z += b[i];
-    }
-    z = row_sum(z);
+    for (int i = 0; i < kLpl; ++i) z += b[i];
+    z = group_sum<G>(z);
     const float inv = 1.0f / z;
-    load_labels<LPL, false>(a.dL_db + (size_t)px.p * a.M, x0, a.M, full, gb, 0.0f);
+    load_labels<false>(a.dL_db + (size_t)px.p * a.M, x0, a.M, full, gb, 0.0f);
     float dot = 0.0f;
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) {
+    for (int i = 0; i < kLpl; ++i) {
         b[i] *= inv;
         dot = fmaf(b[i], gb[i], dot);
     }
-    dot = row_sum(dot);
-    float abar[LPL];
+    dot = group_sum<G>(dot);
+    float abar[kLpl];
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) abar[i] = b[i] * (gb[i] - dot);
-    store_labels<LPL, false>(a.theta_bar + (size_t)px.p * a.M, x0, a.M, full, abar);
+    for (int i = 0; i < kLpl; ++i) abar[i] = b[i] * (gb[i] - dot);
+    store_labels<false>(a.theta_bar + (size_t)px.p * a.M, x0, a.M, full, abar);
     const size_t plane = (size_t)a.N * a.M;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (px.has[k])
-            store_labels<LPL, true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, abar);
+        if (px.has[k]) store_labels<true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, abar);
 }
 
 // One reverse synchronous step (see the header comment).
-template <int LPL, int K>
+template <int G, int TW>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
-    constexpr int RPB = kBlock / kRow;
+    constexpr int RPB = kBlock / G;
     __shared__ float red[RPB];
-    const int lane = threadIdx.x & (kRow - 1);
-    const int row = threadIdx.x / kRow;
-    const int slot = blockIdx.x * RPB + row;
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int slot = blockIdx.x * RPB + grp;
     const Pixel px = sync_pixel(slot, a.H, a.W, a.N);
-    const int x0 = lane * LPL;
-    const bool full = a.M == kRow * LPL;
+    const int x0 = pos * kLpl;
+    const bool full = a.M == G * kLpl;
     const size_t plane = (size_t)a.N * a.M;
-    PixelInputs<LPL> in;
-    load_pixel_at<LPL>(a.g, a.m, a.N, a.M, px, x0, full, in);
-    float h[4][LPL];
-    make_h<LPL>(in, h);
-    float eta[4][LPL];
+    PixelInputs in;
+    load_pixel_at(a.g, a.m, a.N, a.M, px, x0, full, in);
+    float h[4][kLpl];
+    make_h(in, h);
+    float eta[4][kLpl];
     float alpha_pix = 0.0f;
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const bool live = px.ok && px.has[o];
-        float lam[LPL];
+        float lam[kLpl];
         if (live) {
             const int q = neighbour(px, o, a.W);
-            load_labels<LPL, true>(a.lam_in + opposite(o) * plane + (size_t)q * a.M, x0, a.M, full, lam, 0.0f);
+            load_labels<true>(a.lam_in + opposite(o) * plane + (size_t)q * a.M, x0, a.M, full, lam, 0.0f);
         } else {
 #pragma unroll
-            for (int i = 0; i < LPL; ++i) lam[i] = 0.0f;
+            for (int i = 0; i < kLpl; ++i) lam[i] = 0.0f;
         }
-        // forward recompute: u (Eq. 7), Z, m
-        const float S = row_total<LPL, kSum>(h[o]);
-        float u[LPL];
-        window_apply<LPL, K, kSum>(h[o], a.w, a.fbar * S, u);
+        // forward recompute: u (Eq. 7), Z, m, accumulated in double as in the
+        // forward update
+        double sd = ((double)h[o][0] + (double)h[o][1]) + ((double)h[o][2] + (double)h[o][3]);
+        sd = group_sum_d<G>(sd);
+        double ud[kLpl];
+        window_sum_d<G, TW>(h[o], a.wd, a.fbar_d * sd, pos, ud);
+        double zd = 0.0;
 #pragma unroll
-        for (int i = 0; i < LPL; ++i)
-            if (!full && x0 + i >= a.M) u[i] = 0.0f;
-        const float inv = 1.0f / row_total<LPL, kSum>(u);
-        const float sl = row_total<LPL, kSum>(lam);
-        float ub[LPL];
-#pragma unroll
-        for (int i = 0; i < LPL; ++i) {
-            const float mu = lam[i] - (u[i] * inv) * sl;
-            ub[i] = (full || x0 + i < a.M) ? mu / u[i] : 0.0f;
+        for (int i = 0; i < kLpl; ++i) {
+            if (!full && x0 + i >= a.M) ud[i] = 0.0;
+            zd += ud[i];
         }
-        const float su = row_total<LPL, kSum>(ub);
-        float hb[LPL];
-        window_apply<LPL, K, kSum>(ub, a.w, a.fbar * su, hb);
+        const double inv = 1.0 / group_sum_d<G>(zd);
+        const float S = (float)sd;
+        const float sl = group_total<G, kSum>(lam);
+        float ub[kLpl];
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) eta[o][i] = hb[i] * h[o][i];
-        float v[LPL];
-        window_apply<LPL, K, kSum>(h[o], a.dw, 0.0f, v);
+        for (int i = 0; i < kLpl; ++i) {
+            const float mu = lam[i] - (float)(ud[i] * inv) * sl;
+            ub[i] = (full || x0 + i < a.M) ? (float)((double)mu / ud[i]) : 0.0f;
+        }
+        const float su = group_total<G, kSum>(ub);
+        float hb[kLpl];
+        window_apply<G, TW, kSum>(ub, a.w, a.fbar * su, pos, hb);
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) eta[o][i] = hb[i] * h[o][i];
+        float v[kLpl];
+        window_apply<G, TW, kSum>(h[o], a.dw, 0.0f, pos, v);
         float dot = 0.0f;
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) dot = fmaf(ub[i], v[i], dot);
-        dot = row_sum(dot);
+        for (int i = 0; i < kLpl; ++i) dot = fmaf(ub[i], v[i], dot);
+        dot = group_sum<G>(dot);
         alpha_pix += fmaf(a.dfbar * S, su, dot);
     }
     if (px.ok) {
-        float tb[LPL];
+        float tb[kLpl];
         float* tp = a.theta_bar + (size_t)px.p * a.M;
-        load_labels<LPL, false>(tp, x0, a.M, full, tb, 0.0f);
+        load_labels<false>(tp, x0, a.M, full, tb, 0.0f);
 #pragma unroll
-        for (int i = 0; i < LPL; ++i)
+        for (int i = 0; i < kLpl; ++i)
             tb[i] += (eta[kLeft][i] + eta[kRight][i]) + (eta[kUp][i] + eta[kDown][i]);
-        store_labels<LPL, false>(tp, x0, a.M, full, tb);
+        store_labels<false>(tp, x0, a.M, full, tb);
         if (a.lam_out) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (!px.has[k]) continue;
-                float lo[LPL];
+                float lo[kLpl];
 #pragma unroll
-                for (int i = 0; i < LPL; ++i) {
+                for (int i = 0; i < kLpl; ++i) {
                     // every outgoing message of p except the one to k
                     const float lr = k < 2 ? eta[k ^ 1][i] : eta[kLeft][i] + eta[kRight][i];
                     const float ud = k < 2 ? eta[kUp][i] + eta[kDown][i] : eta[k ^ 1][i];
                     lo[i] = lr + ud;
                 }
-                store_labels<LPL, true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, lo);
+                store_labels<true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, lo);
             }
         }
     }
-    if (lane == 0) red[row] = px.ok ? alpha_pix : 0.0f;
+    if (pos == 0) red[grp] = px.ok ? alpha_pix : 0.0f;
     __syncthreads();
     if (threadIdx.x == 0) {
         float s = 0.0f;

@@ -36,13 +36,16 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // invalidates the checkpoints of a previous bp_forward_ckpt.
 void invalidate_grad(bp_grid* G) { G->grad_ready = false; }
 
-// f(d) = exp(-alpha d) in double, rounded to float32.
+// f(d) = exp(-alpha d) in double; float32 tables for max-product and the
+// float32 paths, the double window for sum-product.
 void build_tables(bp_grid* G) {
+    G->fbar_d = G->fbar_tied ? std::exp(-(double)G->alpha * G->T) : (double)G->fbar;
     for (int d = 0; d < bpk::kMaxTab; ++d) {
         const bool in = d <= G->T;
         const double f = std::exp(-(double)G->alpha * d);
         G->tab_f[d] = in ? (float)f : 0.0f;
         G->tab_w[d] = in ? (float)(f - (double)G->fbar) : 0.0f;
+        if (d < bpk::kDTab) G->tab_wd[d] = in ? f - G->fbar_d : 0.0;
     }
 }
 
@@ -67,6 +70,9 @@ UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int colour) 
     a.n_slots = colour < 0 ? G->N : G->H * a.half_w;
     a.T = G->T;
     a.fbar = G->fbar;
+    a.fbar_d = G->fbar_d;
+    a.alpha_d = (double)G->alpha;
+    memcpy(a.dtab, G->tab_wd, sizeof a.dtab);
     return a;
 }
 
@@ -97,6 +103,15 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         return fail(BP_EUNSUPPORTED,
                     "max-product needs f(d) >= fbar for |d| <= T (Eq. 11); fbar=%g exceeds f", G->fbar);
     if (dense && G->M > 128) return fail(BP_EUNSUPPORTED, "dense kernel supports M <= 128");
+    if (dense) {
+        int max_lds = 0;
+        hipError_t e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, G->dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        const size_t need = bpk::dense_lds_need(G->M, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax);
+        if (need > (size_t)max_lds)
+            return fail(BP_EUNSUPPORTED, "dense kernel needs %zu bytes of LDS per workgroup, device allows %d",
+                        need, max_lds);
+    }
     if ((st = with_device(G))) return st;
     const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
     // sparse sum uses w(d) = f(d) - fbar; sparse max and dense use f(d)

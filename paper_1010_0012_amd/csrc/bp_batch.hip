@@ -26,7 +26,7 @@ struct bp_batch {
     std::vector<int> arm;
     std::vector<float> fbar;
     // plan
-    int passes[4] = {4, 2, 1, 1};
+    int passes[bpk::kBatchClasses] = {1, 1, 1, 1, 1};
     int grid_blocks = 0;
     // device memory
     char* ws = nullptr;
@@ -45,17 +45,17 @@ struct bp_batch {
 
 namespace {
 
-int lpl_class(int M) {
-    const int l = bpk::pick_lpl(M);
-    return l == 1 ? 0 : l == 2 ? 1 : l == 4 ? 2 : 3;
+// Lane class 0..4 for G = 4, 8, 16, 32, 64.
+int lane_class(int M) {
+    const int g = bpk::lanes_for(M);
+    return g == 4 ? 0 : g == 8 ? 1 : g == 16 ? 2 : g == 32 ? 3 : 4;
 }
 
-// Smallest compiled code path whose window reaches T (see kArmLpl/kArmK).
+// Smallest compiled code path whose window reaches T (see kArmG/kArmTw).
 int pick_arm(int M, int T) {
-    const int lpl = bpk::pick_lpl(M);
-    const int k = std::max(1, bpk::window_lanes(T, lpl));
+    const int g = bpk::lanes_for(M);
     for (int a = 0; a < bpk::kBatchArms; ++a)
-        if (bpk::kArmLpl[a] == lpl && bpk::kArmK[a] >= k) return a;
+        if (bpk::kArmG[a] == g && bpk::kArmTw[a] >= T) return a;
     return -1;
 }
 
@@ -64,27 +64,30 @@ void drop_graphs(bp_batch* B) {
     B->graphs.clear();
 }
 
-// Work queue: every instance cut into items of 16*passes pixels, sorted by
-// bytes moved (passes * 16 * M), longest first, ties by instance then pixel.
+// Work queue: every instance cut into items of passes*kBlock/G pixels,
+// sorted by bytes moved (pixels * M), longest first, ties by instance then
+// pixel.
 void build_items(bp_batch* B) {
     B->hitems.clear();
     for (int j = 0; j < B->n; ++j) {
         const int N = B->desc[j].H * B->desc[j].W;
-        const int P = B->passes[lpl_class(B->desc[j].M)];
-        const int chunk = 16 * P;
+        const int P = B->passes[lane_class(B->desc[j].M)];
+        const int rpb = bpk::kBlock / bpk::lanes_for(B->desc[j].M);
+        const int chunk = rpb * P;
         for (int first = 0; first < N; first += chunk) {
             const int left = N - first;
             bpk::Item it;
             it.inst = j;
             it.first = first;
-            it.passes = std::min(P, (left + 15) / 16);
+            it.passes = std::min(P, (left + rpb - 1) / rpb);
             it.pad = 0;
             B->hitems.push_back(it);
         }
     }
     std::stable_sort(B->hitems.begin(), B->hitems.end(), [&](const bpk::Item& a, const bpk::Item& b) {
-        const long long ca = (long long)a.passes * B->desc[a.inst].M;
-        const long long cb = (long long)b.passes * B->desc[b.inst].M;
+        const int ga = bpk::lanes_for(B->desc[a.inst].M), gb = bpk::lanes_for(B->desc[b.inst].M);
+        const long long ca = (long long)a.passes * (bpk::kBlock / ga) * B->desc[a.inst].M;
+        const long long cb = (long long)b.passes * (bpk::kBlock / gb) * B->desc[b.inst].M;
         return ca > cb;
     });
 }
@@ -152,7 +155,8 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
         if (d.H < 1 || d.W < 1 || (int64_t)d.H * d.W >= (int64_t(1) << 29))
             return fail(BP_EINVAL, "instance %d: bad grid %d x %d", j, d.H, d.W);
         if (d.M < 1 || d.T < 0 || d.T >= d.M) return fail(BP_EINVAL, "instance %d: need 1 <= M and 0 <= T < M", j);
-        if (d.M > 128 || d.T > 8) return fail(BP_EUNSUPPORTED, "instance %d: batches support M <= 128, T <= 8", j);
+        if (d.M > BP_MAX_LABELS || d.T > 8)
+            return fail(BP_EUNSUPPORTED, "instance %d: batches support M <= %d, T <= 8", j, BP_MAX_LABELS);
         if (!std::isfinite(d.alpha)) return fail(BP_EINVAL, "instance %d: alpha not finite", j);
         float fb = d.fbar;
         if (fb == BP_FBAR_TIED) fb = (float)std::exp(-(double)d.alpha * d.T);
@@ -173,7 +177,10 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
     B->fbar = fbars;
     B->grid_blocks = std::max(1, cus) * 8;
     // layout: descriptors, work queue (sized for one pass per item), messages
-    for (int j = 0; j < n; ++j) B->max_items += (size_t)(descs[j].H * descs[j].W + 15) / 16;
+    for (int j = 0; j < n; ++j) {
+        const int rpb = bpk::kBlock / bpk::lanes_for(descs[j].M);
+        B->max_items += (size_t)(descs[j].H * descs[j].W + rpb - 1) / rpb;
+    }
     B->desc_off = 0;
     B->item_off = bp_align_up(n * sizeof(bpk::InstDesc), 256);
     B->msg_off = B->item_off + bp_align_up(B->max_items * sizeof(bpk::Item), 256);
@@ -224,11 +231,12 @@ int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
         h.H = d.H; h.W = d.W; h.M = d.M; h.N = d.H * d.W; h.T = d.T;
         h.arm = B->arm[j];
         h.fbar = B->fbar[j];
+        h.fbar_d = d.fbar == BP_FBAR_TIED ? std::exp(-(double)d.alpha * d.T) : (double)d.fbar;
         for (int k = 0; k < bpk::kBatchTab; ++k) {
             const bool in = k <= d.T;
             const double f = std::exp(-(double)d.alpha * k);
             h.tab_f[k] = in ? (float)f : 0.0f;
-            h.tab_w[k] = in ? (float)(f - (double)h.fbar) : 0.0f;
+            h.tab_wd[k] = in ? f - h.fbar_d : 0.0;
         }
         boff += (long long)h.N * d.M;
         loff += h.N;
@@ -303,26 +311,26 @@ int bp_batch_set_graphs(bp_batch* B, int32_t enable) {
     return BP_OK;
 }
 
-int bp_batch_set_plan(bp_batch* B, const int32_t passes[4], int32_t grid_blocks) {
+int bp_batch_set_plan(bp_batch* B, const int32_t passes[5], int32_t grid_blocks) {
     int st = ready(B);
     if (st) return st;
     if (!passes || grid_blocks < 1) return fail(BP_EINVAL, "bad plan");
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < bpk::kBatchClasses; ++c)
         if (passes[c] < 1 || passes[c] > 4096) return fail(BP_EINVAL, "passes[%d] out of range", c);
     if ((st = set_device(B))) return st;
     // the previous queue may still be read by queued launches
     hipError_t e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     drop_graphs(B);
-    for (int c = 0; c < 4; ++c) B->passes[c] = passes[c];
+    for (int c = 0; c < bpk::kBatchClasses; ++c) B->passes[c] = passes[c];
     B->grid_blocks = grid_blocks;
     build_items(B);
     return upload(B);
 }
 
-int bp_batch_get_plan(const bp_batch* B, int32_t passes[4], int32_t* grid_blocks) {
+int bp_batch_get_plan(const bp_batch* B, int32_t passes[5], int32_t* grid_blocks) {
     if (!B || !passes || !grid_blocks) return fail(BP_EINVAL, "null argument");
-    for (int c = 0; c < 4; ++c) passes[c] = B->passes[c];
+    for (int c = 0; c < bpk::kBatchClasses; ++c) passes[c] = B->passes[c];
     *grid_blocks = B->grid_blocks;
     return BP_OK;
 }
@@ -340,17 +348,17 @@ int bp_batch_autotune(bp_batch* B, int32_t mode, int32_t trial_iters, float* bes
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
-    // Candidates: item sizes that move about the same bytes per item across
-    // the labels-per-lane classes (scaled 1x/2x/4x/8x), times persistent grid
-    // sizes of 2..16 workgroups per CU.
-    const int base[4] = {4, 2, 1, 1};
+    // Candidates: items of 1/2/4/8 passes (a pass moves about the same bytes
+    // in every lane class), times persistent grid sizes of 2..16 workgroups
+    // per CU, and one item per workgroup (hardware dispatch order).
     float best = 1e30f;
-    int best_passes[4] = {4, 2, 1, 1}, best_grid = std::max(1, cus) * 8;
+    int best_passes[bpk::kBatchClasses] = {1, 1, 1, 1, 1}, best_grid = std::max(1, cus) * 8;
     for (int scale : {1, 2, 4, 8}) {
-        for (int per_cu : {2, 4, 8, 16}) {
-            int32_t pl[4];
-            for (int c = 0; c < 4; ++c) pl[c] = base[c] * scale;
-            if ((st = bp_batch_set_plan(B, pl, std::max(1, cus) * per_cu))) break;
+        for (int per_cu : {2, 4, 8, 16, 0}) {
+            int32_t pl[bpk::kBatchClasses];
+            for (int c = 0; c < bpk::kBatchClasses; ++c) pl[c] = scale;
+            const int grid_try = per_cu ? std::max(1, cus) * per_cu : (1 << 30);
+            if ((st = bp_batch_set_plan(B, pl, grid_try))) break;
             e = launch_iters(B, kmode, 1, B->parity, B->stream);  // warm
             if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
             if (e == hipSuccess) e = launch_iters(B, kmode, trial_iters, B->parity ^ 1, B->stream);
@@ -363,8 +371,8 @@ int bp_batch_autotune(bp_batch* B, int32_t mode, int32_t trial_iters, float* bes
             const float us = ms * 1000.0f / trial_iters;
             if (us < best) {
                 best = us;
-                for (int c = 0; c < 4; ++c) best_passes[c] = pl[c];
-                best_grid = std::max(1, cus) * per_cu;
+                for (int c = 0; c < bpk::kBatchClasses; ++c) best_passes[c] = pl[c];
+                best_grid = grid_try;
             }
         }
         if (st) break;

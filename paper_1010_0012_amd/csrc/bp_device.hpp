@@ -1,10 +1,19 @@
 // Device-side building blocks shared by every BP kernel (gfx950, wave64).
 //
-// Mapping: one pixel per 16-lane DPP row.  Lane l of the row owns the LPL
-// consecutive labels [l*LPL, (l+1)*LPL); the row's capacity is 16*LPL >= M
-// and labels >= M are padding that holds h = 0.  Cross-lane traffic stays
-// inside a row, so every row-wide reduction and every label shift is a DPP
-// modifier on an ordinary VALU op: no LDS, no barrier.
+// Mapping: one pixel per group of G lanes, G = 4, 8, 16, 32 or 64, each lane
+// owning kLpl = 4 consecutive labels [4*pos, 4*pos + 4) with pos = lane mod G:
+// the group holds 4*G >= M labels and labels >= M are padding with h = 0.
+// Every label row is therefore read and written as one float4 per lane, and
+// a wave's load or store instruction covers 64/G consecutive pixels'
+// contiguous rows.  (With 8 labels per lane, two float4 per lane at a 32-byte
+// lane stride, the same memory pattern measured 4.75 TB/s on MI355X against
+// 6.0 TB/s for one float4 per lane at M = 128.)
+//
+// Cross-lane traffic stays inside the group: reductions are DPP butterflies
+// (quad_perm, row_half_mirror, row_mirror) plus, for G >= 32, ds_swizzle
+// (xor 16) and ds_bpermute (xor 32); label shifts are DPP row_shr/row_shl
+// (G <= 16) or chained wave_shr/wave_shl by one lane (G >= 32), with the
+// lanes that would read another pixel's labels zeroed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,12 +21,13 @@
 
 namespace bpk {
 
-constexpr int kRow = 16;            // lanes per pixel (one DPP row)
+constexpr int kLpl = 4;             // labels per lane
 #ifndef BP_BLOCK
 #define BP_BLOCK 256
 #endif
-constexpr int kBlock = BP_BLOCK;    // threads per workgroup (16 lanes per pixel row)
+constexpr int kBlock = BP_BLOCK;    // threads per workgroup
 constexpr int kMaxTab = 256;        // potential table entries (|d| < BP_MAX_LABELS)
+constexpr int kDTab = 32;           // double window weights carried in the arguments (|d| <= 31)
 
 enum Mode { kSum = 0, kMax = 1 };
 
@@ -29,6 +39,14 @@ enum Mode { kSum = 0, kMax = 1 };
 #endif
 constexpr bool kMsgNT = BP_MSG_NT;      // message loads/stores non-temporal
 constexpr bool kUnaryNT = BP_UNARY_NT;  // unary loads non-temporal
+
+// Lanes per pixel for M labels: the smallest power of two >= ceil(M/4), at
+// least 4 (a quad) and at most 64 (a wave).
+constexpr int lanes_for(int M) {
+    int g = 4;
+    while (g * kLpl < M && g < 64) g *= 2;
+    return g;
+}
 
 // Inbox directions: where the sender sits relative to the receiver.
 enum Dir { kLeft = 0, kRight = 1, kUp = 2, kDown = 3 };
@@ -45,18 +63,26 @@ struct UpdateArgs {
     int half_w;            // (W + 1) / 2, checkerboard slot mapping
     int n_slots;           // pixels (or checkerboard slots) covered by the launch
     int T;                 // truncation (used by the runtime-window kernels)
-    float fbar;            // potential outside the window
-    float tab[kMaxTab];    // sum: f(d) - fbar for d <= T, 0 beyond; max/dense: f(d) for d <= T
+    float fbar;            // potential outside the window (float32, max-product)
+    float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)
+    // Sum-product works in double end to end: the potential in double and
+    // every accumulation in double, messages rounded once to float32.
+    double fbar_d;         // fbar in double
+    double alpha_d;        // alpha in double (tables built on the device)
+    double dtab[kDTab];    // f(d) - fbar in double for d <= min(T, kDTab-1), 0 beyond T
 };
 
 // ---------------------------------------------------------------- DPP ----
 // DPP16 controls (GFX9 encoding).
-constexpr int kQuad1032 = 0xB1;     // quad_perm:[1,0,3,2]
-constexpr int kQuad2301 = 0x4E;     // quad_perm:[2,3,0,1]
-constexpr int kRowMirror = 0x140;   // lane i <- lane 15-i
+constexpr int kQuad1032 = 0xB1;       // quad_perm:[1,0,3,2]
+constexpr int kQuad2301 = 0x4E;       // quad_perm:[2,3,0,1]
+constexpr int kRowMirror = 0x140;     // lane i <- lane 15-i
 constexpr int kRowHalfMirror = 0x141; // lane i <- lane 7-i within each half row
+constexpr int kWaveShl1 = 0x130;      // lane i <- lane i+1 across the wave
+constexpr int kWaveShr1 = 0x138;      // lane i <- lane i-1 across the wave
 constexpr int row_shl(int j) { return 0x100 + j; }  // lane i <- lane i+j (0 past the row end)
 constexpr int row_shr(int j) { return 0x110 + j; }  // lane i <- lane i-j (0 before the row start)
+constexpr int kSwizzleXor16 = 0x401F; // ds_swizzle bit mode: lane i <- lane i^16 (within 32)
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -69,31 +95,121 @@ __device__ __forceinline__ int dpp_i(int v) {
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
-// Butterfly over the 16 lanes of a row; every lane ends with the same bits
+__device__ __forceinline__ float xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), kSwizzleXor16));
+}
+__device__ __forceinline__ int xor16_i(int v) { return __builtin_amdgcn_ds_swizzle(v, kSwizzleXor16); }
+__device__ __forceinline__ float xor32(float v) {
+    const int src = ((int)(threadIdx.x & 63) ^ 32) << 2;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
+}
+__device__ __forceinline__ int xor32_i(int v) {
+    const int src = ((int)(threadIdx.x & 63) ^ 32) << 2;
+    return __builtin_amdgcn_ds_bpermute(src, v);
+}
+
+// Butterfly over the G lanes of a pixel; every lane ends with the same bits
 // (each step adds two operands that are the same pair on both partners).
-__device__ __forceinline__ float row_sum(float v) {
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
     v += dpp<kQuad1032>(v);
     v += dpp<kQuad2301>(v);
-    v += dpp<kRowHalfMirror>(v);
-    v += dpp<kRowMirror>(v);
+    if constexpr (G >= 8) v += dpp<kRowHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp<kRowMirror>(v);
+    if constexpr (G >= 32) v += xor16(v);
+    if constexpr (G >= 64) v += xor32(v);
     return v;
 }
 
-__device__ __forceinline__ float row_max(float v) {
+template <int G>
+__device__ __forceinline__ float group_max(float v) {
     v = fmaxf(v, dpp<kQuad1032>(v));
     v = fmaxf(v, dpp<kQuad2301>(v));
-    v = fmaxf(v, dpp<kRowHalfMirror>(v));
-    v = fmaxf(v, dpp<kRowMirror>(v));
+    if constexpr (G >= 8) v = fmaxf(v, dpp<kRowHalfMirror>(v));
+    if constexpr (G >= 16) v = fmaxf(v, dpp<kRowMirror>(v));
+    if constexpr (G >= 32) v = fmaxf(v, xor16(v));
+    if constexpr (G >= 64) v = fmaxf(v, xor32(v));
     return v;
 }
 
-template <int MODE>
-__device__ __forceinline__ float row_reduce(float v) {
-    if constexpr (MODE == kSum) return row_sum(v); else return row_max(v);
+template <int MODE, int G>
+__device__ __forceinline__ float group_reduce(float v) {
+    if constexpr (MODE == kSum) return group_sum<G>(v); else return group_max<G>(v);
+}
+
+// Double-precision shuffles: each 32-bit half moves with the same pattern.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double xor16_d(double v) {
+    return __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(v), kSwizzleXor16),
+                            __builtin_amdgcn_ds_swizzle(__double2loint(v), kSwizzleXor16));
+}
+__device__ __forceinline__ double xor32_d(double v) {
+    const int src = ((int)(threadIdx.x & 63) ^ 32) << 2;
+    return __hiloint2double(__builtin_amdgcn_ds_bpermute(src, __double2hiint(v)),
+                            __builtin_amdgcn_ds_bpermute(src, __double2loint(v)));
+}
+
+// Group sum in double (the sum-product accumulations; same butterfly, so
+// every lane ends with the same bits).
+template <int G>
+__device__ __forceinline__ double group_sum_d(double v) {
+    v += dpp_d<kQuad1032>(v);
+    v += dpp_d<kQuad2301>(v);
+    if constexpr (G >= 8) v += dpp_d<kRowHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_d<kRowMirror>(v);
+    if constexpr (G >= 32) v += xor16_d(v);
+    if constexpr (G >= 64) v += xor32_d(v);
+    return v;
+}
+
+// (value, index) tournament over the group: larger value wins, the lower
+// index breaks ties; the result is the same on every lane.
+template <int G>
+__device__ __forceinline__ void group_argmax(float& best, int& arg) {
+    auto take = [&](float ob, int oa) {
+        if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
+    };
+    take(dpp<kQuad1032>(best), dpp_i<kQuad1032>(arg));
+    take(dpp<kQuad2301>(best), dpp_i<kQuad2301>(arg));
+    if constexpr (G >= 8) take(dpp<kRowHalfMirror>(best), dpp_i<kRowHalfMirror>(arg));
+    if constexpr (G >= 16) take(dpp<kRowMirror>(best), dpp_i<kRowMirror>(arg));
+    if constexpr (G >= 32) take(xor16(best), xor16_i(arg));
+    if constexpr (G >= 64) take(xor32(best), xor32_i(arg));
+}
+
+// Label shifts inside the group: lane pos receives lane pos-J (from_lower)
+// or pos+J (from_upper) of the same pixel, 0 where that lane does not exist.
+template <int G, int J>
+__device__ __forceinline__ float from_lower(float v, int pos) {
+    static_assert(G <= 16, "wide groups shift one lane at a time");
+    const float t = dpp<row_shr(J)>(v);
+    if constexpr (G == 16) return t;
+    else return pos < J ? 0.0f : t;
+}
+template <int G, int J>
+__device__ __forceinline__ float from_upper(float v, int pos) {
+    static_assert(G <= 16, "wide groups shift one lane at a time");
+    const float t = dpp<row_shl(J)>(v);
+    if constexpr (G == 16) return t;
+    else return pos >= G - J ? 0.0f : t;
+}
+template <int G>
+__device__ __forceinline__ float lower1(float v, int pos) {  // G >= 32: one lane across rows
+    const float t = dpp<kWaveShr1>(v);
+    return pos == 0 ? 0.0f : t;
+}
+template <int G>
+__device__ __forceinline__ float upper1(float v, int pos) {
+    const float t = dpp<kWaveShl1>(v);
+    return pos == G - 1 ? 0.0f : t;
 }
 
 // ------------------------------------------------------- label vectors ----
-typedef float v2f __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Streaming hint: every message and unary entry is touched once per launch
@@ -109,47 +225,29 @@ __device__ __forceinline__ void st(T* p, T v, bool nt) {
     if (nt) __builtin_nontemporal_store(v, p); else *p = v;
 }
 
-// Load this lane's LPL labels of one pixel row (base points at label 0).
-// full: M == 16*LPL, so the lane's labels are all real and 4*LPL-byte
-// aligned; otherwise labels >= M read `fill`.
-template <int LPL, bool NT>
+// Load this lane's 4 labels of one pixel row (base points at label 0).
+// full: M == 4*G, so every lane's float4 is real and 16-byte aligned;
+// otherwise labels >= M read `fill` (and M need not be a multiple of 4).
+template <bool NT>
 __device__ __forceinline__ void load_labels(const float* base, int x0, int M, bool full,
-                                            float (&v)[LPL], float fill) {
+                                            float (&v)[kLpl], float fill) {
     if (full) {
-        if constexpr (LPL == 1) {
-            v[0] = ld(base + x0, NT);
-        } else if constexpr (LPL == 2) {
-            v2f t = ld(reinterpret_cast<const v2f*>(base + x0), NT);
-            v[0] = t.x; v[1] = t.y;
-        } else {
-#pragma unroll
-            for (int i = 0; i < LPL; i += 4) {
-                v4f t = ld(reinterpret_cast<const v4f*>(base + x0 + i), NT);
-                v[i] = t.x; v[i + 1] = t.y; v[i + 2] = t.z; v[i + 3] = t.w;
-            }
-        }
+        const v4f t = ld(reinterpret_cast<const v4f*>(base + x0), NT);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     } else {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i) v[i] = (x0 + i < M) ? ld(base + x0 + i, NT) : fill;
+        for (int i = 0; i < kLpl; ++i) v[i] = (x0 + i < M) ? ld(base + x0 + i, NT) : fill;
     }
 }
 
-template <int LPL, bool NT>
+template <bool NT>
 __device__ __forceinline__ void store_labels(float* base, int x0, int M, bool full,
-                                             const float (&v)[LPL]) {
+                                             const float (&v)[kLpl]) {
     if (full) {
-        if constexpr (LPL == 1) {
-            st(base + x0, v[0], NT);
-        } else if constexpr (LPL == 2) {
-            st(reinterpret_cast<v2f*>(base + x0), v2f{v[0], v[1]}, NT);
-        } else {
-#pragma unroll
-            for (int i = 0; i < LPL; i += 4)
-                st(reinterpret_cast<v4f*>(base + x0 + i), v4f{v[i], v[i + 1], v[i + 2], v[i + 3]}, NT);
-        }
+        st(reinterpret_cast<v4f*>(base + x0), v4f{v[0], v[1], v[2], v[3]}, NT);
     } else {
 #pragma unroll
-        for (int i = 0; i < LPL; ++i)
+        for (int i = 0; i < kLpl; ++i)
             if (x0 + i < M) st(base + x0 + i, v[i], NT);
     }
 }
@@ -183,49 +281,6 @@ __device__ __forceinline__ Pixel map_slot(int slot, const UpdateArgs& a) {
     return px;
 }
 
-__device__ __forceinline__ int neighbour(const Pixel& px, int dir, int W) {
-    switch (dir) {
-        case kLeft: return px.p - 1;
-        case kRight: return px.p + 1;
-        case kUp: return px.p - W;
-        default: return px.p + W;
-    }
-}
-
-__device__ __forceinline__ constexpr int opposite(int dir) { return dir ^ 1; }
-
-// The unary and the four inbox messages of one pixel (this lane's labels).
-template <int LPL>
-struct PixelInputs {
-    float g[LPL];
-    float m[4][LPL];
-};
-
-// Load the unary and the inbox of one pixel from explicit pointers (plane =
-// N*M floats between inbox planes); off-grid neighbours read as 1.
-template <int LPL>
-__device__ __forceinline__ void load_pixel_ptr(const float* g, const float* in, size_t plane, int M,
-                                               const Pixel& px, int x0, bool full,
-                                               PixelInputs<LPL>& r) {
-    const size_t off = (size_t)px.p * M;
-    load_labels<LPL, kUnaryNT>(g + off, x0, M, full, r.g, 0.0f);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (px.has[k]) {
-            load_labels<LPL, kMsgNT>(in + k * plane + off, x0, M, full, r.m[k], 1.0f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < LPL; ++i) r.m[k][i] = 1.0f;
-        }
-    }
-}
-
-template <int LPL>
-__device__ __forceinline__ void load_pixel(const UpdateArgs& a, const Pixel& px, int x0, bool full,
-                                           PixelInputs<LPL>& in) {
-    load_pixel_ptr<LPL>(a.g, a.in, (size_t)a.N * a.M, a.M, px, x0, full, in);
-}
-
 // Synchronous slot -> pixel (row-major).
 __device__ __forceinline__ Pixel sync_pixel(int slot, int H, int W, int N) {
     Pixel px;
@@ -240,15 +295,63 @@ __device__ __forceinline__ Pixel sync_pixel(int slot, int H, int W, int N) {
     return px;
 }
 
+__device__ __forceinline__ int neighbour(const Pixel& px, int dir, int W) {
+    switch (dir) {
+        case kLeft: return px.p - 1;
+        case kRight: return px.p + 1;
+        case kUp: return px.p - W;
+        default: return px.p + W;
+    }
+}
+
+__device__ __forceinline__ constexpr int opposite(int dir) { return dir ^ 1; }
+
+// The unary and the four inbox messages of one pixel (this lane's labels).
+struct PixelInputs {
+    float g[kLpl];
+    float m[4][kLpl];
+};
+
+// Inputs of a slot that maps to no pixel: finite values whose results are
+// never stored.
+__device__ __forceinline__ void dummy_pixel(PixelInputs& r) {
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        r.g[i] = 1.0f;
+        r.m[0][i] = r.m[1][i] = r.m[2][i] = r.m[3][i] = 1.0f;
+    }
+}
+
+// Load the unary and the inbox of one pixel from explicit pointers (plane =
+// N*M floats between inbox planes); off-grid neighbours read as 1.
+__device__ __forceinline__ void load_pixel_ptr(const float* g, const float* in, size_t plane, int M,
+                                               const Pixel& px, int x0, bool full, PixelInputs& r) {
+    const size_t off = (size_t)px.p * M;
+    load_labels<kUnaryNT>(g + off, x0, M, full, r.g, 0.0f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (px.has[k]) {
+            load_labels<kMsgNT>(in + k * plane + off, x0, M, full, r.m[k], 1.0f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) r.m[k][i] = 1.0f;
+        }
+    }
+}
+
+__device__ __forceinline__ void load_pixel(const UpdateArgs& a, const Pixel& px, int x0, bool full,
+                                           PixelInputs& in) {
+    load_pixel_ptr(a.g, a.in, (size_t)a.N * a.M, a.M, px, x0, full, in);
+}
+
 // Eq. 5 for the four outgoing messages: h_o = g * product of the inbox
 // messages except the one from the target o.  Shared partial products:
 // gUD = g*mU*mD serves the horizontal targets, gLR = g*mL*mR the vertical
 // ones (8 multiplies per label for the four vectors).  Padding labels have
 // g = 0, hence h = 0.
-template <int LPL>
-__device__ __forceinline__ void make_h(const PixelInputs<LPL>& in, float (&h)[4][LPL]) {
+__device__ __forceinline__ void make_h(const PixelInputs& in, float (&h)[4][kLpl]) {
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) {
+    for (int i = 0; i < kLpl; ++i) {
         const float gud = (in.g[i] * in.m[kUp][i]) * in.m[kDown][i];
         const float glr = (in.g[i] * in.m[kLeft][i]) * in.m[kRight][i];
         h[kLeft][i] = gud * in.m[kRight][i];   // to the left neighbour: skip its message
@@ -258,32 +361,73 @@ __device__ __forceinline__ void make_h(const PixelInputs<LPL>& in, float (&h)[4]
     }
 }
 
-// Normalise u (Sec. 3: explicit normalisation after each update) with one
-// IEEE division per message, then store into the receiver's inbox slot.
-template <int LPL>
-__device__ __forceinline__ void normalise_store_ptr(float* out, size_t plane, int M, int W,
-                                                    const Pixel& px, int dir, int x0, bool full,
-                                                    float (&u)[LPL]) {
-    float z = 0.0f;
+// Eq. 3 before normalisation, in the order every readout uses.
+__device__ __forceinline__ void make_belief(const PixelInputs& in, float (&b)[kLpl]) {
 #pragma unroll
-    for (int i = 0; i < LPL; ++i) {
-        if (!full && x0 + i >= M) u[i] = 0.0f;
-        z += u[i];
-    }
-    z = row_sum(z);
-    const float inv = 1.0f / z;
-#pragma unroll
-    for (int i = 0; i < LPL; ++i) u[i] *= inv;
+    for (int i = 0; i < kLpl; ++i)
+        b[i] = (((in.g[i] * in.m[kLeft][i]) * in.m[kRight][i]) * in.m[kUp][i]) * in.m[kDown][i];
+}
+
+// Store a finished message into the receiver's inbox slot.
+__device__ __forceinline__ void store_message(float* out, size_t plane, int M, int W, const Pixel& px,
+                                              int dir, int x0, bool full, const float (&m)[kLpl]) {
     if (px.ok && px.has[dir]) {
         const int q = neighbour(px, dir, W);
-        store_labels<LPL, kMsgNT>(out + opposite(dir) * plane + (size_t)q * M, x0, M, full, u);
+        store_labels<kMsgNT>(out + opposite(dir) * plane + (size_t)q * M, x0, M, full, m);
     }
 }
 
-template <int LPL>
+// 1/z in double from the hardware reciprocal and two Newton steps (each
+// roughly doubles the correct bits), ample for a result rounded to float.
+__device__ __forceinline__ double recip_d(double z) {
+    double r = __builtin_amdgcn_rcp(z);
+    r = fma(r, fma(-z, r, 1.0), r);
+    r = fma(r, fma(-z, r, 1.0), r);
+    return r;
+}
+
+// Sum-product normalisation (Sec. 3) in double: Z = sum of u over the
+// group, one reciprocal per message, m = u / Z rounded once to float.
+template <int G>
+__device__ __forceinline__ void normalise_d(double (&u)[kLpl], int M, int x0, bool full, float (&m)[kLpl]) {
+    double z = 0.0;
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        if (!full && x0 + i >= M) u[i] = 0.0;
+        z += u[i];
+    }
+    z = group_sum_d<G>(z);
+    const double inv = recip_d(z);
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) m[i] = (float)(u[i] * inv);
+}
+
+// Normalise u (Sec. 3: explicit normalisation after each update) with one
+// IEEE division per message, then store into the receiver's inbox slot.
+template <int G>
+__device__ __forceinline__ void normalise_store_ptr(float* out, size_t plane, int M, int W,
+                                                    const Pixel& px, int dir, int x0, bool full,
+                                                    float (&u)[kLpl]) {
+    float z = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        if (!full && x0 + i >= M) u[i] = 0.0f;
+        z += u[i];
+    }
+    z = group_sum<G>(z);
+    const float inv = 1.0f / z;
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) u[i] *= inv;
+    if (px.ok && px.has[dir]) {
+        const int q = neighbour(px, dir, W);
+        store_labels<kMsgNT>(out + opposite(dir) * plane + (size_t)q * M, x0, M, full, u);
+    }
+}
+
+template <int G>
 __device__ __forceinline__ void normalise_store(const UpdateArgs& a, const Pixel& px, int dir,
-                                                int x0, bool full, float (&u)[LPL]) {
-    normalise_store_ptr<LPL>(a.out, (size_t)a.N * a.M, a.M, a.W, px, dir, x0, full, u);
+                                                int x0, bool full, float (&u)[kLpl]) {
+    normalise_store_ptr<G>(a.out, (size_t)a.N * a.M, a.M, a.W, px, dir, x0, full, u);
 }
 
 }  // namespace bpk

@@ -25,7 +25,7 @@ struct GradLayout {
         nseg = n > 0 ? (n + k - 1) / k : 0;
         nckpt = nseg > 1 ? nseg - 1 : 0;
         buf = bp_align_up(G->msg_floats() * sizeof(float), 256);
-        blocks = bpk::adjoint_blocks(G->N);
+        blocks = bpk::adjoint_blocks(G->M, G->N);
         ckpt_off = 0;
         seg_off = ckpt_off + (size_t)nckpt * buf;
         lam_off = seg_off + (size_t)(n > 0 ? (k < n ? k : n) : 0) * buf;
@@ -44,7 +44,7 @@ int grad_checks(const bp_grid* G, int n, int k) {
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
     if (k < 1) return fail(BP_EINVAL, "ckpt_every must be >= 1");
     if (!bpk::adjoint_supported(G->M, G->T))
-        return fail(BP_EUNSUPPORTED, "adjoint supports M <= 128 and T <= 15 (M=%d, T=%d)", G->M, G->T);
+        return fail(BP_EUNSUPPORTED, "adjoint supports T <= 16 (12 for M <= 16) (M=%d, T=%d)", G->M, G->T);
     return BP_OK;
 }
 
@@ -127,12 +127,14 @@ int bp_backward(bp_grid* G, const float* dL_db, float* dtheta, float* dalpha) {
     aa.alpha_part = L.part(ws);
     aa.H = G->H; aa.W = G->W; aa.M = G->M; aa.N = G->N;
     aa.fbar = G->fbar;
+    aa.fbar_d = G->fbar_d;
     const double dfbar = G->fbar_tied ? -(double)G->T * std::exp(-(double)G->alpha * G->T) : 0.0;
     aa.dfbar = (float)dfbar;
     for (int d = 0; d < bpk::kAdjTab; ++d) {
         const bool in = d <= G->T;
         const double f = std::exp(-(double)G->alpha * d);
         aa.w[d] = in ? G->tab_w[d] : 0.0f;
+        aa.wd[d] = in ? f - G->fbar_d : 0.0;
         aa.dw[d] = in ? (float)(-(double)d * f - dfbar) : 0.0f;
     }
     int lcur = 0;

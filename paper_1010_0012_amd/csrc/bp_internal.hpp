@@ -17,6 +17,8 @@ struct bp_grid {
     bool fbar_tied = false;               // fbar = f(T), moves with alpha
     float tab_f[bpk::kMaxTab] = {};  // f(d), d <= T (0 beyond)
     float tab_w[bpk::kMaxTab] = {};  // f(d) - fbar, d <= T (0 beyond)
+    double tab_wd[bpk::kDTab] = {};  // f(d) - fbar in double, d <= T (0 beyond)
+    double fbar_d = 0.0;             // fbar in double (exact exp(-alpha T) when tied)
     // caller-owned device memory
     void* ws = nullptr;
     int64_t ws_bytes = 0;

@@ -5,6 +5,9 @@
 namespace bpk {
 namespace {
 
+template <int G>
+unsigned adjoint_blocks_g(int N) { return (unsigned)((N + kBlock / G - 1) / (kBlock / G)); }
+
 // Fixed-order sum of the per-workgroup partials into out[0] (one workgroup).
 __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const float* part, int n, float* out) {
     __shared__ float s[kBlock];
@@ -20,79 +23,83 @@ __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const float* part,
 }
 
 
-// Register-window widths compiled for the adjoint (sum-product only); the
-// window reaches K*LPL labels each side and must fit the kAdjTab tables.
-template <int LPL> struct AdjK;
-template <> struct AdjK<1> { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8, 15}; };
-template <> struct AdjK<2> { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8}; };
-template <> struct AdjK<4> { static constexpr int v[] = {0, 1, 2, 3, 4}; };
-template <> struct AdjK<8> { static constexpr int v[] = {0, 1, 2}; };
+// Window half-widths compiled for the adjoint (sum-product only); every tap
+// index must fit the kAdjTab tables and the window must stay in the group.
+template <int G> struct AdjTw { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8, 12, 16}; };
+template <> struct AdjTw<4> { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8, 12}; };
 
-template <int LPL>
-int adj_round_k(int k) {
-    for (int c : AdjK<LPL>::v)
-        if (c >= k && c * LPL < kAdjTab) return c;
+template <int G>
+int adj_round_tw(int T) {
+    for (int c : AdjTw<G>::v)
+        if (c >= T && c < kAdjTab) return c;
     return -1;
 }
 
-template <int LPL, int K>
+template <int G, int TW>
 hipError_t go_step(const AdjointArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((adjoint_step_kernel<LPL, K>), dim3(adjoint_blocks(a.N)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((adjoint_step_kernel<G, TW>), dim3(adjoint_blocks_g<G>(a.N)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
-template <int LPL>
-hipError_t step_k(const AdjointArgs& a, int T, hipStream_t s) {
-    switch (adj_round_k<LPL>(window_lanes(T, LPL))) {
-        case 0: return go_step<LPL, 0>(a, s);
-        case 1: return go_step<LPL, 1>(a, s);
-        case 2: return go_step<LPL, 2>(a, s);
-        case 3: if constexpr (LPL <= 4) return go_step<LPL, 3>(a, s); break;
-        case 4: if constexpr (LPL <= 4) return go_step<LPL, 4>(a, s); break;
-        case 6: if constexpr (LPL <= 2) return go_step<LPL, 6>(a, s); break;
-        case 8: if constexpr (LPL <= 2) return go_step<LPL, 8>(a, s); break;
-        case 15: if constexpr (LPL == 1) return go_step<LPL, 15>(a, s); break;
-        default: break;
+template <int G, int I = 0>
+hipError_t step_tw(const AdjointArgs& a, int tw, hipStream_t s) {
+    constexpr int n = sizeof(AdjTw<G>::v) / sizeof(int);
+    if constexpr (I < n) {
+        constexpr int TW = AdjTw<G>::v[I];
+        if (tw == TW) return go_step<G, TW>(a, s);
+        return step_tw<G, I + 1>(a, tw, s);
+    } else {
+        return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
-template <int LPL>
+template <int G>
 hipError_t go_seed(const SeedArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((adjoint_seed_kernel<LPL>), dim3(adjoint_blocks(a.N)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((adjoint_seed_kernel<G>), dim3(adjoint_blocks_g<G>(a.N)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-unsigned adjoint_blocks(int N) { return (unsigned)((N + kBlock / kRow - 1) / (kBlock / kRow)); }
+unsigned adjoint_blocks(int M, int N) {
+    switch (lanes_for(M)) {
+        case 4: return adjoint_blocks_g<4>(N);
+        case 8: return adjoint_blocks_g<8>(N);
+        case 16: return adjoint_blocks_g<16>(N);
+        case 32: return adjoint_blocks_g<32>(N);
+        default: return adjoint_blocks_g<64>(N);
+    }
+}
 
 bool adjoint_supported(int M, int T) {
-    switch (pick_lpl(M)) {
-        case 1: return adj_round_k<1>(window_lanes(T, 1)) >= 0;
-        case 2: return adj_round_k<2>(window_lanes(T, 2)) >= 0;
-        case 4: return adj_round_k<4>(window_lanes(T, 4)) >= 0;
-        case 8: return adj_round_k<8>(window_lanes(T, 8)) >= 0;
+    switch (lanes_for(M)) {
+        case 4: return adj_round_tw<4>(T) >= 0;
+        case 8: return adj_round_tw<8>(T) >= 0;
+        case 16: return adj_round_tw<16>(T) >= 0;
+        case 32: return adj_round_tw<32>(T) >= 0;
+        case 64: return adj_round_tw<64>(T) >= 0;
         default: return false;
     }
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs& a, int T, hipStream_t stream) {
-    switch (pick_lpl(a.M)) {
-        case 1: return step_k<1>(a, T, stream);
-        case 2: return step_k<2>(a, T, stream);
-        case 4: return step_k<4>(a, T, stream);
-        case 8: return step_k<8>(a, T, stream);
+    switch (lanes_for(a.M)) {
+        case 4: return step_tw<4>(a, adj_round_tw<4>(T), stream);
+        case 8: return step_tw<8>(a, adj_round_tw<8>(T), stream);
+        case 16: return step_tw<16>(a, adj_round_tw<16>(T), stream);
+        case 32: return step_tw<32>(a, adj_round_tw<32>(T), stream);
+        case 64: return step_tw<64>(a, adj_round_tw<64>(T), stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_adjoint_seed(const SeedArgs& a, hipStream_t stream) {
-    switch (pick_lpl(a.M)) {
-        case 1: return go_seed<1>(a, stream);
-        case 2: return go_seed<2>(a, stream);
+    switch (lanes_for(a.M)) {
         case 4: return go_seed<4>(a, stream);
         case 8: return go_seed<8>(a, stream);
+        case 16: return go_seed<16>(a, stream);
+        case 32: return go_seed<32>(a, stream);
+        case 64: return go_seed<64>(a, stream);
         default: return hipErrorInvalidValue;
     }
 }

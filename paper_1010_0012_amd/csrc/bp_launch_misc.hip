@@ -12,55 +12,55 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(float* dst, size_t n, floa
 }
 
 
-template <int LPL, int MODE>
+template <int G, int MODE>
 hipError_t go_dense(const UpdateArgs& a, hipStream_t s) {
-    constexpr int CAP = kRow * LPL;
-    const size_t lds = ((size_t)a.M * CAP + (kBlock / kRow) * CAP * 4) * sizeof(float);
+    const size_t lds = dense_lds_bytes(G, a.M, MODE);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&dense_update_kernel<LPL, MODE>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_update_kernel<G, MODE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int n_tiles = (a.n_slots + (kBlock / kRow) - 1) / (kBlock / kRow);
+    const int n_tiles = (a.n_slots + (kBlock / G) - 1) / (kBlock / G);
     const int grid = n_tiles < 4096 ? n_tiles : 4096;
-    hipLaunchKernelGGL((dense_update_kernel<LPL, MODE>), dim3(grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((dense_update_kernel<G, MODE>), dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t dense_lpl(const UpdateArgs& a, hipStream_t s) {
-    switch (pick_lpl(a.M)) {
-        case 1: return go_dense<1, MODE>(a, s);
-        case 2: return go_dense<2, MODE>(a, s);
+hipError_t dense_g(const UpdateArgs& a, hipStream_t s) {
+    switch (lanes_for(a.M)) {
         case 4: return go_dense<4, MODE>(a, s);
         case 8: return go_dense<8, MODE>(a, s);
+        case 16: return go_dense<16, MODE>(a, s);
+        case 32: return go_dense<32, MODE>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <int LPL>
+template <int G>
 hipError_t go_readout(const UpdateArgs& a, float* b, int* lab, hipStream_t s) {
-    const unsigned blocks = (unsigned)((a.n_slots + (kBlock / kRow) - 1) / (kBlock / kRow));
-    hipLaunchKernelGGL((readout_kernel<LPL>), dim3(blocks), dim3(kBlock), 0, s, a, b, lab);
+    const unsigned blocks = (unsigned)((a.n_slots + (kBlock / G) - 1) / (kBlock / G));
+    hipLaunchKernelGGL((readout_kernel<G>), dim3(blocks), dim3(kBlock), 0, s, a, b, lab);
     return hipGetLastError();
 }
 
 }  // namespace
 
+size_t dense_lds_need(int M, int mode) { return dense_lds_bytes(lanes_for(M), M, mode); }
+
 hipError_t launch_dense(const UpdateArgs& a, int mode, hipStream_t stream) {
     if (a.n_slots <= 0) return hipSuccess;
-    return mode == kSum ? dense_lpl<kSum>(a, stream) : dense_lpl<kMax>(a, stream);
+    return mode == kSum ? dense_g<kSum>(a, stream) : dense_g<kMax>(a, stream);
 }
 
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream) {
     if (a.n_slots <= 0) return hipSuccess;
-    switch (pick_lpl(a.M)) {
-        case 1: return go_readout<1>(a, beliefs, labels, stream);
-        case 2: return go_readout<2>(a, beliefs, labels, stream);
+    switch (lanes_for(a.M)) {
         case 4: return go_readout<4>(a, beliefs, labels, stream);
         case 8: return go_readout<8>(a, beliefs, labels, stream);
         case 16: return go_readout<16>(a, beliefs, labels, stream);
+        case 32: return go_readout<32>(a, beliefs, labels, stream);
+        case 64: return go_readout<64>(a, beliefs, labels, stream);
         default: return hipErrorInvalidValue;
     }
 }

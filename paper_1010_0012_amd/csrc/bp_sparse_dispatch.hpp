@@ -1,0 +1,79 @@
+// Instantiation table and dispatch of the sparse O(mM) update kernels,
+// included once per mode (bp_launch_sparse_sum.hip, bp_launch_sparse_max.hip).
+#pragma once
+
+#include "bp_kernels.hpp"
+#include "bp_launch.hpp"
+
+namespace bpk {
+
+// Window half-widths TW compiled per group size G; a request with truncation
+// T runs the smallest listed TW >= T (extra taps have weight 0).  The window
+// reaches ceil(TW/4) lanes each side, fewer than G.  Wider requests use the
+// runtime-window kernel.
+template <int G> struct TwList { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8, 12, 16}; };
+template <> struct TwList<4> { static constexpr int v[] = {0, 1, 2, 3, 4, 6, 8, 12}; };
+
+template <int G>
+int round_tw(int T) {
+    for (int c : TwList<G>::v)
+        if (c >= T) return c;
+    return -1;
+}
+
+inline int sparse_tw(int M, int T) {
+    switch (lanes_for(M)) {
+        case 4: return round_tw<4>(T);
+        case 8: return round_tw<8>(T);
+        case 16: return round_tw<16>(T);
+        case 32: return round_tw<32>(T);
+        case 64: return round_tw<64>(T);
+        default: return -1;
+    }
+}
+
+template <int G>
+unsigned groups_blocks(int n_slots) {
+    return (unsigned)((n_slots + kBlock / G - 1) / (kBlock / G));
+}
+
+template <int G, int TW, int MODE>
+hipError_t go_sparse(const UpdateArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((sparse_update_kernel<G, TW, MODE>), dim3(groups_blocks<G>(a.n_slots)), dim3(kBlock), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+template <int G, int MODE>
+hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((sparse_update_wide_kernel<G, MODE>), dim3(groups_blocks<G>(a.n_slots)), dim3(kBlock),
+                       wide_lds_bytes(G), s, a);
+    return hipGetLastError();
+}
+
+template <int G, int MODE, int I = 0>
+hipError_t dispatch_tw(const UpdateArgs& a, int tw, hipStream_t s) {
+    constexpr int n = sizeof(TwList<G>::v) / sizeof(int);
+    if constexpr (I < n) {
+        constexpr int TW = TwList<G>::v[I];
+        if (tw == TW) return go_sparse<G, TW, MODE>(a, s);
+        return dispatch_tw<G, MODE, I + 1>(a, tw, s);
+    } else {
+        return go_sparse_wide<G, MODE>(a, s);
+    }
+}
+
+template <int MODE>
+hipError_t dispatch_sparse(const UpdateArgs& a, hipStream_t s) {
+    const int tw = sparse_tw(a.M, a.T);
+    switch (lanes_for(a.M)) {
+        case 4: return dispatch_tw<4, MODE>(a, tw, s);
+        case 8: return dispatch_tw<8, MODE>(a, tw, s);
+        case 16: return dispatch_tw<16, MODE>(a, tw, s);
+        case 32: return dispatch_tw<32, MODE>(a, tw, s);
+        case 64: return dispatch_tw<64, MODE>(a, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bpk

@@ -40,6 +40,9 @@ def run_gpu(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5,
 
 def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, impl=gb.SPARSE,
                init=None):
+    # the C ABI takes alpha and fbar as float32: give the oracle the same model
+    alpha = float(np.float32(alpha))
+    fbar = None if fbar is None else float(np.float32(fbar))
     pot = gb.truncated_linear(M, T, alpha, fbar)
     g = g32.astype(np.float64)
     state = gb.run(g, pot, mode, n_iters, schedule, impl,

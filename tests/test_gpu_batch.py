@@ -95,7 +95,7 @@ def test_plans_do_not_change_results():
     batch, _ = make_batch(SMALL, seeds)
     batch.iterate("sum", 4)
     ref = results(batch)
-    for passes, grid in (([1, 1, 1, 1], 1), ([3, 5, 2, 7], 7), ([64, 32, 16, 16], 1024)):
+    for passes, grid in (([1, 1, 1, 1, 1], 1), ([3, 5, 2, 7, 1], 7), ([64, 32, 16, 16, 4], 1024), ([2, 2, 2, 2, 2], 1 << 30)):
         batch.set_plan(passes, grid)
         batch.reset()
         batch.iterate("sum", 4)
@@ -118,7 +118,7 @@ def test_batch_errors():
     g = torch.rand(4, 4, 16, device="cuda") + 0.1
     with pytest.raises(L.BPError) as e:
         L.bp_batch_init([L.bp_grid_desc(4, 4, 16, 9, 1.0, L.BP_FBAR_TIED, g.data_ptr())])
-    assert e.value.status == L.BP_EUNSUPPORTED
+    assert e.value.status == L.BP_EUNSUPPORTED  # T > 8
     with pytest.raises(L.BPError) as e:
         L.bp_batch_init([L.bp_grid_desc(4, 4, 16, 2, 1.0, -3.0, g.data_ptr())])
     assert e.value.status == L.BP_EINVAL
