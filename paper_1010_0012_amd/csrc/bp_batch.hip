@@ -36,6 +36,8 @@ struct bp_batch {
     std::vector<size_t> msg_bytes_off;        // per instance, first of its two buffers
     std::vector<bpk::InstDesc> hdesc;
     std::vector<bpk::Item> hitems;
+    int class_off[bpk::kBatchClasses] = {};   // items of lane class c: [class_off[c], +class_n[c])
+    int class_n[bpk::kBatchClasses] = {};
     int parity = 0;
     bool use_graphs = true;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (mode, n, parity)
@@ -65,13 +67,14 @@ void drop_graphs(bp_batch* B) {
 }
 
 // Work queue: every instance cut into items of passes*kBlock/G pixels,
-// sorted by bytes moved (pixels * M), longest first, ties by instance then
-// pixel.
+// grouped by lane class (one kernel per class) and, within a class, sorted
+// by bytes moved (pixels * M), longest first, ties by instance then pixel.
 void build_items(bp_batch* B) {
-    B->hitems.clear();
+    std::vector<bpk::Item> per[bpk::kBatchClasses];
     for (int j = 0; j < B->n; ++j) {
         const int N = B->desc[j].H * B->desc[j].W;
-        const int P = B->passes[lane_class(B->desc[j].M)];
+        const int c = lane_class(B->desc[j].M);
+        const int P = B->passes[c];
         const int rpb = bpk::kBlock / bpk::lanes_for(B->desc[j].M);
         const int chunk = rpb * P;
         for (int first = 0; first < N; first += chunk) {
@@ -81,15 +84,38 @@ void build_items(bp_batch* B) {
             it.first = first;
             it.passes = std::min(P, (left + rpb - 1) / rpb);
             it.pad = 0;
-            B->hitems.push_back(it);
+            per[c].push_back(it);
         }
     }
-    std::stable_sort(B->hitems.begin(), B->hitems.end(), [&](const bpk::Item& a, const bpk::Item& b) {
-        const int ga = bpk::lanes_for(B->desc[a.inst].M), gb = bpk::lanes_for(B->desc[b.inst].M);
-        const long long ca = (long long)a.passes * (bpk::kBlock / ga) * B->desc[a.inst].M;
-        const long long cb = (long long)b.passes * (bpk::kBlock / gb) * B->desc[b.inst].M;
-        return ca > cb;
-    });
+    B->hitems.clear();
+    for (int c = 0; c < bpk::kBatchClasses; ++c) {
+        std::stable_sort(per[c].begin(), per[c].end(), [&](const bpk::Item& a, const bpk::Item& b) {
+            return (long long)a.passes * B->desc[a.inst].M > (long long)b.passes * B->desc[b.inst].M;
+        });
+        B->class_off[c] = (int)B->hitems.size();
+        B->class_n[c] = (int)per[c].size();
+        B->hitems.insert(B->hitems.end(), per[c].begin(), per[c].end());
+    }
+}
+
+template <int MODE, int G>
+hipError_t launch_class(const bpk::InstDesc* inst, const bpk::Item* items, int n, unsigned grid, int par,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((bpk::batch_update_kernel<MODE, G>), dim3(grid), dim3(bpk::kBlock), 0, s, inst, items, n,
+                       par);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_class_mode(int c, const bpk::InstDesc* inst, const bpk::Item* items, int n, unsigned grid,
+                             int par, hipStream_t s) {
+    switch (c) {
+        case 0: return launch_class<MODE, 4>(inst, items, n, grid, par, s);
+        case 1: return launch_class<MODE, 8>(inst, items, n, grid, par, s);
+        case 2: return launch_class<MODE, 16>(inst, items, n, grid, par, s);
+        case 3: return launch_class<MODE, 32>(inst, items, n, grid, par, s);
+        default: return launch_class<MODE, 64>(inst, items, n, grid, par, s);
+    }
 }
 
 int upload(bp_batch* B) {
@@ -104,21 +130,22 @@ int upload(bp_batch* B) {
     return e == hipSuccess ? BP_OK : hip_fail(e, "upload synchronize");
 }
 
+// One iteration = one persistent launch per non-empty lane class; the
+// classes touch disjoint instances, so their order does not matter.
 hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s) {
     const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
     const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
-    const int n_items = (int)B->hitems.size();
-    const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, n_items));
     for (int t = 0; t < n; ++t) {
         const int par = (parity0 + t) & 1;
-        if (mode == bpk::kSum)
-            hipLaunchKernelGGL(bpk::batch_update_kernel<bpk::kSum>, dim3(grid), dim3(bpk::kBlock), 0, s,
-                               inst, items, n_items, par);
-        else
-            hipLaunchKernelGGL(bpk::batch_update_kernel<bpk::kMax>, dim3(grid), dim3(bpk::kBlock), 0, s,
-                               inst, items, n_items, par);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int c = 0; c < bpk::kBatchClasses; ++c) {
+            const int cn = B->class_n[c];
+            if (cn == 0) continue;
+            const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, cn));
+            const bpk::Item* ci = items + B->class_off[c];
+            hipError_t e = mode == bpk::kSum ? launch_class_mode<bpk::kSum>(c, inst, ci, cn, grid, par, s)
+                                             : launch_class_mode<bpk::kMax>(c, inst, ci, cn, grid, par, s);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -391,12 +418,27 @@ static int batch_readout(bp_batch* B, float* beliefs, int32_t* labels) {
     if ((st = set_device(B))) return st;
     const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
     const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
-    const int n_items = (int)B->hitems.size();
-    const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, n_items));
-    hipLaunchKernelGGL(bpk::batch_readout_kernel, dim3(grid), dim3(bpk::kBlock), 0, B->stream, inst, items,
-                       n_items, B->parity, beliefs, labels);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? BP_OK : hip_fail(e, "batch readout launch");
+    for (int c = 0; c < bpk::kBatchClasses; ++c) {
+        const int cn = B->class_n[c];
+        if (cn == 0) continue;
+        const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, cn));
+        const bpk::Item* ci = items + B->class_off[c];
+        switch (c) {
+            case 0: hipLaunchKernelGGL(bpk::batch_readout_kernel<4>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       inst, ci, cn, B->parity, beliefs, labels); break;
+            case 1: hipLaunchKernelGGL(bpk::batch_readout_kernel<8>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       inst, ci, cn, B->parity, beliefs, labels); break;
+            case 2: hipLaunchKernelGGL(bpk::batch_readout_kernel<16>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       inst, ci, cn, B->parity, beliefs, labels); break;
+            case 3: hipLaunchKernelGGL(bpk::batch_readout_kernel<32>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       inst, ci, cn, B->parity, beliefs, labels); break;
+            default: hipLaunchKernelGGL(bpk::batch_readout_kernel<64>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                        inst, ci, cn, B->parity, beliefs, labels); break;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "batch readout launch");
+    }
+    return BP_OK;
 }
 
 int bp_batch_beliefs(bp_batch* B, float* out_dev) {

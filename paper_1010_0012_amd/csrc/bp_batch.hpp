@@ -79,29 +79,20 @@ __device__ __forceinline__ void batch_item(const InstDesc* __restrict__ d, const
     }
 }
 
-template <int MODE>
+// One persistent kernel per lane class G (the work queue is partitioned by
+// class), so each kernel's register budget is that of its own three window
+// variants rather than the union over every class.
+template <int MODE, int G>
 __global__ __launch_bounds__(kBlock) void batch_update_kernel(const InstDesc* __restrict__ inst,
                                                               const Item* __restrict__ items,
                                                               int n_items, int parity) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item item = items[it];
         const InstDesc* d = inst + item.inst;
-        switch (d->arm) {
-            case 0: batch_item<4, 2, MODE>(d, item, parity); break;
-            case 1: batch_item<4, 4, MODE>(d, item, parity); break;
-            case 2: batch_item<4, 8, MODE>(d, item, parity); break;
-            case 3: batch_item<8, 2, MODE>(d, item, parity); break;
-            case 4: batch_item<8, 4, MODE>(d, item, parity); break;
-            case 5: batch_item<8, 8, MODE>(d, item, parity); break;
-            case 6: batch_item<16, 2, MODE>(d, item, parity); break;
-            case 7: batch_item<16, 4, MODE>(d, item, parity); break;
-            case 8: batch_item<16, 8, MODE>(d, item, parity); break;
-            case 9: batch_item<32, 2, MODE>(d, item, parity); break;
-            case 10: batch_item<32, 4, MODE>(d, item, parity); break;
-            case 11: batch_item<32, 8, MODE>(d, item, parity); break;
-            case 12: batch_item<64, 2, MODE>(d, item, parity); break;
-            case 13: batch_item<64, 4, MODE>(d, item, parity); break;
-            default: batch_item<64, 8, MODE>(d, item, parity); break;
+        switch (d->arm % 3) {  // arms 3c, 3c+1, 3c+2: TW = 2, 4, 8 for class c
+            case 0: batch_item<G, 2, MODE>(d, item, parity); break;
+            case 1: batch_item<G, 4, MODE>(d, item, parity); break;
+            default: batch_item<G, 8, MODE>(d, item, parity); break;
         }
     }
 }
@@ -127,20 +118,14 @@ __device__ __forceinline__ void batch_readout_item(const InstDesc* __restrict__ 
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(kBlock) void batch_readout_kernel(const InstDesc* __restrict__ inst,
                                                                const Item* __restrict__ items,
                                                                int n_items, int parity,
                                                                float* beliefs, int* labels) {
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const Item item = items[it];
-        const InstDesc* d = inst + item.inst;
-        switch (d->arm / 3) {  // three arms per group size
-            case 0: batch_readout_item<4>(d, item, parity, beliefs, labels); break;
-            case 1: batch_readout_item<8>(d, item, parity, beliefs, labels); break;
-            case 2: batch_readout_item<16>(d, item, parity, beliefs, labels); break;
-            case 3: batch_readout_item<32>(d, item, parity, beliefs, labels); break;
-            default: batch_readout_item<64>(d, item, parity, beliefs, labels); break;
-        }
+        batch_readout_item<G>(inst + item.inst, item, parity, beliefs, labels);
     }
 }
 
