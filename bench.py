@@ -46,6 +46,20 @@ KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update_stereo480x640.json")
 
 
+def sparse_kernel_name(M, T, mode):
+    """Template instance of the sparse update that runs (M, T): lanes per pixel
+    G is the smallest power of two >= ceil(M/4) in [4, 64]; the window width is
+    the smallest compiled half-width >= T."""
+    G = 4
+    while G * 4 < M and G < 64:
+        G *= 2
+    tws = (0, 1, 2, 3, 4, 6, 8, 12) + (() if G == 4 else (16,))
+    tw = next((t for t in tws if t >= T), None)
+    if tw is None:
+        return f"sparse_update_wide_kernel<{G}, {mode}>"
+    return f"sparse_update_kernel<{G}, {tw}, {mode}>"
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (each scaled by the same counter on a plain
@@ -262,7 +276,7 @@ def main():
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                "kernel": "sparse_update_kernel<LPL=4,K=1,sum>",
+                "kernel": sparse_kernel_name(cfg.M, cfg.T, 0),
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3}
     log(f"bench: sparse sum launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
