@@ -24,6 +24,10 @@ Message forms (all exact, they must agree up to rounding):
   split  : Eq. 6 (sum) and Eq. 10 (max)
   sparse : Eq. 7 (sum) and Eq. 11 (max), O(mM) -- the paper's trick
 
+Schedules: synchronous (every message from the previous state), the
+checkerboard of [2] (Sec. 2), and the directional sweeps of Sec. 6 (one
+sweep = passes in the left, right, up and down directions).
+
 Max-product is taken in the product domain: u(y) = max_x F(x, y) h(x), the
 exponential of the log-domain max-sum of Eq. 9-11 with f and fbar read as
 potentials.  Every message is normalised to sum 1 right after it is computed
@@ -43,7 +47,7 @@ OPPOSITE = {LEFT: RIGHT, RIGHT: LEFT, UP: DOWN, DOWN: UP}
 DIRS = (LEFT, RIGHT, UP, DOWN)
 
 SUM, MAX = "sum", "max"
-SYNC, CHECKERBOARD = "sync", "checkerboard"
+SYNC, CHECKERBOARD, SWEEP = "sync", "checkerboard", "sweep"
 DENSE, SPLIT, SPARSE = "dense", "split", "sparse"
 
 
@@ -284,11 +288,58 @@ def checkerboard_pass(g, inbox, pot, mode, t, impl=SPARSE):
     return deliver(inbox, compute_messages(g, inbox, pot, mode, impl), colour_mask(H, W, t))
 
 
+# Directions of the four passes of one sweep (Sec. 6): messages travelling
+# left, then right, then up, then down.
+SWEEP_ORDER = (LEFT, RIGHT, UP, DOWN)
+
+
+def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE):
+    """One directional pass of the sweep schedule (Sec. 6): every message sent
+    towards direction o, computed in scan order along o, in place.
+
+    Scanlines (rows for left/right, columns for up/down) are independent;
+    along a scanline the senders are visited from the far end towards o, so
+    each message uses the one its sender has just received from the opposite
+    side in the same pass.  Returns a new state.
+    """
+    g = np.asarray(g, dtype=np.float64)
+    H, W, _ = g.shape
+    has = has_neighbor(H, W)
+    form = MESSAGE_FORMS[(mode, impl)]
+    potential = oriented_potential(pot, o)
+    k = OPPOSITE[o]
+    dr, dc = OFFSETS[o]
+    state = np.array(inbox, dtype=np.float64)
+    if dc != 0:
+        senders = range(0, W - 1) if dc > 0 else range(W - 1, 0, -1)
+        line = lambda s: (slice(None), s)            # column s, every row
+    else:
+        senders = range(0, H - 1) if dr > 0 else range(H - 1, 0, -1)
+        line = lambda s: (s, slice(None))            # row s, every column
+    for s in senders:
+        src = line(s)
+        h = g[src].copy()
+        for j in DIRS:
+            if j != o:
+                h = h * np.where(has[j][src][..., None], state[j][src], 1.0)
+        msg = normalize(form(h, potential))
+        dst = line(s + (dc if dc != 0 else dr))
+        state[k][dst] = msg
+    return state
+
+
+def sweep(g, inbox, pot, mode, impl=SPARSE):
+    """One sweep: the four directional passes in SWEEP_ORDER."""
+    for o in SWEEP_ORDER:
+        inbox = sweep_pass(g, inbox, pot, mode, o, impl)
+    return inbox
+
+
 def run(g, pot, mode=SUM, n_iters=10, schedule=SYNC, impl=SPARSE, inbox=None,
         record=False):
     """Run BP from uniform messages (or `inbox`); returns the final state
     (and the list of all states when record=True).  For the checkerboard
-    schedule n_iters counts passes."""
+    schedule n_iters counts passes, for the sweep schedule whole sweeps."""
     g = np.asarray(g, dtype=np.float64)
     H, W, M = g.shape
     assert pot.M == M
@@ -299,6 +350,8 @@ def run(g, pot, mode=SUM, n_iters=10, schedule=SYNC, impl=SPARSE, inbox=None,
             state = sync_step(g, state, pot, mode, impl)
         elif schedule == CHECKERBOARD:
             state = checkerboard_pass(g, state, pot, mode, t, impl)
+        elif schedule == SWEEP:
+            state = sweep(g, state, pot, mode, impl)
         else:
             raise ValueError(schedule)
         if record:
