@@ -65,8 +65,14 @@ enum bp_mode { BP_SUM_PRODUCT = 0, BP_MAX_PRODUCT = 1 };
 
 enum bp_schedule {
     BP_SCHED_SYNC = 0,        /* Jacobi: every message from the previous state */
-    BP_SCHED_CHECKERBOARD = 1 /* bipartite: pass t updates messages sent by
-                                 pixels with (row + col) % 2 == t % 2, in place */
+    BP_SCHED_CHECKERBOARD = 1, /* bipartite: pass t updates messages sent by
+                                  pixels with (row + col) % 2 == t % 2, in place */
+    BP_SCHED_SWEEP = 2         /* directional sweeps (Sec. 6): one sweep is four
+                                  in-place passes, messages travelling left,
+                                  right, up, then down; each pass walks every
+                                  row (left/right) or column (up/down) from
+                                  its far end, each message using the one its
+                                  sender has just received in the same pass */
 };
 
 #define BP_MAX_LABELS 256     /* largest M this library accepts */
@@ -115,15 +121,18 @@ int bp_reset_messages(bp_grid* grid);
 /* Run n_iters >= 0 iterations of the O(mM) update (Eq. 7 for sum-product,
  * Eq. 11 for max-product) with the given schedule.  For the checkerboard
  * schedule n_iters counts passes (two passes update every message once) and
- * the pass parity continues across calls until the next reset.
+ * the pass parity continues across calls until the next reset; for the sweep
+ * schedule it counts whole sweeps (each updates every message once).
  * Max-product requires f >= fbar on every compatible pair (Sec. 5: Eq. 11
  * equals Eq. 9 only then), i.e. fbar <= f(T) as rounded to float32;
  * otherwise BP_EUNSUPPORTED.  Sum-product accepts any fbar >= 0. */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
 /* Same contract as bp_iterate, but each message is the plain O(M^2) sum or
- * max over all sender labels (Eq. 2 / Eq. 9) with the same float32 potential
- * table.  The comparison point for the sparse update; requires M <= 128. */
+ * max over all sender labels (Eq. 2 / Eq. 9) with the same potential table.
+ * The comparison point for the sparse update (Sec. 6 compares the two under
+ * the sweep schedule); requires M <= 128 and the table to fit the device's
+ * LDS (else BP_EUNSUPPORTED). */
 int bp_iterate_dense(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
 /* Beliefs (Eq. 3) from the current messages into out_dev (device,

@@ -186,6 +186,18 @@ def normalize(u):
     return u / u.sum(axis=-1, keepdims=True)
 
 
+def stored(msg, storage=None):
+    """A message as it is kept in the state.
+
+    storage=None keeps FP64.  storage=numpy.float32 models a state held in
+    float32: each message is computed in FP64 from the stored (float32)
+    values and rounded once to float32 when it is stored.  This is a model of
+    a storage format, not of the method: it measures how far the format
+    alone moves BP from the FP64 result.
+    """
+    return msg if storage is None else np.asarray(msg, dtype=storage).astype(np.float64)
+
+
 # --------------------------------------------------------------------------
 # Grid bookkeeping
 # --------------------------------------------------------------------------
@@ -235,7 +247,7 @@ def h_vector(g, inbox, has, o):
     return h
 
 
-def compute_messages(g, inbox, pot, mode, impl):
+def compute_messages(g, inbox, pot, mode, impl, storage=None):
     """All new outgoing messages from the current state: out[o] is [H, W, M],
     the normalised message each pixel sends to its neighbour in direction o."""
     H, W, _ = g.shape
@@ -244,7 +256,7 @@ def compute_messages(g, inbox, pot, mode, impl):
     out = {}
     for o in DIRS:
         h = h_vector(g, inbox, has, o)
-        out[o] = normalize(form(h, oriented_potential(pot, o)))
+        out[o] = stored(normalize(form(h, oriented_potential(pot, o))), storage)
     return out
 
 
@@ -269,9 +281,9 @@ def deliver(inbox, out, sender_mask=None):
     return new
 
 
-def sync_step(g, inbox, pot, mode, impl=SPARSE):
+def sync_step(g, inbox, pot, mode, impl=SPARSE, storage=None):
     """One synchronous (Jacobi) iteration: every message from the previous state."""
-    return deliver(inbox, compute_messages(g, inbox, pot, mode, impl))
+    return deliver(inbox, compute_messages(g, inbox, pot, mode, impl, storage))
 
 
 def colour_mask(H, W, t):
@@ -280,12 +292,12 @@ def colour_mask(H, W, t):
     return (r + c) % 2 == t % 2
 
 
-def checkerboard_pass(g, inbox, pot, mode, t, impl=SPARSE):
+def checkerboard_pass(g, inbox, pot, mode, t, impl=SPARSE, storage=None):
     """Pass t of the bipartite schedule (Sec. 2, [2]): only pixels of colour
     t mod 2 send, using the current state; their receivers are all of the
     other colour, so the pass reads and writes disjoint slots."""
     H, W, _ = g.shape
-    return deliver(inbox, compute_messages(g, inbox, pot, mode, impl), colour_mask(H, W, t))
+    return deliver(inbox, compute_messages(g, inbox, pot, mode, impl, storage), colour_mask(H, W, t))
 
 
 # Directions of the four passes of one sweep (Sec. 6): messages travelling
@@ -293,7 +305,7 @@ def checkerboard_pass(g, inbox, pot, mode, t, impl=SPARSE):
 SWEEP_ORDER = (LEFT, RIGHT, UP, DOWN)
 
 
-def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE):
+def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE, storage=None):
     """One directional pass of the sweep schedule (Sec. 6): every message sent
     towards direction o, computed in scan order along o, in place.
 
@@ -322,36 +334,37 @@ def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE):
         for j in DIRS:
             if j != o:
                 h = h * np.where(has[j][src][..., None], state[j][src], 1.0)
-        msg = normalize(form(h, potential))
+        msg = stored(normalize(form(h, potential)), storage)
         dst = line(s + (dc if dc != 0 else dr))
         state[k][dst] = msg
     return state
 
 
-def sweep(g, inbox, pot, mode, impl=SPARSE):
+def sweep(g, inbox, pot, mode, impl=SPARSE, storage=None):
     """One sweep: the four directional passes in SWEEP_ORDER."""
     for o in SWEEP_ORDER:
-        inbox = sweep_pass(g, inbox, pot, mode, o, impl)
+        inbox = sweep_pass(g, inbox, pot, mode, o, impl, storage)
     return inbox
 
 
 def run(g, pot, mode=SUM, n_iters=10, schedule=SYNC, impl=SPARSE, inbox=None,
-        record=False):
+        record=False, storage=None):
     """Run BP from uniform messages (or `inbox`); returns the final state
     (and the list of all states when record=True).  For the checkerboard
-    schedule n_iters counts passes, for the sweep schedule whole sweeps."""
+    schedule n_iters counts passes, for the sweep schedule whole sweeps.
+    storage: see `stored` (the uniform start is rounded the same way)."""
     g = np.asarray(g, dtype=np.float64)
     H, W, M = g.shape
     assert pot.M == M
-    state = init_messages(H, W, M) if inbox is None else np.array(inbox, dtype=np.float64)
+    state = stored(init_messages(H, W, M), storage) if inbox is None else np.array(inbox, dtype=np.float64)
     states = [state]
     for t in range(n_iters):
         if schedule == SYNC:
-            state = sync_step(g, state, pot, mode, impl)
+            state = sync_step(g, state, pot, mode, impl, storage)
         elif schedule == CHECKERBOARD:
-            state = checkerboard_pass(g, state, pot, mode, t, impl)
+            state = checkerboard_pass(g, state, pot, mode, t, impl, storage)
         elif schedule == SWEEP:
-            state = sweep(g, state, pot, mode, impl)
+            state = sweep(g, state, pot, mode, impl, storage)
         else:
             raise ValueError(schedule)
         if record:

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(PKG_DIR), "include", "bp.h")
 
 BP_OK, BP_EINVAL, BP_ESTATE, BP_ENOMEM, BP_EHIP, BP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 BP_SUM_PRODUCT, BP_MAX_PRODUCT = 0, 1
-BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD = 0, 1
+BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD, BP_SCHED_SWEEP = 0, 1, 2
 BP_MAX_LABELS = 256
 BP_FBAR_TIED = -1.0
 

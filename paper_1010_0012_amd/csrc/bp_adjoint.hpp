@@ -108,6 +108,8 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
     load_pixel_at(a.g, a.m, a.N, a.M, px, x0, full, in);
     float h[4][kLpl];
     make_h(in, h);
+    double hd[4][kLpl];  // the forward update's h, for the recompute of u
+    make_h_d(in, hd);
     float eta[4][kLpl];
     float alpha_pix = 0.0f;
 #pragma unroll
@@ -123,10 +125,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
         }
         // forward recompute: u (Eq. 7), Z, m, accumulated in double as in the
         // forward update
-        double sd = ((double)h[o][0] + (double)h[o][1]) + ((double)h[o][2] + (double)h[o][3]);
+        double sd = (hd[o][0] + hd[o][1]) + (hd[o][2] + hd[o][3]);
         sd = group_sum_d<G>(sd);
         double ud[kLpl];
-        window_sum_d<G, TW>(h[o], a.wd, a.fbar_d * sd, pos, ud);
+        window_sum_d<G, TW>(hd[o], a.wd, a.fbar_d * sd, pos, ud);
         double zd = 0.0;
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) {

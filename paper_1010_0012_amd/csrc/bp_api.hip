@@ -89,14 +89,14 @@ int with_device(const bp_grid* G) {
     return e == hipSuccess ? BP_OK : hip_fail(e, "hipSetDevice");
 }
 
-// One sweep-worth of launches: n synchronous iterations (ping-pong) or n
-// checkerboard passes (in place) of the sparse or dense update.
+// n synchronous iterations (ping-pong), n checkerboard passes or n
+// directional sweeps (both in place) of the sparse or dense update.
 int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     int st = check_ready(G);
     if (st) return st;
     invalidate_grad(G);
     if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
-    if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD)
+    if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD && schedule != BP_SCHED_SWEEP)
         return fail(BP_EINVAL, "bad schedule %d", schedule);
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
     if (mode == BP_MAX_PRODUCT && !max_product_ok(G))
@@ -107,7 +107,9 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         int max_lds = 0;
         hipError_t e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, G->dev);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-        const size_t need = bpk::dense_lds_need(G->M, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax);
+        const int km = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+        const size_t need = schedule == BP_SCHED_SWEEP ? bpk::sweep_dense_lds_need(G->M, km)
+                                                       : bpk::dense_lds_need(G->M, km);
         if (need > (size_t)max_lds)
             return fail(BP_EUNSUPPORTED, "dense kernel needs %zu bytes of LDS per workgroup, device allows %d",
                         need, max_lds);
@@ -116,6 +118,20 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
     // sparse sum uses w(d) = f(d) - fbar; sparse max and dense use f(d)
     const float* tab = (!dense && kmode == bpk::kSum) ? G->tab_w : G->tab_f;
+    if (schedule == BP_SCHED_SWEEP) {
+        // one sweep = passes with messages travelling left, right, up, down
+        static const int kOrder[4] = {bpk::kLeft, bpk::kRight, bpk::kUp, bpk::kDown};
+        for (int t = 0; t < n; ++t) {
+            for (int dir : kOrder) {
+                UpdateArgs a = base_args(G, G->msg[G->cur], G->msg[G->cur], -1);
+                a.dir = dir;
+                memcpy(a.tab, tab, sizeof a.tab);
+                hipError_t e = bpk::launch_sweep(a, kmode, dense, G->stream);
+                if (e != hipSuccess) return hip_fail(e, "sweep pass launch");
+            }
+        }
+        return BP_OK;
+    }
     for (int t = 0; t < n; ++t) {
         UpdateArgs a;
         if (schedule == BP_SCHED_SYNC) {

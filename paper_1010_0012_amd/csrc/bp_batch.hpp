@@ -63,18 +63,14 @@ __device__ __forceinline__ void batch_item(const InstDesc* __restrict__ d, const
         if (!px.ok) continue;  // whole groups only
         PixelInputs pin;
         load_pixel_ptr(d->g, in, plane, M, px, x0, full, pin);
-        float h[4][kLpl];
-        make_h(pin, h);
+        double h[4][kLpl];
+        make_h_d(pin, h);
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             float u[kLpl];
-            if constexpr (MODE == kSum) {
-                sum_message_d<G, TW>(h[o], d->tab_wd, d->fbar_d, pos, M, x0, full, u);
-                store_message(out, plane, M, W, px, o, x0, full, u);
-            } else {
-                sparse_message<G, TW, MODE>(h[o], tab, fbar, pos, u);
-                normalise_store_ptr<G>(out, plane, M, W, px, o, x0, full, u);
-            }
+            if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], d->tab_wd, d->fbar_d, pos, M, x0, full, u);
+            else max_message_d<G, TW>(h[o], tab, fbar, pos, M, x0, full, u);
+            store_message(out, plane, M, W, px, o, x0, full, u);
         }
     }
 }

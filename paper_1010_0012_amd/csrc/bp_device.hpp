@@ -63,6 +63,7 @@ struct UpdateArgs {
     int half_w;            // (W + 1) / 2, checkerboard slot mapping
     int n_slots;           // pixels (or checkerboard slots) covered by the launch
     int T;                 // truncation (used by the runtime-window kernels)
+    int dir;               // sweep pass: direction the messages travel (kLeft .. kDown)
     float fbar;            // potential outside the window (float32, max-product)
     float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)
     // Sum-product works in double end to end: the potential in double and
@@ -167,6 +168,17 @@ __device__ __forceinline__ double group_sum_d(double v) {
     return v;
 }
 
+template <int G>
+__device__ __forceinline__ double group_max_d(double v) {
+    v = fmax(v, dpp_d<kQuad1032>(v));
+    v = fmax(v, dpp_d<kQuad2301>(v));
+    if constexpr (G >= 8) v = fmax(v, dpp_d<kRowHalfMirror>(v));
+    if constexpr (G >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
+    if constexpr (G >= 32) v = fmax(v, xor16_d(v));
+    if constexpr (G >= 64) v = fmax(v, xor32_d(v));
+    return v;
+}
+
 // (value, index) tournament over the group: larger value wins, the lower
 // index breaks ties; the result is the same on every lane.
 template <int G>
@@ -207,6 +219,32 @@ template <int G>
 __device__ __forceinline__ float upper1(float v, int pos) {
     const float t = dpp<kWaveShl1>(v);
     return pos == G - 1 ? 0.0f : t;
+}
+
+// The same shifts for doubles (both halves move together).
+template <int G, int J>
+__device__ __forceinline__ double from_lower_d(double v, int pos) {
+    static_assert(G <= 16, "wide groups shift one lane at a time");
+    const double t = dpp_d<row_shr(J)>(v);
+    if constexpr (G == 16) return t;
+    else return pos < J ? 0.0 : t;
+}
+template <int G, int J>
+__device__ __forceinline__ double from_upper_d(double v, int pos) {
+    static_assert(G <= 16, "wide groups shift one lane at a time");
+    const double t = dpp_d<row_shl(J)>(v);
+    if constexpr (G == 16) return t;
+    else return pos >= G - J ? 0.0 : t;
+}
+template <int G>
+__device__ __forceinline__ double lower1_d(double v, int pos) {
+    const double t = dpp_d<kWaveShr1>(v);
+    return pos == 0 ? 0.0 : t;
+}
+template <int G>
+__device__ __forceinline__ double upper1_d(double v, int pos) {
+    const double t = dpp_d<kWaveShl1>(v);
+    return pos == G - 1 ? 0.0 : t;
 }
 
 // ------------------------------------------------------- label vectors ----
@@ -361,6 +399,22 @@ __device__ __forceinline__ void make_h(const PixelInputs& in, float (&h)[4][kLpl
     }
 }
 
+// make_h in double (the max-product path): g * m is exact in double, so h
+// carries at most two double roundings and every max-product message is its
+// exact value rounded once to float32 at the store.
+__device__ __forceinline__ void make_h_d(const PixelInputs& in, double (&h)[4][kLpl]) {
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        const double g = in.g[i];
+        const double gud = (g * in.m[kUp][i]) * in.m[kDown][i];
+        const double glr = (g * in.m[kLeft][i]) * in.m[kRight][i];
+        h[kLeft][i] = gud * in.m[kRight][i];
+        h[kRight][i] = gud * in.m[kLeft][i];
+        h[kUp][i] = glr * in.m[kDown][i];
+        h[kDown][i] = glr * in.m[kUp][i];
+    }
+}
+
 // Eq. 3 before normalisation, in the order every readout uses.
 __device__ __forceinline__ void make_belief(const PixelInputs& in, float (&b)[kLpl]) {
 #pragma unroll
@@ -386,7 +440,7 @@ __device__ __forceinline__ double recip_d(double z) {
     return r;
 }
 
-// Sum-product normalisation (Sec. 3) in double: Z = sum of u over the
+// Normalisation (Sec. 3) in double, both modes: Z = sum of u over the
 // group, one reciprocal per message, m = u / Z rounded once to float.
 template <int G>
 __device__ __forceinline__ void normalise_d(double (&u)[kLpl], int M, int x0, bool full, float (&m)[kLpl]) {
@@ -400,34 +454,6 @@ __device__ __forceinline__ void normalise_d(double (&u)[kLpl], int M, int x0, bo
     const double inv = recip_d(z);
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) m[i] = (float)(u[i] * inv);
-}
-
-// Normalise u (Sec. 3: explicit normalisation after each update) with one
-// IEEE division per message, then store into the receiver's inbox slot.
-template <int G>
-__device__ __forceinline__ void normalise_store_ptr(float* out, size_t plane, int M, int W,
-                                                    const Pixel& px, int dir, int x0, bool full,
-                                                    float (&u)[kLpl]) {
-    float z = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i) {
-        if (!full && x0 + i >= M) u[i] = 0.0f;
-        z += u[i];
-    }
-    z = group_sum<G>(z);
-    const float inv = 1.0f / z;
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i) u[i] *= inv;
-    if (px.ok && px.has[dir]) {
-        const int q = neighbour(px, dir, W);
-        store_labels<kMsgNT>(out + opposite(dir) * plane + (size_t)q * M, x0, M, full, u);
-    }
-}
-
-template <int G>
-__device__ __forceinline__ void normalise_store(const UpdateArgs& a, const Pixel& px, int dir,
-                                                int x0, bool full, float (&u)[kLpl]) {
-    normalise_store_ptr<G>(a.out, (size_t)a.N * a.M, a.M, a.W, px, dir, x0, full, u);
 }
 
 }  // namespace bpk

@@ -76,31 +76,51 @@ __device__ __forceinline__ void window_apply(const float (&v)[kLpl], const float
     }
 }
 
+// fill_window for double label vectors.
+template <int G, int K, int J>
+__device__ __forceinline__ void fill_window_d(const double (&h)[kLpl], double (&win)[(2 * K + 1) * kLpl],
+                                              int pos, double (&lo)[kLpl], double (&hi)[kLpl]) {
+    if constexpr (J <= K) {
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) {
+            if constexpr (G <= 16) {
+                lo[i] = from_lower_d<G, J>(h[i], pos);
+                hi[i] = from_upper_d<G, J>(h[i], pos);
+            } else {
+                lo[i] = lower1_d<G>(lo[i], pos);
+                hi[i] = upper1_d<G>(hi[i], pos);
+            }
+            win[(K - J) * kLpl + i] = lo[i];
+            win[(K + J) * kLpl + i] = hi[i];
+        }
+        fill_window_d<G, K, J + 1>(h, win, pos, lo, hi);
+    }
+}
+
 // Sum-product window in double: u[i] = base + sum_{|d| <= TW} dtab[|d|] *
-// v(y_i + d), with the double weights and float32 h converted exactly to
-// double, so the only roundings are the double FMAs.  On ill-conditioned
-// loopy grids float32 weights or a float32 accumulation both showed belief
-// errors near 1e-5 after 30 iterations; double weights and accumulation
-// stay near 1e-6.
+// v(y_i + d) with double weights and double h, so the only roundings are the
+// double FMAs.  (A float32 h, or float32 weights or accumulation, lose
+// relative precision where messages are tiny -- fbar = 0 drives entries to
+// zero -- and on ill-conditioned loopy grids.)
 template <int G, int TW>
-__device__ __forceinline__ void window_sum_d(const float (&v)[kLpl], const double* dtab, double base,
+__device__ __forceinline__ void window_sum_d(const double (&v)[kLpl], const double* dtab, double base,
                                              int pos, double (&u)[kLpl]) {
     constexpr int K = window_k<TW>();
     static_assert(K < G, "window wider than the pixel group");
     constexpr int NW = (2 * K + 1) * kLpl;
-    float win[NW];
-    float lo[kLpl], hi[kLpl];
+    double win[NW];
+    double lo[kLpl], hi[kLpl];
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) {
         win[K * kLpl + i] = v[i];
         lo[i] = hi[i] = v[i];
     }
-    fill_window<G, K, 1>(v, win, pos, lo, hi);
+    fill_window_d<G, K, 1>(v, win, pos, lo, hi);
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) {
         double acc = base;
 #pragma unroll
-        for (int d = -TW; d <= TW; ++d) acc = fma(dtab[d < 0 ? -d : d], (double)win[K * kLpl + i + d], acc);
+        for (int d = -TW; d <= TW; ++d) acc = fma(dtab[d < 0 ? -d : d], win[K * kLpl + i + d], acc);
         u[i] = acc;
     }
 }
@@ -108,12 +128,53 @@ __device__ __forceinline__ void window_sum_d(const float (&v)[kLpl], const doubl
 // One sum-product message (Eq. 7) in double: S = sum h once per message,
 // the window, Z and the normalisation in double, m rounded once to float.
 template <int G, int TW>
-__device__ __forceinline__ void sum_message_d(const float (&h)[kLpl], const double* dtab, double fbar, int pos,
+__device__ __forceinline__ void sum_message_d(const double (&h)[kLpl], const double* dtab, double fbar, int pos,
                                               int M, int x0, bool full, float (&m)[kLpl]) {
-    double s = ((double)h[0] + (double)h[1]) + ((double)h[2] + (double)h[3]);
+    double s = (h[0] + h[1]) + (h[2] + h[3]);
     s = group_sum_d<G>(s);
     double u[kLpl];
     window_sum_d<G, TW>(h, dtab, fbar * s, pos, u);
+    normalise_d<G>(u, M, x0, full, m);
+}
+
+// Max-product window in double: u[i] = max(base, max_{|d| <= TW} tab[|d|] *
+// v(y_i + d)), each product of the float32 f(d) and the double h rounded
+// once in double.
+template <int G, int TW>
+__device__ __forceinline__ void window_max_d(const double (&v)[kLpl], const float* tab, double base,
+                                             int pos, double (&u)[kLpl]) {
+    constexpr int K = window_k<TW>();
+    static_assert(K < G, "window wider than the pixel group");
+    constexpr int NW = (2 * K + 1) * kLpl;
+    double win[NW];
+    double lo[kLpl], hi[kLpl];
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        win[K * kLpl + i] = v[i];
+        lo[i] = hi[i] = v[i];
+    }
+    fill_window_d<G, K, 1>(v, win, pos, lo, hi);
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        double acc = base;
+#pragma unroll
+        for (int d = -TW; d <= TW; ++d) acc = fmax(acc, (double)tab[d < 0 ? -d : d] * win[K * kLpl + i + d]);
+        u[i] = acc;
+    }
+}
+
+// One max-product message (Eq. 11) in double: Hm = max h once per message,
+// the window, Z and the normalisation in double, m rounded once to float.
+// The max of exact-to-rounding products equals Eq. 9's max bit for bit when
+// f >= fbar (rounding is monotone), so the dense kernel, doing the same in
+// double, returns the same bits.
+template <int G, int TW>
+__device__ __forceinline__ void max_message_d(const double (&h)[kLpl], const float* tab, float fbar, int pos,
+                                              int M, int x0, bool full, float (&m)[kLpl]) {
+    double hm = fmax(fmax(h[0], h[1]), fmax(h[2], h[3]));
+    hm = group_max_d<G>(hm);
+    double u[kLpl];
+    window_max_d<G, TW>(h, tab, (double)fbar * hm, pos, u);
     normalise_d<G>(u, M, x0, full, m);
 }
 
@@ -132,13 +193,6 @@ __device__ __forceinline__ float group_total(const float (&v)[kLpl]) {
     return group_reduce<MODE, G>(s);
 }
 
-template <int G, int TW, int MODE>
-__device__ __forceinline__ void sparse_message(const float (&h)[kLpl], const float* tab, float fbar,
-                                               int pos, float (&u)[kLpl]) {
-    const float s = group_total<G, MODE>(h);  // the once-per-message term
-    window_apply<G, TW, MODE>(h, tab, fbar * s, pos, u);
-}
-
 // Grid-wide update, register window.  One group of G lanes per sending
 // pixel; a wave's load and store instructions cover 64/G consecutive pixels.
 template <int G, int TW, int MODE>
@@ -151,19 +205,15 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
     const bool full = a.M == G * kLpl;
     PixelInputs in;
     load_pixel(a, px, x0, full, in);
-    float h[4][kLpl];
-    make_h(in, h);
     const size_t plane = (size_t)a.N * a.M;
+    double h[4][kLpl];
+    make_h_d(in, h);
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         float u[kLpl];
-        if constexpr (MODE == kSum) {
-            sum_message_d<G, TW>(h[o], a.dtab, a.fbar_d, pos, a.M, x0, full, u);
-            store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
-        } else {
-            sparse_message<G, TW, MODE>(h[o], a.tab, a.fbar, pos, u);
-            normalise_store<G>(a, px, o, x0, full, u);
-        }
+        if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], a.dtab, a.fbar_d, pos, a.M, x0, full, u);
+        else max_message_d<G, TW>(h[o], a.tab, a.fbar, pos, a.M, x0, full, u);
+        store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
     }
 }
 
@@ -172,16 +222,16 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
 // h is staged in LDS per pixel and the compatible states of each y are
 // visited with runtime bounds [max(0, y-T), min(M-1, y+T)].
 constexpr size_t wide_lds_bytes(int G) {
-    return kMaxTab * sizeof(double) + kMaxTab * sizeof(float) + (size_t)(kBlock / G) * G * kLpl * sizeof(float);
+    return kMaxTab * sizeof(double) + kMaxTab * sizeof(float) + (size_t)(kBlock / G) * G * kLpl * sizeof(double);
 }
 
 template <int G, int MODE>
 __global__ __launch_bounds__(kBlock) void sparse_update_wide_kernel(UpdateArgs a) {
-    extern __shared__ double lds_d[];  // dtab[kMaxTab] (sum), tab[kMaxTab] (max), h[kBlock/G][4G]
+    extern __shared__ double lds_d[];  // dtab[kMaxTab] (sum), tab[kMaxTab] (max), h[kBlock/G][4G] (double)
     constexpr int CAP = G * kLpl;
     double* dtab = lds_d;
     float* tab = reinterpret_cast<float*>(lds_d + kMaxTab);
-    float* lds = tab + kMaxTab;
+    double* lds_h = reinterpret_cast<double*>(tab + kMaxTab);
     for (int i = threadIdx.x; i < kMaxTab; i += kBlock) {
         if constexpr (MODE == kSum) dtab[i] = weight_d(a, i);
         else tab[i] = a.tab[i];
@@ -194,83 +244,78 @@ __global__ __launch_bounds__(kBlock) void sparse_update_wide_kernel(UpdateArgs a
     const bool full = a.M == CAP;
     PixelInputs in;
     if (px.ok) load_pixel(a, px, x0, full, in); else dummy_pixel(in);
-    float h[4][kLpl];
-    make_h(in, h);
-    float* hs = lds + grp * CAP;
+    double h[4][kLpl];
+    make_h_d(in, h);
+    double* hs = lds_h + grp * CAP;
     __syncthreads();
 #pragma unroll 1
     for (int o = 0; o < 4; ++o) {
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[o][i];
         __syncthreads();
-        float u[kLpl];
-        if constexpr (MODE == kSum) {
-            // double accumulation, as in the register variants
-            double s = ((double)h[o][0] + (double)h[o][1]) + ((double)h[o][2] + (double)h[o][3]);
-            s = group_sum_d<G>(s);
-            const double base = a.fbar_d * s;
-            double ud[kLpl];
+        // the once-per-message term, then the compatible states of each y
+        const double base = MODE == kSum
+            ? a.fbar_d * group_sum_d<G>((h[o][0] + h[o][1]) + (h[o][2] + h[o][3]))
+            : (double)a.fbar * group_max_d<G>(fmax(fmax(h[o][0], h[o][1]), fmax(h[o][2], h[o][3])));
+        double ud[kLpl];
 #pragma unroll
-            for (int i = 0; i < kLpl; ++i) {
-                const int y = x0 + i;
-                const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                double acc = base;
-                for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], (double)hs[x], acc);
-                ud[i] = acc;
+        for (int i = 0; i < kLpl; ++i) {
+            const int y = x0 + i;
+            const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+            double acc = base;
+            for (int x = lo; x <= hi; ++x) {
+                const int d = x > y ? x - y : y - x;
+                if constexpr (MODE == kSum) acc = fma(dtab[d], hs[x], acc);
+                else acc = fmax(acc, (double)tab[d] * hs[x]);
             }
-            normalise_d<G>(ud, a.M, x0, full, u);
-            __syncthreads();
-            store_message(a.out, (size_t)a.N * a.M, a.M, a.W, px, o, x0, full, u);
-        } else {
-            const float base = a.fbar * group_total<G, MODE>(h[o]);
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) {
-                const int y = x0 + i;
-                const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                float acc = base;
-                for (int x = lo; x <= hi; ++x) acc = fmaxf(acc, tab[x > y ? x - y : y - x] * hs[x]);
-                u[i] = acc;
-            }
-            __syncthreads();
-            normalise_store<G>(a, px, o, x0, full, u);
+            ud[i] = acc;
         }
+        float u[kLpl];
+        normalise_d<G>(ud, a.M, x0, full, u);
+        __syncthreads();
+        store_message(a.out, (size_t)a.N * a.M, a.M, a.W, px, o, x0, full, u);
     }
 }
 
 // ------------------------------------------ dense O(M^2) comparison ----
 // Eq. 2 / Eq. 9 as written: u(y) = sum (or max) over every sender label x of
-// F[x][y] * h(x), with F the full M x M float32 table (f(|x-y|) inside the
-// window, fbar outside) staged in LDS once per workgroup.  h, the
-// normalisation and the store are the same device functions as the sparse
-// kernels, so max-product results match them bit for bit.
+// F[x][y] * h(x), with F the full M x M table (f(|x-y|) inside the window,
+// fbar outside) staged in LDS once per workgroup.  h, the precision, the
+// normalisation and the store are those of the sparse kernels, so
+// max-product results match them bit for bit.
 // Workgroups loop over tiles of kBlock/G pixels to amortise the table.
 // LDS of the dense kernel: sum-product keeps F in double (with a double
-// f(d) table to build it from), max-product in float32; then h staging.
+// f(d) table to build it from), max-product in float32; h in double.
+// Workgroup size: 128 threads for 32-lane groups keeps the M = 128 double
+// table plus h within the 160 KB of LDS.
+constexpr int dense_block(int G) { return G >= 32 ? 128 : kBlock; }
+
 constexpr size_t dense_lds_bytes(int G, int M, int mode) {
-    return mode == kSum
-        ? kMaxTab * sizeof(double) + (size_t)M * G * kLpl * sizeof(double) + (size_t)kBlock * kLpl * 4 * sizeof(float)
-        : (size_t)M * G * kLpl * sizeof(float) + (size_t)kBlock * kLpl * 4 * sizeof(float);
+    const size_t hbytes = (size_t)dense_block(G) * kLpl * 4 * sizeof(double);
+    return mode == kSum ? kMaxTab * sizeof(double) + (size_t)M * G * kLpl * sizeof(double) + hbytes
+                        : (size_t)M * G * kLpl * sizeof(float) + hbytes;
 }
 
 template <int G, int MODE>
-__global__ __launch_bounds__(kBlock) void dense_update_kernel(UpdateArgs a) {
+__global__ __launch_bounds__(dense_block(G)) void dense_update_kernel(UpdateArgs a) {
     extern __shared__ double lds_d[];
     constexpr int CAP = G * kLpl;
-    constexpr int RPB = kBlock / G;
+    constexpr int BLK = dense_block(G);
+    constexpr int RPB = BLK / G;
     double* Fd = lds_d + kMaxTab;                              // sum: F[M][4G] in double
     float* F = reinterpret_cast<float*>(lds_d);                // max: F[M][4G] in float32
-    float* hs = MODE == kSum ? reinterpret_cast<float*>(Fd + a.M * CAP) : F + a.M * CAP;
+    double* hsd = MODE == kSum ? Fd + a.M * CAP : reinterpret_cast<double*>(F + a.M * CAP);
     if constexpr (MODE == kSum) {
         double* fd = lds_d;                                    // f(d) = exp(-alpha d), d <= T
-        for (int d = threadIdx.x; d < kMaxTab; d += kBlock) fd[d] = d <= a.T ? exp(-a.alpha_d * d) : 0.0;
+        for (int d = threadIdx.x; d < kMaxTab; d += BLK) fd[d] = d <= a.T ? exp(-a.alpha_d * d) : 0.0;
         __syncthreads();
-        for (int i = threadIdx.x; i < a.M * CAP; i += kBlock) {
+        for (int i = threadIdx.x; i < a.M * CAP; i += BLK) {
             const int x = i / CAP, y = i - x * CAP;
             const int d = x > y ? x - y : y - x;
             Fd[i] = (y >= a.M) ? 0.0 : (d <= a.T ? fd[d] : a.fbar_d);
         }
     } else {
-        for (int i = threadIdx.x; i < a.M * CAP; i += kBlock) {
+        for (int i = threadIdx.x; i < a.M * CAP; i += BLK) {
             const int x = i / CAP, y = i - x * CAP;
             const int d = x > y ? x - y : y - x;
             F[i] = (y >= a.M) ? 0.0f : (d <= a.T ? a.tab[d] : a.fbar);
@@ -281,64 +326,60 @@ __global__ __launch_bounds__(kBlock) void dense_update_kernel(UpdateArgs a) {
     const int x0 = pos * kLpl;
     const bool full = a.M == CAP;
     const int n_tiles = (a.n_slots + RPB - 1) / RPB;
-    float* hg = hs + grp * CAP * 4;
+    double* hgd = hsd + grp * CAP * 4;
+    const size_t plane = (size_t)a.N * a.M;
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const Pixel px = map_slot(tile * RPB + grp, a);
         PixelInputs in;
         if (px.ok) load_pixel(a, px, x0, full, in); else dummy_pixel(in);
-        float h[4][kLpl];
-        make_h(in, h);
-        __syncthreads();  // previous tile done with hs (and F built on entry)
+        double h[4][kLpl];
+        make_h_d(in, h);
+        __syncthreads();  // previous tile done with h (and F built on entry)
 #pragma unroll
-        for (int i = 0; i < kLpl; ++i)
-            *reinterpret_cast<float4*>(hg + (x0 + i) * 4) = make_float4(h[0][i], h[1][i], h[2][i], h[3][i]);
+        for (int i = 0; i < kLpl; ++i) {
+            *reinterpret_cast<double2*>(hgd + (x0 + i) * 4) = make_double2(h[0][i], h[1][i]);
+            *reinterpret_cast<double2*>(hgd + (x0 + i) * 4 + 2) = make_double2(h[2][i], h[3][i]);
+        }
         __syncthreads();
-        if constexpr (MODE == kSum) {
-            // same precision as the sparse sum-product update: double accumulation
-            double u[4][kLpl];
+        double u[4][kLpl];
 #pragma unroll
-            for (int o = 0; o < 4; ++o)
+        for (int o = 0; o < 4; ++o)
 #pragma unroll
-                for (int i = 0; i < kLpl; ++i) u[o][i] = 0.0;
-            for (int x = 0; x < a.M; ++x) {
-                const float4 hv = *reinterpret_cast<const float4*>(hg + x * 4);
+            for (int i = 0; i < kLpl; ++i) u[o][i] = 0.0;
+        for (int x = 0; x < a.M; ++x) {
+            const double2 h01 = *reinterpret_cast<const double2*>(hgd + x * 4);
+            const double2 h23 = *reinterpret_cast<const double2*>(hgd + x * 4 + 2);
+            double f[kLpl];
+            if constexpr (MODE == kSum) {
                 const double2 f01 = *reinterpret_cast<const double2*>(Fd + x * CAP + x0);
                 const double2 f23 = *reinterpret_cast<const double2*>(Fd + x * CAP + x0 + 2);
-                const double hd[4] = {(double)hv.x, (double)hv.y, (double)hv.z, (double)hv.w};
-                const double fd[kLpl] = {f01.x, f01.y, f23.x, f23.y};
-#pragma unroll
-                for (int i = 0; i < kLpl; ++i)
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) u[o][i] = fma(fd[i], hd[o], u[o][i]);
-            }
-            const size_t plane = (size_t)a.N * a.M;
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                float m[kLpl];
-                normalise_d<G>(u[o], a.M, x0, full, m);
-                store_message(a.out, plane, a.M, a.W, px, o, x0, full, m);
-            }
-        } else {
-            float u[4][kLpl];
-#pragma unroll
-            for (int o = 0; o < 4; ++o)
-#pragma unroll
-                for (int i = 0; i < kLpl; ++i) u[o][i] = 0.0f;
-            for (int x = 0; x < a.M; ++x) {
-                const float4 hv = *reinterpret_cast<const float4*>(hg + x * 4);
+                f[0] = f01.x; f[1] = f01.y; f[2] = f23.x; f[3] = f23.y;
+            } else {
                 const float4 fr = *reinterpret_cast<const float4*>(F + x * CAP + x0);
-                const float f4[kLpl] = {fr.x, fr.y, fr.z, fr.w};
+                f[0] = fr.x; f[1] = fr.y; f[2] = fr.z; f[3] = fr.w;
+            }
 #pragma unroll
-                for (int i = 0; i < kLpl; ++i) {
-                    const float f = f4[i];
-                    u[0][i] = fmaxf(u[0][i], f * hv.x);
-                    u[1][i] = fmaxf(u[1][i], f * hv.y);
-                    u[2][i] = fmaxf(u[2][i], f * hv.z);
-                    u[3][i] = fmaxf(u[3][i], f * hv.w);
+            for (int i = 0; i < kLpl; ++i) {
+                if constexpr (MODE == kSum) {
+                    u[0][i] = fma(f[i], h01.x, u[0][i]);
+                    u[1][i] = fma(f[i], h01.y, u[1][i]);
+                    u[2][i] = fma(f[i], h23.x, u[2][i]);
+                    u[3][i] = fma(f[i], h23.y, u[3][i]);
+                } else {
+                    // the products and the max as in the sparse kernel, so both
+                    // return the same bits
+                    u[0][i] = fmax(u[0][i], f[i] * h01.x);
+                    u[1][i] = fmax(u[1][i], f[i] * h01.y);
+                    u[2][i] = fmax(u[2][i], f[i] * h23.x);
+                    u[3][i] = fmax(u[3][i], f[i] * h23.y);
                 }
             }
+        }
 #pragma unroll
-            for (int o = 0; o < 4; ++o) normalise_store<G>(a, px, o, x0, full, u[o]);
+        for (int o = 0; o < 4; ++o) {
+            float m[kLpl];
+            normalise_d<G>(u[o], a.M, x0, full, m);
+            store_message(a.out, plane, a.M, a.W, px, o, x0, full, m);
         }
     }
 }

@@ -17,6 +17,11 @@ int sparse_variant_tw(int M, int T);
 // LDS bytes one workgroup needs.
 size_t dense_lds_need(int M, int mode);
 hipError_t launch_dense(const UpdateArgs& a, int mode, hipStream_t stream);
+// One directional pass of the sweep schedule (a.dir = direction the messages
+// travel, in place: a.in == a.out), sparse or dense; sweep_dense_lds_need
+// gives the LDS bytes of the dense form (M <= 128).
+hipError_t launch_sweep(const UpdateArgs& a, int mode, bool dense, hipStream_t stream);
+size_t sweep_dense_lds_need(int M, int mode);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

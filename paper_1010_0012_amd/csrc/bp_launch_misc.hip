@@ -20,9 +20,10 @@ hipError_t go_dense(const UpdateArgs& a, hipStream_t s) {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int n_tiles = (a.n_slots + (kBlock / G) - 1) / (kBlock / G);
+    constexpr int BLK = dense_block(G);
+    const int n_tiles = (a.n_slots + (BLK / G) - 1) / (BLK / G);
     const int grid = n_tiles < 4096 ? n_tiles : 4096;
-    hipLaunchKernelGGL((dense_update_kernel<G, MODE>), dim3(grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((dense_update_kernel<G, MODE>), dim3(grid), dim3(BLK), lds, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,186 @@
+// Directional sweep schedule (Sec. 6): one sweep passes messages left, then
+// right, then up, then down across the lattice.  A pass sends every message
+// towards one direction, scanline by scanline (rows for left/right, columns
+// for up/down), visiting the senders of a scanline from its far end so that
+// each message uses the one its sender has just received from the opposite
+// side.  Scanlines are independent; along one the updates are sequential.
+//
+// One group of G lanes walks one scanline.  The message a sender has just
+// sent is exactly the inbox entry the next sender reads from the opposite
+// side, so it stays in registers (the carry) as well as being stored for the
+// later passes and the readout.  The unary and the two perpendicular inbox
+// messages of the next sender do not depend on the carry and are loaded one
+// step ahead.  A pass writes only the inbox plane opposite to its direction
+// and reads only the two perpendicular planes, so it runs in place.
+#pragma once
+
+#include "bp_kernels.hpp"
+
+namespace bpk {
+
+constexpr int kSweepBlock = 64;  // one wave per workgroup: a pass has only H (or W) scanlines
+
+// How a sender's message is computed: register window (the O(mM) update),
+// LDS window with a runtime bound (wide T), or the dense O(M^2) form.
+enum SweepKind { kSweepReg = 0, kSweepLds = 1, kSweepDense = 2 };
+
+// LDS: the potential tables and each group's h (double).
+constexpr size_t sweep_lds_bytes(int G, int M, int mode, int kind) {
+    const size_t hbytes = (size_t)kSweepBlock * kLpl * sizeof(double);
+    return kind == kSweepReg ? 0
+         : kind == kSweepLds ? kMaxTab * sizeof(double) + kMaxTab * sizeof(float) + hbytes
+         : mode == kSum ? kMaxTab * sizeof(double) + (size_t)M * G * kLpl * sizeof(double) + hbytes
+                        : (size_t)M * G * kLpl * sizeof(float) + hbytes;
+}
+
+template <int G, int TW, int MODE, int KIND>
+__global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
+    constexpr int CAP = G * kLpl;
+    constexpr int LPB = kSweepBlock / G;  // scanlines per workgroup
+    extern __shared__ double lds_d[];
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int dir = a.dir;
+    const bool horiz = dir == kLeft || dir == kRight;
+    const bool forward = dir == kRight || dir == kDown;  // senders in increasing index
+    const int n_lines = horiz ? a.H : a.W;
+    const int len = horiz ? a.W : a.H;
+    const int line = blockIdx.x * LPB + grp;
+    const bool live = line < n_lines;  // other groups run on dummy inputs and store nothing
+    const int x0 = pos * kLpl;
+    const bool full = a.M == CAP;
+    const size_t plane = (size_t)a.N * a.M;
+    const int side0 = horiz ? kUp : kLeft;   // h = ((g * m_side0) * m_side1) * carry,
+    const int side1 = horiz ? kDown : kRight;  // the product order of the other updates
+    const bool has0 = line > 0;                       // up (rows) / left (columns) neighbour
+    const bool has1 = line + 1 < (horiz ? a.H : a.W);  // down / right neighbour
+    const int step_q = dir == kLeft ? -1 : dir == kRight ? 1 : dir == kUp ? -a.W : a.W;
+
+    // tables in LDS for the LDS-window and dense forms
+    double* dtab = lds_d;                                    // kSweepLds sum: w(d); dense sum: f(d)
+    float* tab = reinterpret_cast<float*>(lds_d + kMaxTab);  // kSweepLds max: f(d)
+    double* Fd = lds_d + kMaxTab;                            // dense sum: F[M][CAP]
+    float* F = reinterpret_cast<float*>(lds_d);              // dense max: F[M][CAP]
+    double* hs = nullptr;
+    if constexpr (KIND == kSweepLds) {
+        for (int i = threadIdx.x; i < kMaxTab; i += kSweepBlock) {
+            if constexpr (MODE == kSum) dtab[i] = weight_d(a, i);
+            else tab[i] = a.tab[i];
+        }
+        hs = reinterpret_cast<double*>(tab + kMaxTab) + grp * CAP;
+        __syncthreads();
+    } else if constexpr (KIND == kSweepDense) {
+        if constexpr (MODE == kSum) {
+            for (int d = threadIdx.x; d < kMaxTab; d += kSweepBlock) dtab[d] = d <= a.T ? exp(-a.alpha_d * d) : 0.0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < a.M * CAP; i += kSweepBlock) {
+                const int x = i / CAP, y = i - x * CAP;
+                const int d = x > y ? x - y : y - x;
+                Fd[i] = (y >= a.M) ? 0.0 : (d <= a.T ? dtab[d] : a.fbar_d);
+            }
+            hs = Fd + a.M * CAP + grp * CAP;
+        } else {
+            for (int i = threadIdx.x; i < a.M * CAP; i += kSweepBlock) {
+                const int x = i / CAP, y = i - x * CAP;
+                const int d = x > y ? x - y : y - x;
+                F[i] = (y >= a.M) ? 0.0f : (d <= a.T ? a.tab[d] : a.fbar);
+            }
+            hs = reinterpret_cast<double*>(F + a.M * CAP) + grp * CAP;
+        }
+        __syncthreads();
+    }
+
+    auto sender = [&](int t) {  // pixel index of the t-th sender of this scanline
+        const int s = forward ? t : len - 1 - t;
+        return horiz ? line * a.W + s : s * a.W + line;
+    };
+    auto load_raw = [&](int t, float (&gv)[kLpl], float (&m0)[kLpl], float (&m1)[kLpl]) {
+        const size_t off = (size_t)sender(t) * a.M;
+        load_labels<kUnaryNT>(a.g + off, x0, a.M, full, gv, 0.0f);
+        if (has0) load_labels<kMsgNT>(a.in + side0 * plane + off, x0, a.M, full, m0, 1.0f);
+        if (has1) load_labels<kMsgNT>(a.in + side1 * plane + off, x0, a.M, full, m1, 1.0f);
+    };
+
+    const int steps = len - 1;  // the last node of the scanline sends nothing this way
+    float cg[kLpl], c0[kLpl], c1[kLpl], carry[kLpl];
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) cg[i] = c0[i] = c1[i] = carry[i] = 1.0f;  // first sender: no carry
+    if (live && steps > 0) load_raw(0, cg, c0, c1);
+    for (int t = 0; t < steps; ++t) {
+        float ng[kLpl], n0[kLpl], n1[kLpl];
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) ng[i] = n0[i] = n1[i] = 1.0f;
+        if (live && t + 1 < steps) load_raw(t + 1, ng, n0, n1);
+        double h[kLpl];  // Eq. 5, in double as in the other updates
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) h[i] = (((double)cg[i] * c0[i]) * c1[i]) * carry[i];
+        float m[kLpl];
+        if constexpr (KIND == kSweepReg) {
+            if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
+            else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
+            __syncthreads();
+            double u[kLpl];
+            if constexpr (MODE == kSum) {
+                if constexpr (KIND == kSweepLds) {
+                    double s = (h[0] + h[1]) + (h[2] + h[3]);
+                    s = group_sum_d<G>(s);
+                    const double base = a.fbar_d * s;
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) {
+                        const int y = x0 + i;
+                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                        double acc = base;
+                        for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], hs[x], acc);
+                        u[i] = acc;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                    for (int x = 0; x < a.M; ++x) {
+                        const double hx = hs[x];
+#pragma unroll
+                        for (int i = 0; i < kLpl; ++i) u[i] = fma(Fd[x * CAP + x0 + i], hx, u[i]);
+                    }
+                }
+            } else {
+                if constexpr (KIND == kSweepLds) {
+                    const double base = (double)a.fbar * group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) {
+                        const int y = x0 + i;
+                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                        double acc = base;
+                        for (int x = lo; x <= hi; ++x) acc = fmax(acc, (double)tab[x > y ? x - y : y - x] * hs[x]);
+                        u[i] = acc;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                    for (int x = 0; x < a.M; ++x) {
+                        const double hx = hs[x];
+#pragma unroll
+                        for (int i = 0; i < kLpl; ++i) u[i] = fmax(u[i], (double)F[x * CAP + x0 + i] * hx);
+                    }
+                }
+            }
+            normalise_d<G>(u, a.M, x0, full, m);
+            __syncthreads();  // every group done reading hs before the next step writes it
+        }
+        if (live) {
+            const int q = sender(t) + step_q;
+            store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
+        }
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) {
+            carry[i] = m[i];
+            cg[i] = ng[i];
+            c0[i] = n0[i];
+            c1[i] = n1[i];
+        }
+    }
+}
+
+}  // namespace bpk

@@ -13,7 +13,7 @@ import torch
 from . import _lib as L
 
 MODES = {"sum": L.BP_SUM_PRODUCT, "max": L.BP_MAX_PRODUCT}
-SCHEDULES = {"sync": L.BP_SCHED_SYNC, "checkerboard": L.BP_SCHED_CHECKERBOARD}
+SCHEDULES = {"sync": L.BP_SCHED_SYNC, "checkerboard": L.BP_SCHED_CHECKERBOARD, "sweep": L.BP_SCHED_SWEEP}
 
 
 def _as_code(v, table):

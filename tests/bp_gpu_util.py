@@ -38,26 +38,64 @@ def run_gpu(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5,
     return msgs, b, lab
 
 
-def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, impl=gb.SPARSE,
-               init=None):
-    # the C ABI takes alpha and fbar as float32: give the oracle the same model
+def library_potential(M, T, alpha, fbar, mode):
+    """The potential as the C ABI documents holding it: alpha and a given
+    fbar are float32; sum-product uses f(d) = exp(-alpha d) in double and a
+    tied fbar = f(T) in double; max-product uses the float32 table f(d) and
+    fbar = float32 f(T) when tied."""
     alpha = float(np.float32(alpha))
-    fbar = None if fbar is None else float(np.float32(fbar))
-    pot = gb.truncated_linear(M, T, alpha, fbar)
+    pot = gb.truncated_linear(M, T, alpha, None if fbar is None else float(np.float32(fbar)))
+    if mode == "max":
+        f32 = np.float32(np.exp(-alpha * T)) if fbar is None else np.float32(fbar)
+        F = np.where(pot.compat, pot.F.astype(np.float32).astype(np.float64), float(f32))
+        pot = gb.Potential(F, pot.compat, float(f32))
+    return pot
+
+
+def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, impl=gb.SPARSE,
+               init=None, storage=None):
+    pot = library_potential(M, T, alpha, fbar, mode)
     g = g32.astype(np.float64)
     state = gb.run(g, pot, mode, n_iters, schedule, impl,
-                   inbox=None if init is None else init.astype(np.float64))
+                   inbox=None if init is None else init.astype(np.float64), storage=storage)
     b = gb.beliefs(g, state)
     return state, b, gb.map_labels(b)
 
 
-def compare(tag, gpu, ref, belief_tol=BELIEF_TOL, msg_tol=MSG_TOL, check_msgs=True):
+STORAGE_TOL = 1e-6     # GPU vs the oracle's float32-storage model (max-product)
+
+
+def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPARSE, init=None,
+          check_msgs=True):
+    """Compare a GPU result with the FP64 oracle and with the oracle's
+    float32-storage model (FP64 arithmetic, each stored message rounded once
+    to float32), which the GPU's double arithmetic reproduces up to rare
+    one-ulp differences.  Max-product does not contract perturbations, and
+    sum-product with fbar = 0 stores zeros and denormals, so on some
+    instances float32 storage alone moves the result past 1e-5 from FP64;
+    the FP64 bar is then widened by exactly that storage-only deviation
+    (computed by the oracle alone) and the MAP rule applies where the FP64
+    margin exceeds twice it."""
+    ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init)
+    ref32 = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, storage=np.float32)
+    compare(tag + " [f32-storage model]", gpu, ref32, belief_tol=STORAGE_TOL, msg_tol=STORAGE_TOL,
+            check_msgs=check_msgs)
+    H, W, _ = g32.shape
+    has = gb.has_neighbor(H, W)
+    dev_b = float(np.max(np.abs(ref32[1] - ref[1])))
+    dev_m = float(np.max(np.abs(ref32[0] - ref[0])[has])) if has.any() else 0.0
+    compare(tag + f" [FP64; storage-only deviation {dev_b:.1e}]", gpu, ref,
+            belief_tol=max(BELIEF_TOL, dev_b + STORAGE_TOL), msg_tol=max(MSG_TOL, dev_m + STORAGE_TOL),
+            check_msgs=check_msgs, map_margin=max(MAP_MARGIN, 2 * dev_b + STORAGE_TOL))
+
+
+def compare(tag, gpu, ref, belief_tol=BELIEF_TOL, msg_tol=MSG_TOL, check_msgs=True, map_margin=MAP_MARGIN):
     """Assert the GPU result (msgs, beliefs, labels) matches the oracle's."""
     msgs, b, lab = gpu
     state, b_ref, lab_ref = ref
     H, W, M = b_ref.shape
     err_b = float(np.max(np.abs(b - b_ref)))
-    sure = gb.top2_margin(b_ref) > MAP_MARGIN
+    sure = gb.top2_margin(b_ref) > map_margin
     bad = (lab != lab_ref) & sure
     line = f"{tag}: max|db|={err_b:.2e} MAP mismatches={int(bad.sum())}/{int(sure.sum())}"
     if check_msgs and msgs is not None:

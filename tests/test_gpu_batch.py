@@ -8,7 +8,7 @@ weight 0, which add exact zeros) and match the FP64 oracle to the parity bar.
 import numpy as np
 import pytest
 
-from bp_gpu_util import compare, run_gpu, run_oracle, say
+from bp_gpu_util import check, compare, run_gpu, run_oracle, say
 from oracle import grid_bp as gb
 from synth_mrf import make_batch_configs, make_batch_instance, random_unary
 
@@ -57,8 +57,7 @@ def test_small_batch_matches_single_and_oracle(mode):
         _, b1, l1 = run_gpu(g32, M, T, a, f, mode, "sync", n, want_messages=False)
         np.testing.assert_array_equal(bb[j], b1)
         np.testing.assert_array_equal(bl[j], l1)
-        compare(f"batch[{j}] {mode}", (None, bb[j], bl[j]),
-                run_oracle(g32, M, T, a, f, mode, "sync", n), check_msgs=False)
+        check(f"batch[{j}] {mode}", (None, bb[j], bl[j]), g32, M, T, a, f, mode, "sync", n, check_msgs=False)
     batch.close()
 
 

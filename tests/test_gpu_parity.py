@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from bp_gpu_util import compare, run_gpu, run_oracle, say
+from bp_gpu_util import check, compare, run_gpu, run_oracle, say
 from oracle import grid_bp as gb
 from synth_mrf import CONFIGS, make_config, random_unary
 
@@ -61,8 +61,7 @@ def test_sparse_shapes(shape, mode, schedule):
     tag = f"sparse {mode} {schedule} {_id(shape)}"
     say(tag)
     gpu = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n)
-    ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n, gb.SPARSE)
-    compare(tag, gpu, ref)
+    check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n, gb.SPARSE)
 
 
 DENSE_SHAPES = [s for s in SHAPES if s[2] <= 128]
@@ -80,7 +79,7 @@ def test_dense_kernel(shape, mode, schedule):
     tag = f"dense {mode} {schedule} {_id(shape)}"
     say(tag)
     gd = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, dense=True)
-    compare(tag, gd, run_oracle(g32, M, T, alpha, fbar, mode, schedule, n, gb.DENSE))
+    check(tag, gd, g32, M, T, alpha, fbar, mode, schedule, n, gb.DENSE)
     gs = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n)
     if mode == "max":
         np.testing.assert_array_equal(gd[0], gs[0])
@@ -100,8 +99,7 @@ def test_stereo16_full(mode, schedule):
     say(tag)
     gpu = run_gpu(g32, cfg.M, cfg.T, cfg.alpha, None, mode, schedule, n)
     for impl in (gb.SPARSE, gb.DENSE):
-        compare(tag + f" vs oracle-{impl}", gpu,
-                run_oracle(g32, cfg.M, cfg.T, cfg.alpha, None, mode, schedule, n, impl))
+        check(tag + f" vs oracle-{impl}", gpu, g32, cfg.M, cfg.T, cfg.alpha, None, mode, schedule, n, impl)
 
 
 @pytest.mark.parametrize("mode", ["sum", "max"])
