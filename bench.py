@@ -176,6 +176,7 @@ def batch_leg(n_iters=30, reps=3):
     batch = Batch([(g, i.T, i.alpha) for g, i in zip(gs, insts)])
     best_us = batch.autotune("sum", 2)
     plan = batch.get_plan()
+    streams = batch.get_streams()
     updates = sum(2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) * i.M for i in insts) * n_iters
     alg_bytes = sum(4 * i.M * (2 * 2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) + i.H * i.W)
                     for i in insts) * n_iters
@@ -207,13 +208,13 @@ def batch_leg(n_iters=30, reps=3):
         t_single += e0.elapsed_time(e1)
         grid.close()
     log(f"bench: batch32 x{n_iters}: {ms:.2f} ms ({updates / (ms * 1e-3):.4e} updates/s, "
-        f"{alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic), plan {plan}; one grid at a time "
+        f"{alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic), plan {plan}, {streams} streams; one grid at a time "
         f"{t_single:.2f} ms")
     return {"batch_workload": f"32 grids, H,W in [64,512], M in {{16,32,64,128}}, T in [1,8], "
                               f"{n_iters} sum-product iterations, one graph replay",
             "batch_ms": ms, "batch_updates_per_s": updates / (ms * 1e-3),
             "batch_alg_GBs": alg_bytes / (ms * 1e-3) / 1e9,
-            "batch_plan": {"passes": plan[0], "grid_blocks": plan[1], "autotune_best_us": best_us},
+            "batch_plan": {"passes": plan[0], "grid_blocks": plan[1], "streams": streams, "autotune_best_us": best_us},
             "batch_one_grid_at_a_time_ms": t_single}
 
 

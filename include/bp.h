@@ -195,11 +195,16 @@ int bp_destroy(bp_grid* grid);
  * Batches: many independent grid MRFs, each with its own H, W, M, T, alpha,
  * fbar and unary (the Sec. 6 stereo model on images of different sizes and
  * disparity ranges), advanced together by the same synchronous O(mM) update
- * (Eq. 7 / Eq. 11).  Each iteration is one persistent kernel launch that
- * walks a precomputed work queue of (instance, pixel range) items, longest
- * first; the n launches of bp_batch_iterate are captured once into a HIP
- * graph (per mode, n and buffer parity) on a private stream of default
- * priority and replayed on the batch's stream.
+ * (Eq. 7 / Eq. 11).  Instances are grouped by code path (lanes per pixel and
+ * window width) and packed, largest first, into launches of up to 8
+ * instances whose descriptors travel in the kernel arguments; the launches of
+ * different groups touch disjoint instances and their chains of iterations
+ * run concurrently on up to 4 private streams (default priority) forked from
+ * and joined back into the batch's stream.  The n iterations of
+ * bp_batch_iterate are captured once into a HIP graph (per mode, n and
+ * buffer parity) and replayed on the batch's stream.  Results do not depend
+ * on the plan (streams, passes, grid size): bit for bit those of running
+ * each instance alone.
  * Per instance: H, W >= 1; 1 <= M <= BP_MAX_LABELS; 0 <= T <= 8; T < M
  * (else BP_EUNSUPPORTED for T > 8, BP_EINVAL for bad values).
  * Outputs are concatenated in instance order: instance j's beliefs start at
@@ -216,13 +221,11 @@ typedef struct bp_grid_desc {
 int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hip_stream);
 int bp_batch_set_stream(bp_batch* batch, void* hip_stream);
 
-/* Device bytes for the descriptor table, the work queue and every
- * instance's two message buffers. */
+/* Device bytes for every instance's two message buffers. */
 int64_t bp_batch_workspace_bytes(const bp_batch* batch);
 
-/* Attach caller-owned workspace (256-byte aligned), upload descriptors and
- * the work queue, and reset all messages to 1/M.  Blocks until the upload
- * has completed. */
+/* Attach caller-owned workspace (256-byte aligned), build the launch plan
+ * and reset all messages to 1/M (enqueued on the batch's stream). */
 int bp_batch_attach_workspace(bp_batch* batch, void* dev_ptr, int64_t bytes);
 
 int bp_batch_reset_messages(bp_batch* batch);
@@ -236,16 +239,23 @@ int bp_batch_iterate(bp_batch* batch, int32_t mode, int32_t n_iters);
  * replaying captured graphs (results are identical). */
 int bp_batch_set_graphs(bp_batch* batch, int32_t enable);
 
-/* Work plan: passes[c] = passes per work item for instances of lane class c
- * (M <= 16, 32, 64, 128, 256; a pass covers one workgroup's worth of pixels,
- * 256 threads over 4, 8, 16, 32 or 64 lanes per pixel), grid_blocks =
- * persistent workgroups per launch (>= 1; more than the number of items
- * means one item per workgroup).  Rebuilds and uploads the work queue
- * (blocking), keeps the messages, drops captured graphs. */
+/* Work plan: passes[c] = passes per workgroup for instances of lane class c
+ * (M <= 16, 32, 64, 128, 256; a pass covers 256 threads' worth of pixels at
+ * 4, 8, 16, 32 or 64 lanes per pixel), grid_blocks = workgroups per launch
+ * (>= 1; a launch with more pixel ranges than that strides over them; more
+ * workgroups than ranges means one range per workgroup).  Keeps the
+ * messages, drops captured graphs. */
 int bp_batch_set_plan(bp_batch* batch, const int32_t passes[5], int32_t grid_blocks);
 int bp_batch_get_plan(const bp_batch* batch, int32_t passes[5], int32_t* grid_blocks);
 
-/* Time a fixed family of candidate plans (item sizes x grid sizes) for
+/* Plan: run the launch chains on at most n_streams (1..4) streams; 1 runs
+ * every launch in order on the batch's stream.  Keeps the messages, drops
+ * captured graphs.  bp_batch_get_streams returns the current value (or a
+ * negative status). */
+int bp_batch_set_streams(bp_batch* batch, int32_t n_streams);
+int bp_batch_get_streams(const bp_batch* batch);
+
+/* Time a fixed family of candidate plans (streams x passes x grid sizes) for
  * trial_iters >= 1 iterations each on this batch and keep the fastest.
  * Blocks; resets the messages afterwards.  best_us (optional, host) receives
  * the best time per iteration in microseconds. */
@@ -255,7 +265,7 @@ int bp_batch_autotune(bp_batch* batch, int32_t mode, int32_t trial_iters, float*
 int bp_batch_beliefs(bp_batch* batch, float* out_dev);
 int bp_batch_map_labels(bp_batch* batch, int32_t* out_dev);
 
-/* Free the handle and its captured graphs and private stream. */
+/* Free the handle and its captured graphs and private streams. */
 int bp_batch_destroy(bp_batch* batch);
 
 const char* bp_status_string(int status);

@@ -67,6 +67,8 @@ _PROTOS = {
     "bp_batch_set_graphs": (_c_int, [_vp, _c_i32]),
     "bp_batch_set_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), _c_i32]),
     "bp_batch_get_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "bp_batch_set_streams": (_c_int, [_vp, _c_i32]),
+    "bp_batch_get_streams": (_c_int, [_vp]),
     "bp_batch_autotune": (_c_int, [_vp, _c_i32, _c_i32, ctypes.POINTER(_c_f)]),
     "bp_batch_beliefs": (_c_int, [_vp, _vp]),
     "bp_batch_map_labels": (_c_int, [_vp, _vp]),
@@ -258,6 +260,16 @@ def bp_batch_get_plan(handle):
     g = _c_i32()
     _check(lib().bp_batch_get_plan(handle, arr, ctypes.byref(g)), "bp_batch_get_plan")
     return list(arr), g.value
+
+
+def bp_batch_set_streams(handle, n_streams):
+    _check(lib().bp_batch_set_streams(handle, n_streams), "bp_batch_set_streams")
+
+
+def bp_batch_get_streams(handle):
+    r = lib().bp_batch_get_streams(handle)
+    _check(min(r, 0), "bp_batch_get_streams")
+    return r
 
 
 def bp_batch_autotune(handle, mode, trial_iters):

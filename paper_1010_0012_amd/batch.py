@@ -68,6 +68,13 @@ class Batch:
     def get_plan(self):
         return L.bp_batch_get_plan(self.handle)
 
+    def set_streams(self, n_streams):
+        self._sync_stream()
+        L.bp_batch_set_streams(self.handle, n_streams)
+
+    def get_streams(self):
+        return L.bp_batch_get_streams(self.handle)
+
     def autotune(self, mode="sum", trial_iters=3):
         self._sync_stream()
         return L.bp_batch_autotune(self.handle, MODES[mode] if isinstance(mode, str) else int(mode),

@@ -1,5 +1,5 @@
-// Host driver of the batched path: instance descriptors, work queue
-// planning, persistent launches, HIP graph capture and the plan autotuner.
+// Host driver of the batched path: instance descriptors, launch planning,
+// concurrent launch chains, HIP graph capture and the plan autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,16 +28,25 @@ struct bp_batch {
     // plan
     int passes[bpk::kBatchClasses] = {1, 1, 1, 1, 1};
     int grid_blocks = 0;
-    // device memory
+    // device memory: every instance's two message buffers
     char* ws = nullptr;
     int64_t ws_bytes = 0;
-    size_t desc_off = 0, item_off = 0, msg_off = 0, total = 0;
-    size_t max_items = 0;
+    size_t total = 0;
     std::vector<size_t> msg_bytes_off;        // per instance, first of its two buffers
     std::vector<bpk::InstDesc> hdesc;
-    std::vector<bpk::Item> hitems;
-    int class_off[bpk::kBatchClasses] = {};   // items of lane class c: [class_off[c], +class_n[c])
-    int class_n[bpk::kBatchClasses] = {};
+    // launches: one or more per non-empty code path
+    std::vector<bpk::BatchLaunch> launches;
+    std::vector<int> launch_arm;
+    // Launches touch disjoint instances, so each launch's iterations form an
+    // independent chain: the chains run on kSide streams (forked from and
+    // joined back into the caller's stream by events), longest work first.
+    static constexpr int kSide = 4;
+    std::vector<int> launch_stream;
+    int n_side = 0;                      // side streams in use (0: the caller's stream only)
+    int max_streams = kSide;             // plan: launch chains on at most this many streams
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[kSide] = {};
     int parity = 0;
     bool use_graphs = true;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (mode, n, parity)
@@ -53,11 +62,11 @@ int lane_class(int M) {
     return g == 4 ? 0 : g == 8 ? 1 : g == 16 ? 2 : g == 32 ? 3 : 4;
 }
 
-// Smallest compiled code path whose window reaches T (see kArmG/kArmTw).
+// Smallest compiled code path whose window reaches T.
 int pick_arm(int M, int T) {
     const int g = bpk::lanes_for(M);
     for (int a = 0; a < bpk::kBatchArms; ++a)
-        if (bpk::kArmG[a] == g && bpk::kArmTw[a] >= T) return a;
+        if (bpk::arm_g(a) == g && bpk::arm_tw(a) >= T) return a;
     return -1;
 }
 
@@ -66,85 +75,117 @@ void drop_graphs(bp_batch* B) {
     B->graphs.clear();
 }
 
-// Work queue: every instance cut into items of passes*kBlock/G pixels,
-// grouped by lane class (one kernel per class) and, within a class, sorted
-// by bytes moved (pixels * M), longest first, ties by instance then pixel.
-void build_items(bp_batch* B) {
-    std::vector<bpk::Item> per[bpk::kBatchClasses];
-    for (int j = 0; j < B->n; ++j) {
-        const int N = B->desc[j].H * B->desc[j].W;
-        const int c = lane_class(B->desc[j].M);
-        const int P = B->passes[c];
-        const int rpb = bpk::kBlock / bpk::lanes_for(B->desc[j].M);
-        const int chunk = rpb * P;
-        for (int first = 0; first < N; first += chunk) {
-            const int left = N - first;
-            bpk::Item it;
-            it.inst = j;
-            it.first = first;
-            it.passes = std::min(P, (left + rpb - 1) / rpb);
-            it.pad = 0;
-            per[c].push_back(it);
+// Launch plan: the instances of each code path, largest first (bytes moved,
+// pixels * M), packed into launches of up to kLaunchInst; each instance is
+// cut into workgroups of passes * kBlock/G pixels (passes per lane class).
+// The launches are then spread over the side streams, longest first.
+void build_launches(bp_batch* B) {
+    B->launches.clear();
+    B->launch_arm.clear();
+    std::vector<long long> work_of;
+    auto work = [&](int j) { return (long long)B->desc[j].H * B->desc[j].W * B->desc[j].M; };
+    for (int a = 0; a < bpk::kBatchArms; ++a) {
+        std::vector<int> js;
+        for (int j = 0; j < B->n; ++j)
+            if (B->arm[j] == a) js.push_back(j);
+        std::stable_sort(js.begin(), js.end(), [&](int x, int y) { return work(x) > work(y); });
+        for (size_t i0 = 0; i0 < js.size(); i0 += bpk::kLaunchInst) {
+            bpk::BatchLaunch L;
+            memset(&L, 0, sizeof L);
+            const int P = B->passes[lane_class(B->desc[js[i0]].M)];
+            L.passes = P;
+            long long w = 0;
+            int blocks = 0;
+            for (size_t i = i0; i < js.size() && i < i0 + bpk::kLaunchInst; ++i) {
+                const int j = js[i];
+                const int per_block = (bpk::kBlock / bpk::lanes_for(B->desc[j].M)) * P;
+                blocks += (B->desc[j].H * B->desc[j].W + per_block - 1) / per_block;
+                L.blocks_end[L.n_inst] = blocks;
+                L.inst[L.n_inst] = B->hdesc[j];
+                L.n_inst++;
+                w += work(j);
+            }
+            B->launches.push_back(L);
+            B->launch_arm.push_back(a);
+            work_of.push_back(w);
         }
     }
-    B->hitems.clear();
-    for (int c = 0; c < bpk::kBatchClasses; ++c) {
-        std::stable_sort(per[c].begin(), per[c].end(), [&](const bpk::Item& a, const bpk::Item& b) {
-            return (long long)a.passes * B->desc[a.inst].M > (long long)b.passes * B->desc[b.inst].M;
-        });
-        B->class_off[c] = (int)B->hitems.size();
-        B->class_n[c] = (int)per[c].size();
-        B->hitems.insert(B->hitems.end(), per[c].begin(), per[c].end());
+    const int nl = (int)B->launches.size();
+    std::vector<int> order(nl);
+    for (int i = 0; i < nl; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work_of[x] > work_of[y]; });
+    const int ns = std::min(B->max_streams, nl);
+    B->n_side = ns > 1 ? ns : 0;
+    B->launch_stream.assign(nl, 0);
+    long long load[bp_batch::kSide] = {};
+    for (int l : order) {
+        int best = 0;
+        for (int i = 1; i < std::max(1, B->n_side); ++i)
+            if (load[i] < load[best]) best = i;
+        B->launch_stream[l] = best;
+        load[best] += work_of[l];
     }
 }
 
-template <int MODE, int G>
-hipError_t launch_class(const bpk::InstDesc* inst, const bpk::Item* items, int n, unsigned grid, int par,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((bpk::batch_update_kernel<MODE, G>), dim3(grid), dim3(bpk::kBlock), 0, s, inst, items, n,
-                       par);
-    return hipGetLastError();
+// Side streams and events, created on first use (default priority, like
+// every stream this library touches).
+hipError_t ensure_side(bp_batch* B) {
+    if (B->ev_fork) return hipSuccess;
+    hipError_t e = hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming);
+    for (int i = 0; i < bp_batch::kSide && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&B->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->ev_join[i], hipEventDisableTiming);
+    }
+    return e;
 }
 
-template <int MODE>
-hipError_t launch_class_mode(int c, const bpk::InstDesc* inst, const bpk::Item* items, int n, unsigned grid,
-                             int par, hipStream_t s) {
-    switch (c) {
-        case 0: return launch_class<MODE, 4>(inst, items, n, grid, par, s);
-        case 1: return launch_class<MODE, 8>(inst, items, n, grid, par, s);
-        case 2: return launch_class<MODE, 16>(inst, items, n, grid, par, s);
-        case 3: return launch_class<MODE, 32>(inst, items, n, grid, par, s);
-        default: return launch_class<MODE, 64>(inst, items, n, grid, par, s);
+unsigned launch_grid(const bp_batch* B, const bpk::BatchLaunch& L) {
+    return (unsigned)std::max(1, std::min(B->grid_blocks, L.blocks_end[L.n_inst - 1]));
+}
+
+template <int MODE, int A = 0>
+hipError_t launch_arm(int arm, const bpk::BatchLaunch& L, unsigned grid, int par, hipStream_t s) {
+    if constexpr (A < bpk::kBatchArms) {
+        if (arm != A) return launch_arm<MODE, A + 1>(arm, L, grid, par, s);
+        if (L.passes == 1 && (int)grid == L.blocks_end[L.n_inst - 1])
+            hipLaunchKernelGGL((bpk::batch_update_kernel<MODE, bpk::arm_g(A), bpk::arm_tw(A), false>), dim3(grid),
+                               dim3(bpk::kBlock), 0, s, L, par);
+        else
+            hipLaunchKernelGGL((bpk::batch_update_kernel<MODE, bpk::arm_g(A), bpk::arm_tw(A), true>), dim3(grid),
+                               dim3(bpk::kBlock), 0, s, L, par);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
     }
 }
 
-int upload(bp_batch* B) {
-    hipError_t e = hipMemcpyAsync(B->ws + B->item_off, B->hitems.data(), B->hitems.size() * sizeof(bpk::Item),
-                                  hipMemcpyHostToDevice, B->stream);
-    if (e != hipSuccess) return hip_fail(e, "work queue upload");
-    e = hipMemcpyAsync(B->ws + B->desc_off, B->hdesc.data(), B->hdesc.size() * sizeof(bpk::InstDesc),
-                       hipMemcpyHostToDevice, B->stream);
-    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-    // the host vectors are the copy sources: wait before they may change
-    e = hipStreamSynchronize(B->stream);
-    return e == hipSuccess ? BP_OK : hip_fail(e, "upload synchronize");
-}
-
-// One iteration = one persistent launch per non-empty lane class; the
-// classes touch disjoint instances, so their order does not matter.
+// n iterations: per iteration one launch per entry of the plan.  The
+// launches touch disjoint instances, so their chains run concurrently on
+// the side streams, forked from s after the work already queued there and
+// joined back into s.
 hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s) {
-    const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
-    const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
+    hipError_t e = hipSuccess;
+    const bool fork = B->n_side > 1;
+    if (fork) {
+        if ((e = ensure_side(B)) != hipSuccess) return e;
+        if ((e = hipEventRecord(B->ev_fork, s)) != hipSuccess) return e;
+        for (int i = 0; i < B->n_side; ++i)
+            if ((e = hipStreamWaitEvent(B->side[i], B->ev_fork, 0)) != hipSuccess) return e;
+    }
     for (int t = 0; t < n; ++t) {
         const int par = (parity0 + t) & 1;
-        for (int c = 0; c < bpk::kBatchClasses; ++c) {
-            const int cn = B->class_n[c];
-            if (cn == 0) continue;
-            const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, cn));
-            const bpk::Item* ci = items + B->class_off[c];
-            hipError_t e = mode == bpk::kSum ? launch_class_mode<bpk::kSum>(c, inst, ci, cn, grid, par, s)
-                                             : launch_class_mode<bpk::kMax>(c, inst, ci, cn, grid, par, s);
+        for (size_t l = 0; l < B->launches.size(); ++l) {
+            const bpk::BatchLaunch& L = B->launches[l];
+            hipStream_t ls = fork ? B->side[B->launch_stream[l]] : s;
+            e = mode == bpk::kSum ? launch_arm<bpk::kSum>(B->launch_arm[l], L, launch_grid(B, L), par, ls)
+                                  : launch_arm<bpk::kMax>(B->launch_arm[l], L, launch_grid(B, L), par, ls);
             if (e != hipSuccess) return e;
+        }
+    }
+    if (fork) {
+        for (int i = 0; i < B->n_side; ++i) {
+            if ((e = hipEventRecord(B->ev_join[i], B->side[i])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, B->ev_join[i], 0)) != hipSuccess) return e;
         }
     }
     return hipSuccess;
@@ -172,9 +213,6 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    int cus = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
     std::vector<int> arms(n);
     std::vector<float> fbars(n);
     for (int j = 0; j < n; ++j) {
@@ -202,16 +240,8 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
     B->desc.assign(descs, descs + n);
     B->arm = arms;
     B->fbar = fbars;
-    B->grid_blocks = std::max(1, cus) * 8;
-    // layout: descriptors, work queue (sized for one pass per item), messages
-    for (int j = 0; j < n; ++j) {
-        const int rpb = bpk::kBlock / bpk::lanes_for(descs[j].M);
-        B->max_items += (size_t)(descs[j].H * descs[j].W + rpb - 1) / rpb;
-    }
-    B->desc_off = 0;
-    B->item_off = bp_align_up(n * sizeof(bpk::InstDesc), 256);
-    B->msg_off = B->item_off + bp_align_up(B->max_items * sizeof(bpk::Item), 256);
-    size_t off = B->msg_off;
+    B->grid_blocks = 1 << 30;  // one workgroup per pixel range until a plan says otherwise
+    size_t off = 0;
     for (int j = 0; j < n; ++j) {
         B->msg_bytes_off.push_back(off);
         off += 2 * bp_align_up(B->msg_floats(j) * sizeof(float), 256);
@@ -268,8 +298,7 @@ int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
         boff += (long long)h.N * d.M;
         loff += h.N;
     }
-    build_items(B);
-    if ((st = upload(B))) return st;
+    build_launches(B);
     return bp_batch_reset_messages(B);
 }
 
@@ -344,15 +373,26 @@ int bp_batch_set_plan(bp_batch* B, const int32_t passes[5], int32_t grid_blocks)
     if (!passes || grid_blocks < 1) return fail(BP_EINVAL, "bad plan");
     for (int c = 0; c < bpk::kBatchClasses; ++c)
         if (passes[c] < 1 || passes[c] > 4096) return fail(BP_EINVAL, "passes[%d] out of range", c);
-    if ((st = set_device(B))) return st;
-    // the previous queue may still be read by queued launches
-    hipError_t e = hipStreamSynchronize(B->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     drop_graphs(B);
     for (int c = 0; c < bpk::kBatchClasses; ++c) B->passes[c] = passes[c];
     B->grid_blocks = grid_blocks;
-    build_items(B);
-    return upload(B);
+    build_launches(B);
+    return BP_OK;
+}
+
+int bp_batch_set_streams(bp_batch* B, int32_t n_streams) {
+    int st = ready(B);
+    if (st) return st;
+    if (n_streams < 1 || n_streams > bp_batch::kSide) return fail(BP_EINVAL, "n_streams must be in [1, %d]", bp_batch::kSide);
+    drop_graphs(B);
+    B->max_streams = n_streams;
+    build_launches(B);
+    return BP_OK;
+}
+
+int bp_batch_get_streams(const bp_batch* B) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    return B->max_streams;
 }
 
 int bp_batch_get_plan(const bp_batch* B, int32_t passes[5], int32_t* grid_blocks) {
@@ -375,39 +415,45 @@ int bp_batch_autotune(bp_batch* B, int32_t mode, int32_t trial_iters, float* bes
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
-    // Candidates: items of 1/2/4/8 passes (a pass moves about the same bytes
-    // in every lane class), times persistent grid sizes of 2..16 workgroups
-    // per CU, and one item per workgroup (hardware dispatch order).
+    // Candidates: launch chains on one stream or on all side streams, times
+    // workgroups of 1/2/4/8 passes (a pass moves about the same bytes in
+    // every lane class), times persistent grid sizes of 2..16 workgroups per
+    // CU, and one workgroup per pixel range.
+    struct Cand { int streams, scale, grid; };
+    std::vector<Cand> cands;
+    for (int streams : {1, bp_batch::kSide})
+        for (int scale : {1, 2, 4, 8})
+            for (int per_cu : {2, 4, 8, 16, 0})
+                cands.push_back({streams, scale, per_cu ? std::max(1, cus) * per_cu : (1 << 30)});
     float best = 1e30f;
-    int best_passes[bpk::kBatchClasses] = {1, 1, 1, 1, 1}, best_grid = std::max(1, cus) * 8;
-    for (int scale : {1, 2, 4, 8}) {
-        for (int per_cu : {2, 4, 8, 16, 0}) {
-            int32_t pl[bpk::kBatchClasses];
-            for (int c = 0; c < bpk::kBatchClasses; ++c) pl[c] = scale;
-            const int grid_try = per_cu ? std::max(1, cus) * per_cu : (1 << 30);
-            if ((st = bp_batch_set_plan(B, pl, grid_try))) break;
-            e = launch_iters(B, kmode, 1, B->parity, B->stream);  // warm
-            if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
-            if (e == hipSuccess) e = launch_iters(B, kmode, trial_iters, B->parity ^ 1, B->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, B->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { st = hip_fail(e, "autotune trial"); break; }
-            B->parity ^= (trial_iters + 1) & 1;
-            const float us = ms * 1000.0f / trial_iters;
-            if (us < best) {
-                best = us;
-                for (int c = 0; c < bpk::kBatchClasses; ++c) best_passes[c] = pl[c];
-                best_grid = grid_try;
-            }
+    Cand best_c = {bp_batch::kSide, 1, 1 << 30};
+    for (const Cand& c : cands) {
+        int32_t pl[bpk::kBatchClasses];
+        for (int k = 0; k < bpk::kBatchClasses; ++k) pl[k] = c.scale;
+        B->max_streams = c.streams;
+        if ((st = bp_batch_set_plan(B, pl, c.grid))) break;
+        e = launch_iters(B, kmode, 1, B->parity, B->stream);  // warm
+        if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
+        if (e == hipSuccess) e = launch_iters(B, kmode, trial_iters, B->parity ^ 1, B->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, B->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = hip_fail(e, "autotune trial"); break; }
+        B->parity ^= (trial_iters + 1) & 1;
+        const float us = ms * 1000.0f / trial_iters;
+        if (us < best) {
+            best = us;
+            best_c = c;
         }
-        if (st) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) return st;
-    if ((st = bp_batch_set_plan(B, best_passes, best_grid))) return st;
+    B->max_streams = best_c.streams;
+    int32_t best_passes[bpk::kBatchClasses];
+    for (int k = 0; k < bpk::kBatchClasses; ++k) best_passes[k] = best_c.scale;
+    if ((st = bp_batch_set_plan(B, best_passes, best_c.grid))) return st;
     if (best_us) *best_us = best;
     return bp_batch_reset_messages(B);
 }
@@ -416,24 +462,20 @@ static int batch_readout(bp_batch* B, float* beliefs, int32_t* labels) {
     int st = ready(B);
     if (st) return st;
     if ((st = set_device(B))) return st;
-    const auto* inst = reinterpret_cast<const bpk::InstDesc*>(B->ws + B->desc_off);
-    const auto* items = reinterpret_cast<const bpk::Item*>(B->ws + B->item_off);
-    for (int c = 0; c < bpk::kBatchClasses; ++c) {
-        const int cn = B->class_n[c];
-        if (cn == 0) continue;
-        const unsigned grid = (unsigned)std::max(1, std::min(B->grid_blocks, cn));
-        const bpk::Item* ci = items + B->class_off[c];
-        switch (c) {
-            case 0: hipLaunchKernelGGL(bpk::batch_readout_kernel<4>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
-                                       inst, ci, cn, B->parity, beliefs, labels); break;
-            case 1: hipLaunchKernelGGL(bpk::batch_readout_kernel<8>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
-                                       inst, ci, cn, B->parity, beliefs, labels); break;
-            case 2: hipLaunchKernelGGL(bpk::batch_readout_kernel<16>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
-                                       inst, ci, cn, B->parity, beliefs, labels); break;
-            case 3: hipLaunchKernelGGL(bpk::batch_readout_kernel<32>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
-                                       inst, ci, cn, B->parity, beliefs, labels); break;
+    for (size_t l = 0; l < B->launches.size(); ++l) {
+        const bpk::BatchLaunch& L = B->launches[l];
+        const unsigned grid = launch_grid(B, L);
+        switch (bpk::arm_g(B->launch_arm[l])) {
+            case 4: hipLaunchKernelGGL(bpk::batch_readout_kernel<4>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       L, B->parity, beliefs, labels); break;
+            case 8: hipLaunchKernelGGL(bpk::batch_readout_kernel<8>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                       L, B->parity, beliefs, labels); break;
+            case 16: hipLaunchKernelGGL(bpk::batch_readout_kernel<16>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                        L, B->parity, beliefs, labels); break;
+            case 32: hipLaunchKernelGGL(bpk::batch_readout_kernel<32>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
+                                        L, B->parity, beliefs, labels); break;
             default: hipLaunchKernelGGL(bpk::batch_readout_kernel<64>, dim3(grid), dim3(bpk::kBlock), 0, B->stream,
-                                        inst, ci, cn, B->parity, beliefs, labels); break;
+                                        L, B->parity, beliefs, labels); break;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "batch readout launch");
@@ -455,6 +497,11 @@ int bp_batch_destroy(bp_batch* B) {
     if (!B) return BP_OK;
     drop_graphs(B);
     if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    for (int i = 0; i < bp_batch::kSide; ++i) {
+        if (B->side[i]) (void)hipStreamDestroy(B->side[i]);
+        if (B->ev_join[i]) (void)hipEventDestroy(B->ev_join[i]);
+    }
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
     delete B;
     return BP_OK;
 }

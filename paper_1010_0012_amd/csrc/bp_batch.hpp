@@ -17,13 +17,16 @@ namespace bpk {
 
 constexpr int kBatchTab = 16;      // window taps per instance table (TW <= 8 used)
 
-// Code paths compiled into the batched kernel: (lanes per pixel G, window
-// half-width TW); an instance with truncation T runs the smallest TW >= T
-// for its G.  Every M <= 256 and T <= 8 has a path.
+// Code paths of the batched update: (lanes per pixel G, window half-width
+// TW), one persistent kernel each; an instance with truncation T runs the
+// smallest TW >= T for its G, the same choice as a single-grid update.  Every
+// M <= 256 and T <= 8 has a path.
 constexpr int kBatchClasses = 5;   // G = 4, 8, 16, 32, 64
-constexpr int kBatchArms = 15;
-constexpr int kArmG[kBatchArms] = {4, 4, 4, 8, 8, 8, 16, 16, 16, 32, 32, 32, 64, 64, 64};
-constexpr int kArmTw[kBatchArms] = {2, 4, 8, 2, 4, 8, 2, 4, 8, 2, 4, 8, 2, 4, 8};
+constexpr int kBatchTws = 7;       // TW = 0, 1, 2, 3, 4, 6, 8
+constexpr int kBatchArms = kBatchClasses * kBatchTws;
+constexpr int kTwOf[kBatchTws] = {0, 1, 2, 3, 4, 6, 8};
+constexpr int arm_g(int a) { return 4 << (a / kBatchTws); }
+constexpr int arm_tw(int a) { return kTwOf[a % kBatchTws]; }
 
 struct InstDesc {
     const float* g;          // unary [H][W][M]
@@ -31,97 +34,104 @@ struct InstDesc {
     long long belief_off;    // offset of this instance in a concatenated beliefs array
     long long label_off;     // offset in a concatenated labels array
     int H, W, M, N, T;
-    int arm;                 // index into kArmG / kArmTw
+    int arm;                 // code path: G = arm_g(arm), TW = arm_tw(arm)
     float fbar;              // float32 (max-product)
     float tab_f[kBatchTab];  // f(d), |d| <= T (max-product, float32)
     double fbar_d;           // double (sum-product)
     double tab_wd[kBatchTab];  // f(d) - fbar, |d| <= T (sum-product, double)
 };
 
-struct Item {
-    int inst;
-    int first;               // first pixel (row-major) of the item
-    int passes;              // passes of kBlock/G pixels (one pixel per G lanes)
-    int pad;
+// One launch of a code path: up to kLaunchInst instances, their descriptors
+// passed by value in the kernel arguments (no dependent loads before a
+// workgroup's first message load).  Workgroup b serves the instance k whose
+// block range [blocks_end[k-1], blocks_end[k]) holds b, covering `passes`
+// passes of kBlock/G pixels from (b - blocks_end[k-1]) * passes * kBlock/G.
+constexpr int kLaunchInst = 8;
+struct BatchLaunch {
+    int n_inst;
+    int passes;
+    int blocks_end[kLaunchInst];  // inclusive prefix sums of workgroups per instance
+    InstDesc inst[kLaunchInst];
 };
 
+__device__ __forceinline__ int launch_instance(const BatchLaunch& L, int b) {
+    int k = 0;
+    while (k + 1 < L.n_inst && b >= L.blocks_end[k]) ++k;  // uniform over the workgroup
+    return k;
+}
+
 template <int G, int TW, int MODE>
-__device__ __forceinline__ void batch_item(const InstDesc* __restrict__ d, const Item& item, int parity) {
+__device__ __forceinline__ void batch_item(const InstDesc& d, int first, int passes, int parity) {
     constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const float* in = d->msg[parity];
-    float* out = d->msg[parity ^ 1];
-    const int M = d->M, W = d->W;
-    const size_t plane = (size_t)d->N * M;
+    const float* in = d.msg[parity];
+    float* out = d.msg[parity ^ 1];
+    const int M = d.M, W = d.W;
+    const size_t plane = (size_t)d.N * M;
     const bool full = M == G * kLpl;
     const int x0 = pos * kLpl;
-    const float* tab = d->tab_f;
-    const float fbar = d->fbar;
-    for (int pass = 0; pass < item.passes; ++pass) {
-        const Pixel px = sync_pixel(item.first + pass * RPB + grp, d->H, W, d->N);
+    for (int pass = 0; pass < passes; ++pass) {
+        const Pixel px = sync_pixel(first + pass * RPB + grp, d.H, W, d.N);
         if (!px.ok) continue;  // whole groups only
         PixelInputs pin;
-        load_pixel_ptr(d->g, in, plane, M, px, x0, full, pin);
+        load_pixel_ptr(d.g, in, plane, M, px, x0, full, pin);
         double h[4][kLpl];
         make_h_d(pin, h);
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             float u[kLpl];
-            if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], d->tab_wd, d->fbar_d, pos, M, x0, full, u);
-            else max_message_d<G, TW>(h[o], tab, fbar, pos, M, x0, full, u);
+            if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], d.tab_wd, d.fbar_d, pos, M, x0, full, u);
+            else max_message_d<G, TW>(h[o], d.tab_f, d.fbar, pos, M, x0, full, u);
             store_message(out, plane, M, W, px, o, x0, full, u);
         }
     }
 }
 
-// One persistent kernel per lane class G (the work queue is partitioned by
-// class), so each kernel's register budget is that of its own three window
-// variants rather than the union over every class.
-template <int MODE, int G>
-__global__ __launch_bounds__(kBlock) void batch_update_kernel(const InstDesc* __restrict__ inst,
-                                                              const Item* __restrict__ items,
-                                                              int n_items, int parity) {
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const Item item = items[it];
-        const InstDesc* d = inst + item.inst;
-        switch (d->arm % 3) {  // arms 3c, 3c+1, 3c+2: TW = 2, 4, 8 for class c
-            case 0: batch_item<G, 2, MODE>(d, item, parity); break;
-            case 1: batch_item<G, 4, MODE>(d, item, parity); break;
-            default: batch_item<G, 8, MODE>(d, item, parity); break;
+// PERSIST: the grid strides over the launch's workgroups and each covers
+// L.passes passes; otherwise (one pass per workgroup, one workgroup per
+// range) the kernel has no loops and the register budget of the single-grid
+// update.
+template <int MODE, int G, int TW, bool PERSIST>
+__global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchLaunch L, int parity) {
+    if constexpr (PERSIST) {
+        const int total = L.blocks_end[L.n_inst - 1];
+        for (int b = blockIdx.x; b < total; b += gridDim.x) {
+            const int k = launch_instance(L, b);
+            const int b0 = k ? L.blocks_end[k - 1] : 0;
+            batch_item<G, TW, MODE>(L.inst[k], (b - b0) * (kBlock / G) * L.passes, L.passes, parity);
         }
+    } else {
+        const int b = blockIdx.x;
+        const int k = launch_instance(L, b);
+        const int b0 = k ? L.blocks_end[k - 1] : 0;
+        batch_item<G, TW, MODE>(L.inst[k], (b - b0) * (kBlock / G), 1, parity);
     }
 }
 
 // Beliefs (Eq. 3) and MAP labels of every instance into concatenated outputs.
 template <int G>
-__device__ __forceinline__ void batch_readout_item(const InstDesc* __restrict__ d, const Item& item,
-                                                   int parity, float* beliefs, int* labels) {
+__global__ __launch_bounds__(kBlock) void batch_readout_kernel(const BatchLaunch L, int parity, float* beliefs,
+                                                               int* labels) {
     constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int M = d->M;
-    const size_t plane = (size_t)d->N * M;
-    const bool full = M == G * kLpl;
     const int x0 = pos * kLpl;
-    for (int pass = 0; pass < item.passes; ++pass) {
-        const Pixel px = sync_pixel(item.first + pass * RPB + grp, d->H, d->W, d->N);
-        if (!px.ok) continue;
-        PixelInputs pin;
-        load_pixel_ptr(d->g, d->msg[parity], plane, M, px, x0, full, pin);
-        readout_pixel<G>(pin, M, x0, full, beliefs ? beliefs + d->belief_off + (size_t)px.p * M : nullptr,
-                         labels ? labels + d->label_off + px.p : nullptr);
-    }
-}
-
-template <int G>
-__global__ __launch_bounds__(kBlock) void batch_readout_kernel(const InstDesc* __restrict__ inst,
-                                                               const Item* __restrict__ items,
-                                                               int n_items, int parity,
-                                                               float* beliefs, int* labels) {
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const Item item = items[it];
-        batch_readout_item<G>(inst + item.inst, item, parity, beliefs, labels);
+    const int total = L.blocks_end[L.n_inst - 1];
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int k = launch_instance(L, b);
+        const InstDesc& d = L.inst[k];
+        const int first = (b - (k ? L.blocks_end[k - 1] : 0)) * RPB * L.passes;
+        const size_t plane = (size_t)d.N * d.M;
+        const bool full = d.M == G * kLpl;
+        for (int pass = 0; pass < L.passes; ++pass) {
+            const Pixel px = sync_pixel(first + pass * RPB + grp, d.H, d.W, d.N);
+            if (!px.ok) continue;
+            PixelInputs pin;
+            load_pixel_ptr(d.g, d.msg[parity], plane, d.M, px, x0, full, pin);
+            readout_pixel<G>(pin, d.M, x0, full, beliefs ? beliefs + d.belief_off + (size_t)px.p * d.M : nullptr,
+                             labels ? labels + d.label_off + px.p : nullptr);
+        }
     }
 }
 

@@ -94,7 +94,9 @@ def test_plans_do_not_change_results():
     batch, _ = make_batch(SMALL, seeds)
     batch.iterate("sum", 4)
     ref = results(batch)
-    for passes, grid in (([1, 1, 1, 1, 1], 1), ([3, 5, 2, 7, 1], 7), ([64, 32, 16, 16, 4], 1024), ([2, 2, 2, 2, 2], 1 << 30)):
+    for streams, passes, grid in ((4, [1, 1, 1, 1, 1], 1), (1, [3, 5, 2, 7, 1], 7), (2, [64, 32, 16, 16, 4], 1024),
+                                  (1, [2, 2, 2, 2, 2], 1 << 30), (1, [1, 1, 1, 1, 1], 1 << 30)):
+        batch.set_streams(streams)
         batch.set_plan(passes, grid)
         batch.reset()
         batch.iterate("sum", 4)
@@ -103,7 +105,7 @@ def test_plans_do_not_change_results():
             np.testing.assert_array_equal(x, y)
     best = batch.autotune("sum", 2)
     plan = batch.get_plan()
-    say(f"autotuned plan {plan}, {best:.1f} us/iteration")
+    say(f"autotuned plan {plan}, {batch.get_streams()} streams, {best:.1f} us/iteration")
     batch.iterate("sum", 4)
     got = results(batch)
     for x, y in zip(got[0] + got[1], ref[0] + ref[1]):
