@@ -162,6 +162,64 @@ def grad_leg(reps=3):
             "fwd_bwd_solves_per_s": 1.0 / dt}
 
 
+def sweep_leg(grid, cfg, reps=2):
+    """Directional sweeps (Sec. 6): one sweep = passes left, right, up and down
+    = every directed message once, sequential along each row or column.
+    Time per sweep on the benchmark grid and at the paper's 144 x 192 shape
+    (sparse vs dense there, beside the paper's CPU ratio of about 3.1)."""
+    import torch
+
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import CONFIGS, make_config
+    out = {}
+    for name, c, gr in (("480x640", cfg, grid), ("144x192", CONFIGS["stereo144x192"], None)):
+        own = gr is None
+        if own:
+            g32, _ = make_config(c)
+            gr = Grid(c.H, c.W)
+            gr.set_potential(c.M, c.T, c.alpha)
+            gr.set_unary(torch.from_numpy(g32).cuda())
+        updates = c.n_directed_edges * c.M
+        for mode, dense in (("sum", False), ("max", False), ("sum", True)):
+            ms = time_launches(gr, mode, 2, "sweep", dense, reps)  # ms per sweep
+            key = f"sweep_{name}_{'dense' if dense else 'sparse'}_{mode}"
+            out[key + "_us"] = ms * 1e3
+            out[key + "_updates_per_s"] = updates / (ms * 1e-3)
+            log(f"bench: {key}: {ms * 1e3:.1f} us/sweep, {updates / (ms * 1e-3):.3e} updates/s")
+        out[f"sweep_{name}_dense_over_sparse_sum"] = out[f"sweep_{name}_dense_sum_us"] / out[f"sweep_{name}_sparse_sum_us"]
+        if own:
+            gr.close()
+    return out
+
+
+def fbar_zero_leg():
+    """Sec. 6's f-bar = 0 experiment on the synthetic 144 x 192 stereo pair:
+    ten sum-product sweeps with f-bar = exp(-alpha T) and with f-bar = 0;
+    the fraction of disparity labels that change, and each map's error rate
+    against the synthetic ground truth (|label - disparity| > 1)."""
+    import numpy as np
+    import torch
+
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import CONFIGS, make_config
+    c = CONFIGS["stereo144x192"]
+    g32, D = make_config(c)
+    labels = {}
+    for name, fbar in (("tied", None), ("zero", 0.0)):
+        gr = Grid(c.H, c.W)
+        gr.set_potential(c.M, c.T, c.alpha, fbar)
+        gr.set_unary(torch.from_numpy(g32).cuda())
+        gr.iterate("sum", c.iters, "sweep")
+        labels[name] = gr.map_labels().cpu().numpy()
+        gr.close()
+    changed = float(np.mean(labels["tied"] != labels["zero"]))
+    bad = {k: float(np.mean(np.abs(v.astype(np.int64) - D) > 1)) for k, v in labels.items()}
+    log(f"bench: fbar=0 experiment (144x192, {c.iters} sweeps): {100 * changed:.2f}% of labels change; "
+        f"bad pixels {100 * bad['tied']:.2f}% (fbar=exp(-aT)) vs {100 * bad['zero']:.2f}% (fbar=0)")
+    return {"fbar0_labels_changed": changed, "fbar0_bad_pixels_tied": bad["tied"],
+            "fbar0_bad_pixels_zero": bad["zero"]}
+
+
 def batch_leg(n_iters=30, reps=3):
     """The 32-instance batch (H, W in [64, 512], M in {16, 32, 64, 128}, T in
     [1, 8]): autotuned plan, n_iters sum-product iterations per graph replay;
@@ -301,6 +359,8 @@ def main():
                 extra[f"sparse_over_dense_{mode}"] = sp / dn
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
     if not args.no_legs:
+        extra.update(sweep_leg(grid, cfg))
+        extra.update(fbar_zero_leg())
         extra.update(grad_leg())
         extra.update(batch_leg())
 

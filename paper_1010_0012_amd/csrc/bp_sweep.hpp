@@ -9,8 +9,8 @@
 // sent is exactly the inbox entry the next sender reads from the opposite
 // side, so it stays in registers (the carry) as well as being stored for the
 // later passes and the readout.  The unary and the two perpendicular inbox
-// messages of the next sender do not depend on the carry and are loaded one
-// step ahead.  A pass writes only the inbox plane opposite to its direction
+// messages of a sender do not depend on the carry and are loaded four steps
+// ahead.  A pass writes only the inbox plane opposite to its direction
 // and reads only the two perpendicular planes, so it runs in place.
 #pragma once
 
@@ -102,83 +102,89 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
     };
 
     const int steps = len - 1;  // the last node of the scanline sends nothing this way
-    float cg[kLpl], c0[kLpl], c1[kLpl], carry[kLpl];
+    // Inputs of the next kAhead senders in flight: a ring of registers,
+    // statically indexed by unrolling the step loop by kAhead.
+    constexpr int kAhead = 4;
+    float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) cg[i] = c0[i] = c1[i] = carry[i] = 1.0f;  // first sender: no carry
-    if (live && steps > 0) load_raw(0, cg, c0, c1);
-    for (int t = 0; t < steps; ++t) {
-        float ng[kLpl], n0[kLpl], n1[kLpl];
+    for (int j = 0; j < kAhead; ++j)
 #pragma unroll
-        for (int i = 0; i < kLpl; ++i) ng[i] = n0[i] = n1[i] = 1.0f;
-        if (live && t + 1 < steps) load_raw(t + 1, ng, n0, n1);
-        double h[kLpl];  // Eq. 5, in double as in the other updates
+        for (int i = 0; i < kLpl; ++i) rg[j][i] = r0[j][i] = r1[j][i] = 1.0f;
 #pragma unroll
-        for (int i = 0; i < kLpl; ++i) h[i] = (((double)cg[i] * c0[i]) * c1[i]) * carry[i];
-        float m[kLpl];
-        if constexpr (KIND == kSweepReg) {
-            if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
-            else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
-        } else {
+    for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
 #pragma unroll
-            for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
-            __syncthreads();
-            double u[kLpl];
-            if constexpr (MODE == kSum) {
-                if constexpr (KIND == kSweepLds) {
-                    double s = (h[0] + h[1]) + (h[2] + h[3]);
-                    s = group_sum_d<G>(s);
-                    const double base = a.fbar_d * s;
+    for (int j = 0; j < kAhead; ++j)
+        if (live && j < steps) load_raw(j, rg[j], r0[j], r1[j]);
+    for (int t0 = 0; t0 < steps; t0 += kAhead) {
 #pragma unroll
-                    for (int i = 0; i < kLpl; ++i) {
-                        const int y = x0 + i;
-                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                        double acc = base;
-                        for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], hs[x], acc);
-                        u[i] = acc;
-                    }
-                } else {
+        for (int j = 0; j < kAhead; ++j) {
+            const int t = t0 + j;
+            if (t >= steps) break;  // the same for every group of the workgroup
+            double h[kLpl];  // Eq. 5, in double as in the other updates
 #pragma unroll
-                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
-                    for (int x = 0; x < a.M; ++x) {
-                        const double hx = hs[x];
-#pragma unroll
-                        for (int i = 0; i < kLpl; ++i) u[i] = fma(Fd[x * CAP + x0 + i], hx, u[i]);
-                    }
-                }
+            for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
+            if (live && t + kAhead < steps) load_raw(t + kAhead, rg[j], r0[j], r1[j]);
+            float m[kLpl];
+            if constexpr (KIND == kSweepReg) {
+                if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
+                else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
             } else {
-                if constexpr (KIND == kSweepLds) {
-                    const double base = (double)a.fbar * group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
 #pragma unroll
-                    for (int i = 0; i < kLpl; ++i) {
-                        const int y = x0 + i;
-                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                        double acc = base;
-                        for (int x = lo; x <= hi; ++x) acc = fmax(acc, (double)tab[x > y ? x - y : y - x] * hs[x]);
-                        u[i] = acc;
+                for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
+                __syncthreads();
+                double u[kLpl];
+                if constexpr (MODE == kSum) {
+                    if constexpr (KIND == kSweepLds) {
+                        double s = (h[0] + h[1]) + (h[2] + h[3]);
+                        s = group_sum_d<G>(s);
+                        const double base = a.fbar_d * s;
+#pragma unroll
+                        for (int i = 0; i < kLpl; ++i) {
+                            const int y = x0 + i;
+                            const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                            double acc = base;
+                            for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], hs[x], acc);
+                            u[i] = acc;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                        for (int x = 0; x < a.M; ++x) {
+                            const double hx = hs[x];
+#pragma unroll
+                            for (int i = 0; i < kLpl; ++i) u[i] = fma(Fd[x * CAP + x0 + i], hx, u[i]);
+                        }
                     }
                 } else {
+                    if constexpr (KIND == kSweepLds) {
+                        const double base = (double)a.fbar * group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
 #pragma unroll
-                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
-                    for (int x = 0; x < a.M; ++x) {
-                        const double hx = hs[x];
+                        for (int i = 0; i < kLpl; ++i) {
+                            const int y = x0 + i;
+                            const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                            double acc = base;
+                            for (int x = lo; x <= hi; ++x) acc = fmax(acc, (double)tab[x > y ? x - y : y - x] * hs[x]);
+                            u[i] = acc;
+                        }
+                    } else {
 #pragma unroll
-                        for (int i = 0; i < kLpl; ++i) u[i] = fmax(u[i], (double)F[x * CAP + x0 + i] * hx);
+                        for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                        for (int x = 0; x < a.M; ++x) {
+                            const double hx = hs[x];
+#pragma unroll
+                            for (int i = 0; i < kLpl; ++i) u[i] = fmax(u[i], (double)F[x * CAP + x0 + i] * hx);
+                        }
                     }
                 }
+                normalise_d<G>(u, a.M, x0, full, m);
+                __syncthreads();  // every group done reading hs before the next step writes it
             }
-            normalise_d<G>(u, a.M, x0, full, m);
-            __syncthreads();  // every group done reading hs before the next step writes it
-        }
-        if (live) {
-            const int q = sender(t) + step_q;
-            store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
-        }
+            if (live) {
+                const int q = sender(t) + step_q;
+                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
+            }
 #pragma unroll
-        for (int i = 0; i < kLpl; ++i) {
-            carry[i] = m[i];
-            cg[i] = ng[i];
-            c0[i] = n0[i];
-            c1[i] = n1[i];
+            for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
         }
     }
 }
