@@ -82,6 +82,58 @@ class Potential:
         return Potential(self.F.T.copy(), self.compat.T.copy(), self.fbar)
 
 
+@dataclass
+class EdgePotentials:
+    """A potential per edge (Sec. 4: f_ij with its own fbar_ij and its own
+    neighbourhood structure; Sec. 7: not necessarily a function of x_i - x_j).
+
+    types[k] is a Potential; th[r, c] is the type of the horizontal pair
+    ((r, c), (r, c+1)) and tv[r, c] that of the vertical pair ((r, c),
+    (r+1, c)); each pair is oriented left-to-right / top-to-bottom as above.
+    """
+
+    types: list
+    th: np.ndarray   # [H, W-1]
+    tv: np.ndarray   # [H-1, W]
+
+    def __post_init__(self):
+        self.th = np.asarray(self.th, dtype=np.int64)
+        self.tv = np.asarray(self.tv, dtype=np.int64)
+        assert len(self.types) > 0 and all(t.M == self.types[0].M for t in self.types)
+
+    @property
+    def M(self) -> int:
+        return self.types[0].M
+
+
+def edge_type_map(pot, H, W, o):
+    """[H, W]: type of the edge from each pixel towards direction o (-1 where
+    there is no neighbour)."""
+    t = np.full((H, W), -1, dtype=np.int64)
+    if o == RIGHT:
+        t[:, :W - 1] = pot.th
+    elif o == LEFT:
+        t[:, 1:] = pot.th
+    elif o == DOWN:
+        t[:H - 1, :] = pot.tv
+    else:
+        t[1:, :] = pot.tv
+    return t
+
+
+def messages_towards(h, pot, o, form, tmap=None):
+    """Normalised messages u for the h rows (any leading shape) sent towards
+    direction o.  With per-edge potentials, tmap gives each row's edge type."""
+    if not isinstance(pot, EdgePotentials):
+        return normalize(form(h, oriented_potential(pot, o)))
+    out = np.zeros_like(h)
+    for k, pk in enumerate(pot.types):
+        sel = tmap == k
+        if np.any(sel):
+            out[sel] = normalize(form(h[sel], oriented_potential(pk, o)))
+    return out
+
+
 def truncated_linear(M: int, T: int, alpha: float, fbar: float | None = None) -> Potential:
     """f(x_i, x_j) = exp(-alpha * |x_i - x_j|) for |x_i - x_j| <= T, fbar otherwise.
 
@@ -256,7 +308,8 @@ def compute_messages(g, inbox, pot, mode, impl, storage=None):
     out = {}
     for o in DIRS:
         h = h_vector(g, inbox, has, o)
-        out[o] = stored(normalize(form(h, oriented_potential(pot, o))), storage)
+        tmap = edge_type_map(pot, H, W, o) if isinstance(pot, EdgePotentials) else None
+        out[o] = stored(messages_towards(h, pot, o, form, tmap), storage)
     return out
 
 
@@ -318,7 +371,7 @@ def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE, storage=None):
     H, W, _ = g.shape
     has = has_neighbor(H, W)
     form = MESSAGE_FORMS[(mode, impl)]
-    potential = oriented_potential(pot, o)
+    tmap = edge_type_map(pot, H, W, o) if isinstance(pot, EdgePotentials) else None
     k = OPPOSITE[o]
     dr, dc = OFFSETS[o]
     state = np.array(inbox, dtype=np.float64)
@@ -334,7 +387,7 @@ def sweep_pass(g, inbox, pot, mode, o, impl=SPARSE, storage=None):
         for j in DIRS:
             if j != o:
                 h = h * np.where(has[j][src][..., None], state[j][src], 1.0)
-        msg = stored(normalize(form(h, potential)), storage)
+        msg = stored(messages_towards(h, pot, o, form, None if tmap is None else tmap[src]), storage)
         dst = line(s + (dc if dc != 0 else dr))
         state[k][dst] = msg
     return state
@@ -418,6 +471,8 @@ def single_update(g, inbox, pot, mode, r, c, o, impl=SPARSE):
         kr, kc = r + OFFSETS[k][0], c + OFFSETS[k][1]
         if 0 <= kr < H and 0 <= kc < W:
             h = h * inbox[k, r, c]
+    if isinstance(pot, EdgePotentials):
+        pot = pot.types[int(edge_type_map(pot, H, W, o)[r, c])]
     u = MESSAGE_FORMS[(mode, impl)](h, oriented_potential(pot, o))
     return normalize(u)
 
