@@ -102,8 +102,8 @@ int bp_set_stream(bp_grid* grid, void* hip_stream);
 int bp_set_potential(bp_grid* grid, int32_t M, int32_t T, float alpha, float fbar);
 
 /* Bytes of device workspace needed after bp_set_potential (two message
- * buffers for the synchronous ping-pong plus small tables), or a negative
- * status. */
+ * buffers for the synchronous ping-pong, plus the tables of the Eq. 10
+ * max-product update sized for any T < M), or a negative status. */
 int64_t bp_workspace_bytes(const bp_grid* grid);
 
 /* Attach caller-owned device workspace (>= bp_workspace_bytes, 256-byte
@@ -123,9 +123,13 @@ int bp_reset_messages(bp_grid* grid);
  * schedule n_iters counts passes (two passes update every message once) and
  * the pass parity continues across calls until the next reset; for the sweep
  * schedule it counts whole sweeps (each updates every message once).
- * Max-product requires f >= fbar on every compatible pair (Sec. 5: Eq. 11
- * equals Eq. 9 only then), i.e. fbar <= f(T) as rounded to float32;
- * otherwise BP_EUNSUPPORTED.  Sum-product accepts any fbar >= 0. */
+ * Eq. 11 equals Eq. 9 only when f >= fbar on every compatible pair (Sec. 5),
+ * i.e. fbar <= f(T) as rounded to float32.  Otherwise max-product runs the
+ * exact Eq. 10 (the largest h outside each window times fbar) through the
+ * general kernel, for the sync and checkerboard schedules; sweeps then
+ * return BP_EUNSUPPORTED.  Sum-product accepts any fbar >= 0.
+ * After bp_set_sparse_potentials the general kernel runs instead (sync and
+ * checkerboard; sweeps and bp_iterate_dense return BP_EUNSUPPORTED). */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
 /* Same contract as bp_iterate, but each message is the plain O(M^2) sum or
@@ -134,6 +138,41 @@ int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
  * the sweep schedule); requires M <= 128 and the table to fit the device's
  * LDS (else BP_EUNSUPPORTED). */
 int bp_iterate_dense(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
+
+/* ------------------------------------------------------------------------
+ * General sparse-compatible potentials (Sec. 4: f_ij with its own constant
+ * fbar_ij outside a set of compatible pairs that may differ from node to
+ * node; Sec. 7: potentials that are not functions of x_i - x_j).  A type is
+ * given in CSR form over the label y of the second node of a pair (the
+ * right or bottom pixel): col_ptr[y] .. col_ptr[y+1]-1 index the compatible
+ * labels x of the first node (left or top pixel), strictly increasing, with
+ * the potential values f(x, y) >= 0; every other pair has the value fbar.
+ * Each message costs O(entries in its list + M) (Eq. 7; Eq. 11 when every
+ * listed f >= fbar, else Eq. 10, exactly).
+ * ---------------------------------------------------------------------- */
+typedef struct bp_sparse_potential {
+    const int32_t* col_ptr;  /* host, [M + 1], col_ptr[0] = 0, non-decreasing */
+    const int32_t* row_idx;  /* host, [col_ptr[M]], labels in [0, M) */
+    const float* val;        /* host, [col_ptr[M]], finite and >= 0 */
+    float fbar;              /* finite and >= 0 */
+} bp_sparse_potential;
+
+/* Device bytes of the tables bp_set_sparse_potentials builds for these
+ * n_types (1..16) types at the grid's M (after bp_set_potential), or a
+ * negative status (BP_EINVAL for a malformed type). */
+int64_t bp_sparse_table_bytes(const bp_grid* grid, int32_t n_types, const bp_sparse_potential* types);
+
+/* Use n_types potential types instead of the truncated-linear potential.
+ * table_dev: caller-owned device buffer (>= bp_sparse_table_bytes, 256-byte
+ * aligned) that receives the tables (copied on the grid's stream; the host
+ * arrays may be freed when the call returns).  type_h_dev (device, [H][W-1])
+ * and type_v_dev (device, [H-1][W]) give the type of every horizontal and
+ * vertical pair (uint8, < n_types), or NULL for type 0 everywhere; they are
+ * borrowed and checked once here.  Keeps the messages.  bp_set_potential
+ * switches back to the truncated-linear potential.  Blocks until earlier
+ * work on the grid's stream has drained. */
+int bp_set_sparse_potentials(bp_grid* grid, int32_t n_types, const bp_sparse_potential* types, void* table_dev,
+                             int64_t table_bytes, const uint8_t* type_h_dev, const uint8_t* type_v_dev);
 
 /* Beliefs (Eq. 3) from the current messages into out_dev (device,
  * [H][W][M]); rows sum to 1.  For max-product they are sum-normalised

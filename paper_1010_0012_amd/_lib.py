@@ -32,6 +32,12 @@ class bp_grid_desc(ctypes.Structure):
                 ("unary", ctypes.c_void_p)]
 
 
+class bp_sparse_potential(ctypes.Structure):
+    """struct bp_sparse_potential (include/bp.h): host CSR arrays."""
+    _fields_ = [("col_ptr", ctypes.POINTER(ctypes.c_int32)), ("row_idx", ctypes.POINTER(ctypes.c_int32)),
+                ("val", ctypes.POINTER(ctypes.c_float)), ("fbar", ctypes.c_float)]
+
+
 class BPError(RuntimeError):
     def __init__(self, status, func, msg):
         super().__init__(f"{func} -> {status}: {msg}")
@@ -44,6 +50,8 @@ _PROTOS = {
     "bp_init_grid": (_c_int, [ctypes.POINTER(_vp), _c_i32, _c_i32, _vp]),
     "bp_set_stream": (_c_int, [_vp, _vp]),
     "bp_set_potential": (_c_int, [_vp, _c_i32, _c_i32, _c_f, _c_f]),
+    "bp_sparse_table_bytes": (_c_i64, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential)]),
+    "bp_set_sparse_potentials": (_c_int, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential), _vp, _c_i64, _vp, _vp]),
     "bp_workspace_bytes": (_c_i64, [_vp]),
     "bp_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
     "bp_set_unary": (_c_int, [_vp, _vp]),
@@ -141,6 +149,34 @@ def bp_set_stream(handle, stream=None):
 
 def bp_set_potential(handle, M, T, alpha, fbar):
     _check(lib().bp_set_potential(handle, M, T, alpha, fbar), "bp_set_potential")
+
+
+def _sparse_types(types):
+    """types: sequence of (col_ptr, row_idx, val, fbar) host arrays.  Returns the
+    ctypes array and the contiguous numpy arrays it points into (keep alive)."""
+    import numpy as np
+    keep, arr = [], (bp_sparse_potential * len(types))()
+    for k, (cp, ri, va, fb) in enumerate(types):
+        cp = np.ascontiguousarray(cp, dtype=np.int32)
+        ri = np.ascontiguousarray(ri, dtype=np.int32)
+        va = np.ascontiguousarray(va, dtype=np.float32)
+        keep += [cp, ri, va]
+        arr[k].col_ptr = cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[k].row_idx = ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[k].val = va.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        arr[k].fbar = float(fb)
+    return arr, keep
+
+
+def bp_sparse_table_bytes(handle, types):
+    arr, keep = _sparse_types(types)
+    return _check(lib().bp_sparse_table_bytes(handle, len(types), arr), "bp_sparse_table_bytes")
+
+
+def bp_set_sparse_potentials(handle, types, table, nbytes, type_h=None, type_v=None):
+    arr, keep = _sparse_types(types)
+    _check(lib().bp_set_sparse_potentials(handle, len(types), arr, _ptr(table), nbytes, _ptr(type_h), _ptr(type_v)),
+           "bp_set_sparse_potentials")
 
 
 def bp_workspace_bytes(handle):

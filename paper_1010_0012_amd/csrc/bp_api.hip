@@ -99,9 +99,19 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD && schedule != BP_SCHED_SWEEP)
         return fail(BP_EINVAL, "bad schedule %d", schedule);
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
-    if (mode == BP_MAX_PRODUCT && !max_product_ok(G))
-        return fail(BP_EUNSUPPORTED,
-                    "max-product needs f(d) >= fbar for |d| <= T (Eq. 11); fbar=%g exceeds f", G->fbar);
+    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+    // General sparse potentials, and max-product of the window potential
+    // when fbar exceeds f somewhere (Eq. 11 does not hold; Eq. 10 does), run
+    // the general kernel.
+    const bool eq10 = !G->general && mode == BP_MAX_PRODUCT && !max_product_ok(G) && !dense;
+    if (G->general || eq10) {
+        if (dense) return fail(BP_EUNSUPPORTED, "the dense kernel takes the truncated-linear potential only");
+        if (schedule == BP_SCHED_SWEEP)
+            return fail(BP_EUNSUPPORTED, "sweeps take the truncated-linear potential with f >= fbar (Eq. 11) only");
+        if ((st = with_device(G))) return st;
+        if (eq10 && (st = build_window_tables(G))) return st;
+        return iterate_general(G, kmode, n, schedule);
+    }
     if (dense && G->M > 128) return fail(BP_EUNSUPPORTED, "dense kernel supports M <= 128");
     if (dense) {
         int max_lds = 0;
@@ -115,7 +125,6 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
                         need, max_lds);
     }
     if ((st = with_device(G))) return st;
-    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
     // sparse sum uses w(d) = f(d) - fbar; sparse max and dense use f(d)
     const float* tab = (!dense && kmode == bpk::kSum) ? G->tab_w : G->tab_f;
     if (schedule == BP_SCHED_SWEEP) {
@@ -208,13 +217,15 @@ int bp_set_potential(bp_grid* G, int32_t M, int32_t T, float alpha, float fbar) 
     G->fbar_tied = tied;
     build_tables(G);
     G->pot_set = true;
+    G->general = false;        // back to the window potential
+    G->win_tab_valid = false;  // its Eq. 10 tables follow T, alpha and fbar
     return BP_OK;
 }
 
 int64_t bp_workspace_bytes(const bp_grid* G) {
     if (!G) return fail(BP_EINVAL, "null handle");
     if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
-    return (int64_t)(2 * align_up(G->msg_floats() * sizeof(float), 256));
+    return (int64_t)(2 * align_up(G->msg_floats() * sizeof(float), 256) + window_table_bytes(G->M));
 }
 
 int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {

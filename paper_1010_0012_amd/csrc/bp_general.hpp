@@ -1,0 +1,183 @@
+// General sparse-compatible potentials (Sec. 4): up to kMaxTypes potential
+// types, each given by its compatible pairs and its constant fbar, assigned
+// per edge; the compatibility structure is arbitrary (a per-node
+// neighbourhood, a potential that is not a function of x_i - x_j, Sec. 7).
+//
+// For each type and orientation the tables hold, per target label y, the
+// list of compatible sender labels x with f(x, y) (float32) and
+// w = f(x, y) - fbar (double), as CSR rows, plus a bitmask of the lists.
+//   sum (Eq. 7):  u(y) = fbar * S + sum over the list of w * h(x)
+//   max (Eq. 11): u(y) = max(fbar * max h, max over the list of f * h(x)),
+//                 exact when every listed f >= fbar;
+//   max (Eq. 10): u(y) = max(max over the list of f * h(x),
+//                            fbar * max over x outside the list of h(x)),
+//                 for types with a listed f < fbar.
+// Eq. 10's complement maximum comes from the K largest entries of h (value
+// descending, label ascending) with K = longest list + 1: the first of them
+// outside list(y) is the maximum over the complement.  Beyond kTopMax the
+// complement is scanned label by label against the bitmask.
+#pragma once
+
+#include "bp_kernels.hpp"
+
+namespace bpk {
+
+constexpr int kMaxTypes = 16;
+constexpr int kTopMax = 32;
+
+struct GenArgs {
+    UpdateArgs u;               // grid, buffers, schedule (its tables are unused)
+    const unsigned char* type_h;  // [H][W-1] edge types of horizontal pairs, or null (type 0)
+    const unsigned char* type_v;  // [H-1][W] edge types of vertical pairs, or null (type 0)
+    const int* ptr;             // [n_types * 2][M + 1]: CSR row starts (absolute entry index)
+    const int* ent_x;           // sender label of each entry
+    const float* ent_f;         // f(x, y) of each entry
+    const double* ent_w;        // f(x, y) - fbar of each entry
+    const unsigned* mask;       // [n_types * 2][M][mask_words]: bit x of row y set iff x in list(y)
+    int mask_words;
+    int n_types;
+    int top_k;                  // K of the Eq. 10 types (0: none needs Eq. 10)
+    float fbar[kMaxTypes];
+    double fbar_d[kMaxTypes];
+    int eq10[kMaxTypes];        // 1: some listed f < fbar (max-product uses Eq. 10)
+};
+
+// Type of the pair between px and its neighbour in direction o (which
+// exists); the host validates the maps, and the clamp keeps every table
+// access in bounds whatever the caller's memory holds later.
+__device__ __forceinline__ int edge_type(const GenArgs& a, const Pixel& px, int o) {
+    const int W = a.u.W;
+    int t;
+    switch (o) {
+        case kRight: t = a.type_h ? a.type_h[px.r * (W - 1) + px.c] : 0; break;
+        case kLeft: t = a.type_h ? a.type_h[px.r * (W - 1) + px.c - 1] : 0; break;
+        case kDown: t = a.type_v ? a.type_v[px.r * W + px.c] : 0; break;
+        default: t = a.type_v ? a.type_v[(px.r - 1) * W + px.c] : 0; break;
+    }
+    return t < a.n_types ? t : a.n_types - 1;
+}
+
+// (value, label) tournament in double: larger value wins, the lower label
+// breaks ties; the same result on every lane of the group.
+template <int G>
+__device__ __forceinline__ void group_argmax_d(double& best, int& arg) {
+    auto take = [&](double ob, int oa) {
+        if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
+    };
+    take(dpp_d<kQuad1032>(best), dpp_i<kQuad1032>(arg));
+    take(dpp_d<kQuad2301>(best), dpp_i<kQuad2301>(arg));
+    if constexpr (G >= 8) take(dpp_d<kRowHalfMirror>(best), dpp_i<kRowHalfMirror>(arg));
+    if constexpr (G >= 16) take(dpp_d<kRowMirror>(best), dpp_i<kRowMirror>(arg));
+    if constexpr (G >= 32) take(xor16_d(best), xor16_i(arg));
+    if constexpr (G >= 64) take(xor32_d(best), xor32_i(arg));
+}
+
+constexpr size_t general_lds_bytes(int G) {
+    // per group: h (4G doubles), the top values (kTopMax doubles) and labels (kTopMax ints)
+    return (size_t)(kBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
+}
+
+template <int G, int MODE, bool EQ10>
+__global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
+    extern __shared__ double lds_d[];
+    constexpr int CAP = G * kLpl;
+    constexpr int RPB = kBlock / G;
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
+    const Pixel px = map_slot(slot, a.u);
+    const int M = a.u.M;
+    const int x0 = pos * kLpl;
+    const bool full = M == CAP;
+    double* hs = lds_d + grp * CAP;
+    double* top_v = lds_d + RPB * CAP + grp * kTopMax;
+    int* top_i = reinterpret_cast<int*>(lds_d + RPB * CAP + RPB * kTopMax) + grp * kTopMax;
+    PixelInputs in;
+    if (px.ok) load_pixel(a.u, px, x0, full, in); else dummy_pixel(in);
+    double h[4][kLpl];
+    make_h_d(in, h);
+    const size_t plane = (size_t)a.u.N * M;
+#pragma unroll 1
+    for (int o = 0; o < 4; ++o) {
+        __syncthreads();  // the previous direction is done with hs and the top list
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[o][i];
+        const bool live = px.ok && px.has[o];
+        const int k = live ? edge_type(a, px, o) : 0;
+        const int ts = 2 * k + ((o == kRight || o == kDown) ? 0 : 1);
+        const int* pt = a.ptr + ts * (M + 1);
+        double u[kLpl];
+        if constexpr (MODE == kSum) {
+            __syncthreads();
+            const double base = a.fbar_d[k] * group_sum_d<G>((h[o][0] + h[o][1]) + (h[o][2] + h[o][3]));
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) {
+                const int y = x0 + i;
+                double acc = base;
+                if (y < M)
+                    for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(a.ent_w[e], hs[a.ent_x[e]], acc);
+                u[i] = acc;
+            }
+        } else {
+            const double hm = group_max_d<G>(fmax(fmax(h[o][0], h[o][1]), fmax(h[o][2], h[o][3])));
+            const bool topk = EQ10 && a.top_k <= kTopMax;
+            if (topk) {
+                // the top_k largest entries of h, value descending, label ascending
+                double last_v = __builtin_huge_val();
+                int last_i = -1;
+                for (int r = 0; r < a.top_k; ++r) {
+                    double bv = -1.0;
+                    int bi = 1 << 30;
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) {
+                        const int y = x0 + i;
+                        const double v = h[o][i];
+                        const bool after = v < last_v || (v == last_v && y > last_i);
+                        if (y < M && after && (v > bv || (v == bv && y < bi))) { bv = v; bi = y; }
+                    }
+                    group_argmax_d<G>(bv, bi);
+                    if (pos == 0) { top_v[r] = bv; top_i[r] = bi; }
+                    last_v = bv;
+                    last_i = bi;
+                }
+            }
+            __syncthreads();
+            const double fb = (double)a.fbar[k];
+            const unsigned* mrow = a.mask + (size_t)ts * M * a.mask_words;
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) {
+                const int y = x0 + i;
+                double inside = 0.0;
+                if (y < M)
+                    for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)a.ent_f[e] * hs[a.ent_x[e]]);
+                double outside;
+                if (!EQ10 || !a.eq10[k]) {
+                    outside = fb * hm;  // Eq. 11: f >= fbar on the list
+                } else if (y >= M) {
+                    outside = 0.0;
+                } else {
+                    // Eq. 10: fbar times the largest h outside list(y) (0 if the list is everything)
+                    const unsigned* row = mrow + (size_t)y * a.mask_words;
+                    double c = 0.0;
+                    if (topk) {
+                        for (int r = 0; r < a.top_k; ++r) {
+                            const int x = top_i[r];
+                            if (x >= M) break;
+                            if (!((row[x >> 5] >> (x & 31)) & 1u)) { c = top_v[r]; break; }
+                        }
+                    } else {
+                        for (int x = 0; x < M; ++x)
+                            if (!((row[x >> 5] >> (x & 31)) & 1u)) c = fmax(c, hs[x]);
+                    }
+                    outside = fb * c;
+                }
+                u[i] = fmax(inside, outside);
+            }
+        }
+        float m[kLpl];
+        normalise_d<G>(u, M, x0, full, m);
+        store_message(a.u.out, plane, M, a.u.W, px, o, x0, full, m);
+    }
+}
+
+}  // namespace bpk

@@ -43,6 +43,7 @@ int grad_checks(const bp_grid* G, int n, int k) {
     if (st) return st;
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
     if (k < 1) return fail(BP_EINVAL, "ckpt_every must be >= 1");
+    if (G->general) return fail(BP_EUNSUPPORTED, "the adjoint takes the truncated-linear potential only");
     if (!bpk::adjoint_supported(G->M, G->T))
         return fail(BP_EUNSUPPORTED, "adjoint supports T <= 16 (12 for M <= 16) (M=%d, T=%d)", G->M, G->T);
     return BP_OK;

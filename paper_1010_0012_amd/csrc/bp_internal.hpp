@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "bp_device.hpp"
 
 struct bp_grid {
@@ -26,6 +28,19 @@ struct bp_grid {
     int cur = 0;                          // buffer holding the current state
     int64_t cb_pass = 0;                  // checkerboard passes since reset
     const float* g = nullptr;
+    // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10
+    // tables of the window potential built into the workspace's table region
+    bool general = false;                 // bp_iterate runs the general kernel on the caller's tables
+    int gen_types = 0, gen_top_k = 0, gen_mask_words = 0;
+    float gen_fbar[16] = {};
+    double gen_fbar_d[16] = {};
+    int gen_eq10[16] = {};
+    char* gen_tab = nullptr;              // device tables
+    size_t gen_off[5] = {};               // offsets of ptr, ent_x, ent_f, ent_w, mask
+    const uint8_t* type_h = nullptr;      // borrowed edge-type maps (null: type 0)
+    const uint8_t* type_v = nullptr;
+    std::vector<char> gen_host;           // host image of the tables (the upload's source)
+    bool win_tab_valid = false;           // window tables in the workspace match (T, alpha, fbar)
     // differentiation: set by bp_forward_ckpt, cleared by any state change
     bool grad_ready = false;
     int grad_n = 0, grad_k = 1;
@@ -46,4 +61,12 @@ void invalidate_grad(bp_grid* G);
 // Launch arguments for one update of G reading `in` and writing `out`
 // (colour < 0: synchronous; 0/1: checkerboard pass of that colour).
 bpk::UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int colour);
+// Device bytes of the window-potential table region at the end of the
+// workspace (Eq. 10 fallback of max-product when fbar exceeds f).
+size_t window_table_bytes(int M);
+// n iterations through the general kernel (caller's tables, or the window
+// potential's Eq. 10 tables); schedule sync or checkerboard.
+int iterate_general(bp_grid* G, int kmode, int n, int schedule);
+// Build the window potential's tables into the workspace table region.
+int build_window_tables(bp_grid* G);
 }  // namespace bpi

@@ -22,6 +22,10 @@ hipError_t launch_dense(const UpdateArgs& a, int mode, hipStream_t stream);
 // gives the LDS bytes of the dense form (M <= 128).
 hipError_t launch_sweep(const UpdateArgs& a, int mode, bool dense, hipStream_t stream);
 size_t sweep_dense_lds_need(int M, int mode);
+// General sparse-potential update (bp_launch_general.hip), same schedule
+// contract as launch_sparse.
+struct GenArgs;
+hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

@@ -1,0 +1,36 @@
+// General sparse-potential update: instantiations and dispatch.
+#include "bp_general.hpp"
+#include "bp_launch.hpp"
+
+namespace bpk {
+namespace {
+
+template <int G, int MODE, bool EQ10>
+hipError_t go_general(const GenArgs& a, hipStream_t s) {
+    const unsigned blocks = (unsigned)((a.u.n_slots + (kBlock / G) - 1) / (kBlock / G));
+    hipLaunchKernelGGL((general_update_kernel<G, MODE, EQ10>), dim3(blocks), dim3(kBlock), general_lds_bytes(G), s,
+                       a);
+    return hipGetLastError();
+}
+
+template <int MODE, bool EQ10>
+hipError_t general_g(const GenArgs& a, hipStream_t s) {
+    switch (lanes_for(a.u.M)) {
+        case 4: return go_general<4, MODE, EQ10>(a, s);
+        case 8: return go_general<8, MODE, EQ10>(a, s);
+        case 16: return go_general<16, MODE, EQ10>(a, s);
+        case 32: return go_general<32, MODE, EQ10>(a, s);
+        case 64: return go_general<64, MODE, EQ10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream) {
+    if (a.u.n_slots <= 0) return hipSuccess;
+    if (mode == kSum) return general_g<kSum, false>(a, stream);
+    return a.top_k > 0 ? general_g<kMax, true>(a, stream) : general_g<kMax, false>(a, stream);
+}
+
+}  // namespace bpk

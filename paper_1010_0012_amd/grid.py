@@ -63,6 +63,23 @@ class Grid:
             L.bp_attach_workspace(self.handle, self._ws.data_ptr() + off, nbytes)
             self._g = None
 
+    def set_sparse_potentials(self, types, type_h=None, type_v=None):
+        """General sparse-compatible potentials: types = [(col_ptr, row_idx,
+        val, fbar), ...] host CSR arrays over the second node's label (see
+        bp_set_sparse_potentials); type_h [H, W-1] / type_v [H-1, W] uint8
+        CUDA tensors or None (type 0).  The tables live in a tensor this
+        wrapper keeps; set_potential switches back."""
+        assert self.M is not None, "set_potential first (it fixes M)"
+        for t, shape in ((type_h, (self.H, self.W - 1)), (type_v, (self.H - 1, self.W))):
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous() and tuple(t.shape) == shape
+        nbytes = L.bp_sparse_table_bytes(self.handle, types)
+        self._tables = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._tables.data_ptr()) % 256
+        self._type_maps = (type_h, type_v)
+        self._sync_stream()
+        L.bp_set_sparse_potentials(self.handle, types, self._tables.data_ptr() + off, nbytes, type_h, type_v)
+
     def set_unary(self, g):
         assert g.is_cuda and g.dtype == torch.float32 and g.is_contiguous()
         assert tuple(g.shape) == (self.H, self.W, self.M), (tuple(g.shape), (self.H, self.W, self.M))

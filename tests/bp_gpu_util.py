@@ -53,8 +53,8 @@ def library_potential(M, T, alpha, fbar, mode):
 
 
 def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, impl=gb.SPARSE,
-               init=None, storage=None):
-    pot = library_potential(M, T, alpha, fbar, mode)
+               init=None, storage=None, pot=None):
+    pot = library_potential(M, T, alpha, fbar, mode) if pot is None else pot
     g = g32.astype(np.float64)
     state = gb.run(g, pot, mode, n_iters, schedule, impl,
                    inbox=None if init is None else init.astype(np.float64), storage=storage)
@@ -66,7 +66,7 @@ STORAGE_TOL = 1e-6     # GPU vs the oracle's float32-storage model (max-product)
 
 
 def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPARSE, init=None,
-          check_msgs=True):
+          check_msgs=True, pot=None):
     """Compare a GPU result with the FP64 oracle and with the oracle's
     float32-storage model (FP64 arithmetic, each stored message rounded once
     to float32), which the GPU's double arithmetic reproduces up to rare
@@ -76,8 +76,8 @@ def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPA
     the FP64 bar is then widened by exactly that storage-only deviation
     (computed by the oracle alone) and the MAP rule applies where the FP64
     margin exceeds twice it."""
-    ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init)
-    ref32 = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, storage=np.float32)
+    ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, pot=pot)
+    ref32 = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, storage=np.float32, pot=pot)
     compare(tag + " [f32-storage model]", gpu, ref32, belief_tol=STORAGE_TOL, msg_tol=STORAGE_TOL,
             check_msgs=check_msgs)
     H, W, _ = g32.shape

@@ -165,7 +165,7 @@ def test_api_errors():
     with pytest.raises(L.BPError) as e:
         L.bp_set_potential(h, 8, 2, 1.0, -0.1)
     assert e.value.status == L.BP_EINVAL
-    L.bp_set_potential(h, 8, 2, 1.0, 0.9)              # fbar above f(2): sum only
+    L.bp_set_potential(h, 8, 2, 1.0, 0.9)              # fbar above f(2): max-product takes Eq. 10
     nbytes = L.bp_workspace_bytes(h)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     with pytest.raises(L.BPError) as e:
@@ -178,8 +178,9 @@ def test_api_errors():
     g = torch.rand(4, 4, 8, device="cuda") + 0.1
     L.bp_set_unary(h, g)
     L.bp_iterate(h, L.BP_SUM_PRODUCT, 2, L.BP_SCHED_SYNC)
-    with pytest.raises(L.BPError) as e:
-        L.bp_iterate(h, L.BP_MAX_PRODUCT, 2, L.BP_SCHED_SYNC)
+    L.bp_iterate(h, L.BP_MAX_PRODUCT, 2, L.BP_SCHED_SYNC)
+    with pytest.raises(L.BPError) as e:                # Eq. 10 sweeps are not built
+        L.bp_iterate(h, L.BP_MAX_PRODUCT, 1, L.BP_SCHED_SWEEP)
     assert e.value.status == L.BP_EUNSUPPORTED
     with pytest.raises(L.BPError) as e:
         L.bp_iterate(h, 7, 1, 0)
