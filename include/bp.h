@@ -174,6 +174,31 @@ int64_t bp_sparse_table_bytes(const bp_grid* grid, int32_t n_types, const bp_spa
 int bp_set_sparse_potentials(bp_grid* grid, int32_t n_types, const bp_sparse_potential* types, void* table_dev,
                              int64_t table_bytes, const uint8_t* type_h_dev, const uint8_t* type_v_dev);
 
+/* ------------------------------------------------------------------------
+ * Multi-scale (coarse-to-fine) BP in tandem with the O(mM) update (Sec. 2,
+ * Sec. 6).  Level l+1 groups the 2 x 2 blocks of level l (ceil(H/2) x
+ * ceil(W/2)); a block's unary is the product of its children's unaries
+ * divided by its maximum over labels (computed in double, rounded once);
+ * the potential is the same at every level.  The coarsest level starts
+ * from uniform messages, every finer level from its parent's inbox (each
+ * pixel copies the inbox of its block), and level l runs iters[l]
+ * synchronous iterations.  A fresh solve: the grid's messages are
+ * overwritten and hold the level-0 result afterwards (slots of off-grid
+ * neighbours, which no update reads, hold prolonged values rather than 1/M).
+ * ---------------------------------------------------------------------- */
+
+/* Device bytes of the levels 1..levels (0..12): their unaries and message
+ * buffers (level 0 uses the grid's own), or a negative status. */
+int64_t bp_multiscale_workspace_bytes(const bp_grid* grid, int32_t levels);
+
+/* Run the multi-scale solve (mode as for bp_iterate; the truncated-linear
+ * potential, with f >= fbar for max-product, else BP_EUNSUPPORTED).
+ * iters: host, [levels + 1], iters[0] for the finest level.  ms_ws: caller-
+ * owned device workspace (>= bp_multiscale_workspace_bytes, 256-byte
+ * aligned; unused when levels = 0), busy until the grid's stream drains. */
+int bp_iterate_multiscale(bp_grid* grid, int32_t mode, int32_t levels, const int32_t* iters, void* ms_ws,
+                          int64_t ms_bytes);
+
 /* Beliefs (Eq. 3) from the current messages into out_dev (device,
  * [H][W][M]); rows sum to 1.  For max-product they are sum-normalised
  * max-marginals. */

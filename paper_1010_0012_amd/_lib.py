@@ -51,6 +51,8 @@ _PROTOS = {
     "bp_set_stream": (_c_int, [_vp, _vp]),
     "bp_set_potential": (_c_int, [_vp, _c_i32, _c_i32, _c_f, _c_f]),
     "bp_sparse_table_bytes": (_c_i64, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential)]),
+    "bp_multiscale_workspace_bytes": (_c_i64, [_vp, _c_i32]),
+    "bp_iterate_multiscale": (_c_int, [_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i32), _vp, _c_i64]),
     "bp_set_sparse_potentials": (_c_int, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential), _vp, _c_i64, _vp, _vp]),
     "bp_workspace_bytes": (_c_i64, [_vp]),
     "bp_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
@@ -177,6 +179,15 @@ def bp_set_sparse_potentials(handle, types, table, nbytes, type_h=None, type_v=N
     arr, keep = _sparse_types(types)
     _check(lib().bp_set_sparse_potentials(handle, len(types), arr, _ptr(table), nbytes, _ptr(type_h), _ptr(type_v)),
            "bp_set_sparse_potentials")
+
+
+def bp_multiscale_workspace_bytes(handle, levels):
+    return _check(lib().bp_multiscale_workspace_bytes(handle, levels), "bp_multiscale_workspace_bytes")
+
+
+def bp_iterate_multiscale(handle, mode, iters, ws, nbytes):
+    arr = (_c_i32 * len(iters))(*iters)
+    _check(lib().bp_iterate_multiscale(handle, mode, len(iters) - 1, arr, _ptr(ws), nbytes), "bp_iterate_multiscale")
 
 
 def bp_workspace_bytes(handle):

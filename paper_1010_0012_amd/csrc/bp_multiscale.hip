@@ -1,0 +1,209 @@
+// Coarse-to-fine (multi-scale) BP in tandem with the O(mM) update (Sec. 2,
+// Sec. 6): a pyramid of 2 x 2 block unaries, the coarsest level solved from
+// uniform messages, every finer level started from its parent's inbox.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "../../include/bp.h"
+#include "bp_internal.hpp"
+#include "bp_kernels.hpp"
+#include "bp_launch.hpp"
+
+using namespace bpi;
+
+namespace bpk {
+namespace {
+
+// Unary of block (r, c) at the next level: the product of its (up to four)
+// children in double, divided by its maximum over labels, rounded once.
+template <int G>
+__global__ __launch_bounds__(kBlock) void pyramid_kernel(const float* __restrict__ fine, int Hf, int Wf,
+                                                         float* __restrict__ coarse, int Hc, int Wc, int M) {
+    const int pos = threadIdx.x & (G - 1);
+    const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
+    if (slot >= Hc * Wc) return;  // whole groups
+    const int r = slot / Wc, c = slot - (slot / Wc) * Wc;
+    const int x0 = pos * kLpl;
+    const bool full = M == G * kLpl;
+    double p[kLpl] = {1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+    for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+        for (int dc = 0; dc < 2; ++dc) {
+            const int fr = 2 * r + dr, fc = 2 * c + dc;
+            if (fr < Hf && fc < Wf) {
+                float v[kLpl];
+                load_labels<false>(fine + ((size_t)fr * Wf + fc) * M, x0, M, full, v, 0.0f);
+#pragma unroll
+                for (int i = 0; i < kLpl; ++i) p[i] *= v[i];
+            }
+        }
+    const double mx = group_max_d<G>(fmax(fmax(p[0], p[1]), fmax(p[2], p[3])));
+    float out[kLpl];
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) out[i] = (float)(p[i] / mx);
+    store_labels<false>(coarse + (size_t)slot * M, x0, M, full, out);
+}
+
+// Initial inbox of a level: pixel (r, c) copies the inbox of block (r/2, c/2).
+__global__ __launch_bounds__(kBlock) void prolong_kernel(const float* __restrict__ coarse, int Hc, int Wc,
+                                                         float* __restrict__ fine, int Hf, int Wf, int M) {
+    const size_t n = (size_t)4 * Hf * Wf * M;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(i % M);
+        const size_t q = i / M;
+        const int p = (int)(q % ((size_t)Hf * Wf));
+        const int k = (int)(q / ((size_t)Hf * Wf));
+        const int r = p / Wf, c = p - (p / Wf) * Wf;
+        fine[i] = coarse[(((size_t)k * Hc + r / 2) * Wc + c / 2) * M + x];
+    }
+}
+
+template <int G>
+hipError_t go_pyramid(const float* fine, int Hf, int Wf, float* coarse, int Hc, int Wc, int M, hipStream_t s) {
+    const unsigned blocks = (unsigned)(((size_t)Hc * Wc + (kBlock / G) - 1) / (kBlock / G));
+    hipLaunchKernelGGL((pyramid_kernel<G>), dim3(blocks), dim3(kBlock), 0, s, fine, Hf, Wf, coarse, Hc, Wc, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramid(const float* fine, int Hf, int Wf, float* coarse, int Hc, int Wc, int M, hipStream_t s) {
+    switch (lanes_for(M)) {
+        case 4: return go_pyramid<4>(fine, Hf, Wf, coarse, Hc, Wc, M, s);
+        case 8: return go_pyramid<8>(fine, Hf, Wf, coarse, Hc, Wc, M, s);
+        case 16: return go_pyramid<16>(fine, Hf, Wf, coarse, Hc, Wc, M, s);
+        case 32: return go_pyramid<32>(fine, Hf, Wf, coarse, Hc, Wc, M, s);
+        default: return go_pyramid<64>(fine, Hf, Wf, coarse, Hc, Wc, M, s);
+    }
+}
+
+hipError_t launch_prolong(const float* coarse, int Hc, int Wc, float* fine, int Hf, int Wf, int M, hipStream_t s) {
+    const size_t n = (size_t)4 * Hf * Wf * M;
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, coarse, Hc, Wc, fine, Hf, Wf, M);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace bpk
+
+namespace {
+
+constexpr int kMaxLevels = 12;
+
+struct Level {
+    int H, W;
+    size_t unary_off, msg_off[2];  // byte offsets in the multi-scale workspace (levels >= 1)
+};
+
+std::vector<Level> plan_levels(const bp_grid* G, int levels, size_t* total) {
+    std::vector<Level> L(levels + 1);
+    L[0].H = G->H;
+    L[0].W = G->W;
+    size_t off = 0;
+    for (int l = 1; l <= levels; ++l) {
+        L[l].H = (L[l - 1].H + 1) / 2;
+        L[l].W = (L[l - 1].W + 1) / 2;
+        const size_t n = (size_t)L[l].H * L[l].W * G->M;
+        L[l].unary_off = off;
+        off += bp_align_up(n * sizeof(float), 256);
+        for (int b = 0; b < 2; ++b) {
+            L[l].msg_off[b] = off;
+            off += bp_align_up(4 * n * sizeof(float), 256);
+        }
+    }
+    *total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bp_multiscale_workspace_bytes(const bp_grid* G, int32_t levels) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
+    if (levels < 0 || levels > kMaxLevels) return fail(BP_EINVAL, "levels must be in [0, %d]", kMaxLevels);
+    size_t total = 0;
+    plan_levels(G, levels, &total);
+    return (int64_t)std::max<size_t>(total, 256);
+}
+
+int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_t* iters, void* ms_ws,
+                          int64_t ms_bytes) {
+    int st = check_ready(G);
+    if (st) return st;
+    invalidate_grad(G);
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (levels < 0 || levels > kMaxLevels) return fail(BP_EINVAL, "levels must be in [0, %d]", kMaxLevels);
+    if (!iters) return fail(BP_EINVAL, "null iteration counts");
+    for (int l = 0; l <= levels; ++l)
+        if (iters[l] < 0) return fail(BP_EINVAL, "iters[%d] < 0", l);
+    if (G->general) return fail(BP_EUNSUPPORTED, "multi-scale BP takes the truncated-linear potential only");
+    if (mode == BP_MAX_PRODUCT)
+        for (int d = 0; d <= G->T; ++d)
+            if (!(G->tab_f[d] >= G->fbar))
+                return fail(BP_EUNSUPPORTED, "multi-scale max-product needs f >= fbar (Eq. 11)");
+    size_t need = 0;
+    std::vector<Level> L = plan_levels(G, levels, &need);
+    if (levels > 0) {
+        if (!ms_ws || reinterpret_cast<uintptr_t>(ms_ws) % 256)
+            return fail(BP_EINVAL, "multi-scale workspace null or not 256-byte aligned");
+        if (ms_bytes < (int64_t)need)
+            return fail(BP_ENOMEM, "multi-scale workspace %lld bytes < %zu needed", (long long)ms_bytes, need);
+    }
+    if ((st = with_device(G))) return st;
+    const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
+    char* base = static_cast<char*>(ms_ws);
+    auto unary = [&](int l) { return l == 0 ? G->g : reinterpret_cast<const float*>(base + L[l].unary_off); };
+    auto buf = [&](int l, int b) {
+        return l == 0 ? G->msg[b] : reinterpret_cast<float*>(base + L[l].msg_off[b]);
+    };
+    hipError_t e;
+    for (int l = 1; l <= levels; ++l) {
+        e = bpk::launch_pyramid(unary(l - 1), L[l - 1].H, L[l - 1].W, const_cast<float*>(unary(l)), L[l].H, L[l].W,
+                                G->M, G->stream);
+        if (e != hipSuccess) return hip_fail(e, "pyramid launch");
+    }
+    int cur = 0;
+    for (int l = levels; l >= 0; --l) {
+        const size_t n = (size_t)4 * L[l].H * L[l].W * G->M;
+        if (l == levels) {
+            for (int b = 0; b < 2; ++b) {
+                e = bpk::launch_fill(buf(l, b), n, 1.0f / (float)G->M, G->stream);
+                if (e != hipSuccess) return hip_fail(e, "multi-scale reset");
+            }
+            cur = 0;
+        } else {
+            // Both buffers: slots of off-grid neighbours are never updated, and
+            // a child's inbox copies its block's, off-grid slots included, so
+            // they must hold the prolonged values whichever buffer is current.
+            for (int b = 0; b < 2; ++b) {
+                e = bpk::launch_prolong(buf(l + 1, cur), L[l + 1].H, L[l + 1].W, buf(l, b), L[l].H, L[l].W, G->M,
+                                        G->stream);
+                if (e != hipSuccess) return hip_fail(e, "prolongation launch");
+            }
+            cur = 0;
+        }
+        for (int t = 0; t < iters[l]; ++t) {
+            bpk::UpdateArgs a = base_args(G, buf(l, cur), buf(l, cur ^ 1), -1);
+            a.g = unary(l);
+            a.H = L[l].H;
+            a.W = L[l].W;
+            a.N = L[l].H * L[l].W;
+            a.n_slots = a.N;
+            a.half_w = (a.W + 1) / 2;
+            memcpy(a.tab, kmode == bpk::kSum ? G->tab_w : G->tab_f, sizeof a.tab);
+            e = bpk::launch_sparse(a, kmode, G->stream);
+            if (e != hipSuccess) return hip_fail(e, "multi-scale update launch");
+            cur ^= 1;
+        }
+    }
+    G->cur = cur;
+    G->cb_pass = 0;
+    return BP_OK;
+}
+
+}  // extern "C"

@@ -95,6 +95,17 @@ class Grid:
         fn = L.bp_iterate_dense if dense else L.bp_iterate
         fn(self.handle, _as_code(mode, MODES), n_iters, _as_code(schedule, SCHEDULES))
 
+    def iterate_multiscale(self, mode="sum", iters=(10, 10, 10)):
+        """Coarse-to-fine solve: iters[l] synchronous iterations at level l
+        (iters[0] the finest), len(iters) - 1 coarser levels."""
+        levels = len(iters) - 1
+        nbytes = L.bp_multiscale_workspace_bytes(self.handle, levels)
+        if getattr(self, "_ms_ws", None) is None or self._ms_ws.numel() < nbytes + 256:
+            self._ms_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ms_ws.data_ptr()) % 256
+        self._sync_stream()
+        L.bp_iterate_multiscale(self.handle, _as_code(mode, MODES), list(iters), self._ms_ws.data_ptr() + off, nbytes)
+
     def beliefs(self, out=None):
         if out is None:
             out = torch.empty((self.H, self.W, self.M), dtype=torch.float32, device=self.device)

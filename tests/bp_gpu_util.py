@@ -62,7 +62,7 @@ def run_oracle(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters
     return state, b, gb.map_labels(b)
 
 
-STORAGE_TOL = 1e-6     # GPU vs the oracle's float32-storage model (max-product)
+STORAGE_TOL = 1e-6     # GPU vs the oracle's float32-storage model
 
 
 def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPARSE, init=None,
@@ -78,6 +78,18 @@ def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPA
     margin exceeds twice it."""
     ref = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, pot=pot)
     ref32 = run_oracle(g32, M, T, alpha, fbar, mode, schedule, n_iters, impl, init, storage=np.float32, pot=pot)
+    check_against(tag, gpu, g32, ref, ref32, check_msgs)
+
+
+def oracle_result(g32, state):
+    """(state, beliefs, MAP) of an oracle state on the unary g32."""
+    b = gb.beliefs(g32.astype(np.float64), state)
+    return state, b, gb.map_labels(b)
+
+
+def check_against(tag, gpu, g32, ref, ref32, check_msgs=True):
+    """The comparison rule of `check` for given FP64 and float32-storage
+    oracle results."""
     compare(tag + " [f32-storage model]", gpu, ref32, belief_tol=STORAGE_TOL, msg_tol=STORAGE_TOL,
             check_msgs=check_msgs)
     H, W, _ = g32.shape
@@ -87,8 +99,6 @@ def check(tag, gpu, g32, M, T, alpha, fbar, mode, schedule, n_iters, impl=gb.SPA
     compare(tag + f" [FP64; storage-only deviation {dev_b:.1e}]", gpu, ref,
             belief_tol=max(BELIEF_TOL, dev_b + STORAGE_TOL), msg_tol=max(MSG_TOL, dev_m + STORAGE_TOL),
             check_msgs=check_msgs, map_margin=max(MAP_MARGIN, 2 * dev_b + STORAGE_TOL))
-
-
 def compare(tag, gpu, ref, belief_tol=BELIEF_TOL, msg_tol=MSG_TOL, check_msgs=True, map_margin=MAP_MARGIN):
     """Assert the GPU result (msgs, beliefs, labels) matches the oracle's."""
     msgs, b, lab = gpu
