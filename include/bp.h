@@ -51,6 +51,7 @@ extern "C" {
 
 typedef struct bp_grid bp_grid;   /* opaque single-grid handle */
 typedef struct bp_batch bp_batch; /* opaque handle for many independent grids */
+typedef struct bp_fgraph bp_fgraph; /* opaque factor-graph handle */
 
 enum bp_status {
     BP_OK = 0,
@@ -198,6 +199,58 @@ int64_t bp_multiscale_workspace_bytes(const bp_grid* grid, int32_t levels);
  * aligned; unused when levels = 0), busy until the grid's stream drains. */
 int bp_iterate_multiscale(bp_grid* grid, int32_t mode, int32_t levels, const int32_t* iters, void* ms_ws,
                           int64_t ms_bytes);
+
+/* ------------------------------------------------------------------------
+ * Factor graphs with sparse-compatible higher-order factors (Sec. 7): a
+ * factor over K = 2 or 3 variables equals a constant fbar except on a set C
+ * of compatible tuples, so its message to slot i costs O(C + M):
+ *   sum: fbar * prod_{j != i} S_j + sum over the tuples with x_i = x of
+ *        (f - fbar) * prod_{j != i} n_j(x_j),   S_j = sum of n_j;
+ *   max: max(fbar * prod_{j != i} max n_j, max over those tuples of
+ *        f * prod_{j != i} n_j(x_j))   (needs f >= fbar on C).
+ * Variable-to-factor messages n are g times the variable's other incoming
+ * factor messages (factor order).  One iteration computes every n from the
+ * current factor messages, then every factor message (synchronous); every
+ * message is normalised in double and stored in float32.
+ * ---------------------------------------------------------------------- */
+typedef struct bp_factor_type {
+    int32_t arity;          /* 2 or 3 */
+    int32_t n_tuples;       /* |C| >= 0 */
+    const int32_t* tuples;  /* host, [n_tuples][arity], labels in [0, M), no duplicates */
+    const float* val;       /* host, [n_tuples], f(tuple), finite and >= 0 */
+    float fbar;             /* value of every other tuple, finite and >= 0 */
+} bp_factor_type;
+
+/* n_vars variables with M labels (1..BP_MAX_LABELS); factor a is of type
+ * factor_type[a] over the variables factor_vars[3a .. 3a+arity-1] (host;
+ * distinct, the third entry is ignored for arity 2).  dense_tables != 0 also
+ * builds the complete tuple lists (M^arity per type, at most 2^24) for the
+ * plain O(M^K) update of bp_fg_iterate(..., dense = 1).  Host copies are
+ * taken; the arrays may be freed afterwards. */
+int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, const int32_t* factor_vars,
+               const int32_t* factor_type, int32_t n_types, const bp_factor_type* types, int32_t dense_tables,
+               void* hip_stream);
+int bp_fg_set_stream(bp_fgraph* fg, void* hip_stream);
+/* Device bytes for the graph, the tables and both message sets. */
+int64_t bp_fg_workspace_bytes(const bp_fgraph* fg);
+/* Attach caller-owned workspace (256-byte aligned), upload the graph and the
+ * tables, reset the messages to 1/M. */
+int bp_fg_attach_workspace(bp_fgraph* fg, void* dev_ptr, int64_t bytes);
+/* Borrow the unary table (device, [n_vars][M], 16-byte aligned). */
+int bp_fg_set_unary(bp_fgraph* fg, const float* g_dev);
+int bp_fg_reset_messages(bp_fgraph* fg);
+/* n_iters synchronous iterations; dense = 1 visits every tuple (the O(M^K)
+ * comparison).  Max-product with some f < fbar in C: BP_EUNSUPPORTED unless
+ * dense. */
+int bp_fg_iterate(bp_fgraph* fg, int32_t mode, int32_t n_iters, int32_t dense);
+/* Beliefs (device [n_vars][M], rows sum to 1) and/or MAP labels (device
+ * [n_vars] int32, lowest label on ties); either may be NULL. */
+int bp_fg_beliefs(bp_fgraph* fg, float* beliefs_dev, int32_t* labels_dev);
+/* Copy the factor->variable (m, [n_factors][3][M]) and variable->factor (n)
+ * messages out (device; either may be NULL; unused slots of arity-2
+ * factors are unspecified). */
+int bp_fg_get_messages(const bp_fgraph* fg, float* m_dev, float* n_dev);
+int bp_fg_destroy(bp_fgraph* fg);
 
 /* Beliefs (Eq. 3) from the current messages into out_dev (device,
  * [H][W][M]); rows sum to 1.  For max-product they are sum-normalised

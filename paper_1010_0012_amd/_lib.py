@@ -38,6 +38,13 @@ class bp_sparse_potential(ctypes.Structure):
                 ("val", ctypes.POINTER(ctypes.c_float)), ("fbar", ctypes.c_float)]
 
 
+class bp_factor_type(ctypes.Structure):
+    """struct bp_factor_type (include/bp.h): host tuple lists."""
+    _fields_ = [("arity", ctypes.c_int32), ("n_tuples", ctypes.c_int32),
+                ("tuples", ctypes.POINTER(ctypes.c_int32)), ("val", ctypes.POINTER(ctypes.c_float)),
+                ("fbar", ctypes.c_float)]
+
+
 class BPError(RuntimeError):
     def __init__(self, status, func, msg):
         super().__init__(f"{func} -> {status}: {msg}")
@@ -52,6 +59,17 @@ _PROTOS = {
     "bp_set_potential": (_c_int, [_vp, _c_i32, _c_i32, _c_f, _c_f]),
     "bp_sparse_table_bytes": (_c_i64, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential)]),
     "bp_multiscale_workspace_bytes": (_c_i64, [_vp, _c_i32]),
+    "bp_fg_init": (_c_int, [ctypes.POINTER(_vp), _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_i32),
+                            ctypes.POINTER(_c_i32), _c_i32, ctypes.POINTER(bp_factor_type), _c_i32, _vp]),
+    "bp_fg_set_stream": (_c_int, [_vp, _vp]),
+    "bp_fg_workspace_bytes": (_c_i64, [_vp]),
+    "bp_fg_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
+    "bp_fg_set_unary": (_c_int, [_vp, _vp]),
+    "bp_fg_reset_messages": (_c_int, [_vp]),
+    "bp_fg_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
+    "bp_fg_beliefs": (_c_int, [_vp, _vp, _vp]),
+    "bp_fg_get_messages": (_c_int, [_vp, _vp, _vp]),
+    "bp_fg_destroy": (_c_int, [_vp]),
     "bp_iterate_multiscale": (_c_int, [_vp, _c_i32, _c_i32, ctypes.POINTER(_c_i32), _vp, _c_i64]),
     "bp_set_sparse_potentials": (_c_int, [_vp, _c_i32, ctypes.POINTER(bp_sparse_potential), _vp, _c_i64, _vp, _vp]),
     "bp_workspace_bytes": (_c_i64, [_vp]),
@@ -188,6 +206,63 @@ def bp_multiscale_workspace_bytes(handle, levels):
 def bp_iterate_multiscale(handle, mode, iters, ws, nbytes):
     arr = (_c_i32 * len(iters))(*iters)
     _check(lib().bp_iterate_multiscale(handle, mode, len(iters) - 1, arr, _ptr(ws), nbytes), "bp_iterate_multiscale")
+
+
+def bp_fg_init(n_vars, M, factor_vars, factor_type, types, dense_tables=False, stream=None):
+    """factor_vars: [n_factors, 3] int (third ignored for arity 2); types:
+    sequence of (arity, tuples [C, arity], values [C], fbar)."""
+    import numpy as np
+    fv = np.ascontiguousarray(np.asarray(factor_vars, dtype=np.int32).reshape(-1, 3))
+    ft = np.ascontiguousarray(np.asarray(factor_type, dtype=np.int32).reshape(-1))
+    keep, arr = [fv, ft], (bp_factor_type * len(types))()
+    for k, (arity, tuples, values, fbar) in enumerate(types):
+        tu = np.ascontiguousarray(np.asarray(tuples, dtype=np.int32).reshape(-1, arity))
+        va = np.ascontiguousarray(np.asarray(values, dtype=np.float32).reshape(-1))
+        keep += [tu, va]
+        arr[k].arity, arr[k].n_tuples, arr[k].fbar = arity, len(va), float(fbar)
+        arr[k].tuples = tu.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[k].val = va.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    h = _vp()
+    _check(lib().bp_fg_init(ctypes.byref(h), n_vars, M, len(ft), fv.ctypes.data_as(ctypes.POINTER(_c_i32)),
+                            ft.ctypes.data_as(ctypes.POINTER(_c_i32)), len(types), arr, int(bool(dense_tables)),
+                            _stream(stream)), "bp_fg_init")
+    return h.value
+
+
+def bp_fg_set_stream(handle, stream=None):
+    _check(lib().bp_fg_set_stream(handle, _stream(stream)), "bp_fg_set_stream")
+
+
+def bp_fg_workspace_bytes(handle):
+    return _check(lib().bp_fg_workspace_bytes(handle), "bp_fg_workspace_bytes")
+
+
+def bp_fg_attach_workspace(handle, ws, nbytes):
+    _check(lib().bp_fg_attach_workspace(handle, _ptr(ws), nbytes), "bp_fg_attach_workspace")
+
+
+def bp_fg_set_unary(handle, g):
+    _check(lib().bp_fg_set_unary(handle, _ptr(g)), "bp_fg_set_unary")
+
+
+def bp_fg_reset_messages(handle):
+    _check(lib().bp_fg_reset_messages(handle), "bp_fg_reset_messages")
+
+
+def bp_fg_iterate(handle, mode, n_iters, dense=False):
+    _check(lib().bp_fg_iterate(handle, mode, n_iters, int(bool(dense))), "bp_fg_iterate")
+
+
+def bp_fg_beliefs(handle, beliefs=None, labels=None):
+    _check(lib().bp_fg_beliefs(handle, _ptr(beliefs), _ptr(labels)), "bp_fg_beliefs")
+
+
+def bp_fg_get_messages(handle, m=None, n=None):
+    _check(lib().bp_fg_get_messages(handle, _ptr(m), _ptr(n)), "bp_fg_get_messages")
+
+
+def bp_fg_destroy(handle):
+    _check(lib().bp_fg_destroy(handle), "bp_fg_destroy")
 
 
 def bp_workspace_bytes(handle):

@@ -1,0 +1,415 @@
+// Factor-graph BP with sparse-compatible higher-order factors (Sec. 7):
+// host-side graph, tables, workspace and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/bp.h"
+#include "bp_factor.hpp"
+#include "bp_internal.hpp"
+#include "bp_launch.hpp"
+
+using namespace bpi;
+
+namespace {
+
+struct Tables {  // one CSR set (sparse, or the complete dense lists)
+    std::vector<int> tptr;            // [n_types][3][M + 1]
+    std::vector<int2> ent_o;
+    std::vector<float> ent_f;
+    std::vector<double> ent_w;
+    size_t off[4] = {};               // device offsets: tptr, ent_o, ent_f, ent_w
+};
+
+}  // namespace
+
+struct bp_fgraph {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    int n_vars = 0, M = 0, n_factors = 0, n_types = 0;
+    std::vector<int> fac_type, var_ptr, var_adj;
+    int arity[bpk::kFgMaxTypes] = {};
+    float fbar[bpk::kFgMaxTypes] = {};
+    bool eq11_ok[bpk::kFgMaxTypes] = {};  // every compatible f >= fbar
+    Tables sparse, dense;
+    bool has_dense = false;
+    // device
+    char* ws = nullptr;
+    int64_t ws_bytes = 0;
+    size_t off_type = 0, off_vptr = 0, off_vadj = 0, off_m = 0, off_n = 0, total = 0;
+    std::vector<char> image;          // host source of the table upload
+    const float* g = nullptr;
+};
+
+namespace {
+
+// Per type and slot i, the tuples grouped by their label at i, tuple order
+// kept; entries hold the other slots' labels in slot order.
+void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const std::vector<std::vector<float>>& val,
+                  const float* fbar, Tables& T) {
+    const int M = F->M;
+    T.tptr.assign((size_t)F->n_types * 3 * (M + 1), 0);
+    T.ent_o.clear();
+    T.ent_f.clear();
+    T.ent_w.clear();
+    for (int k = 0; k < F->n_types; ++k) {
+        const int K = F->arity[k];
+        const size_t C = val[k].size();
+        for (int i = 0; i < 3; ++i) {
+            int* row = T.tptr.data() + ((size_t)k * 3 + i) * (M + 1);
+            if (i >= K) {
+                for (int x = 0; x <= M; ++x) row[x] = (int)T.ent_o.size();
+                continue;
+            }
+            std::vector<std::vector<size_t>> by(M);
+            for (size_t c = 0; c < C; ++c) by[tup[k][c * K + i]].push_back(c);
+            for (int x = 0; x < M; ++x) {
+                row[x] = (int)T.ent_o.size();
+                for (size_t c : by[x]) {
+                    int o[2] = {-1, -1}, q = 0;
+                    for (int j = 0; j < K; ++j)
+                        if (j != i) o[q++] = tup[k][c * K + j];
+                    T.ent_o.push_back(make_int2(o[0], o[1]));
+                    T.ent_f.push_back(val[k][c]);
+                    T.ent_w.push_back((double)val[k][c] - (double)fbar[k]);
+                }
+            }
+            row[M] = (int)T.ent_o.size();
+        }
+    }
+}
+
+size_t place(size_t& off, size_t bytes) {
+    const size_t at = off;
+    off += bp_align_up(std::max<size_t>(bytes, 1), 256);
+    return at;
+}
+
+void layout_tables(Tables& T, size_t& off) {
+    T.off[0] = place(off, T.tptr.size() * sizeof(int));
+    T.off[1] = place(off, T.ent_o.size() * sizeof(int2));
+    T.off[2] = place(off, T.ent_f.size() * sizeof(float));
+    T.off[3] = place(off, T.ent_w.size() * sizeof(double));
+}
+
+void copy_tables(const Tables& T, char* img) {
+    memcpy(img + T.off[0], T.tptr.data(), T.tptr.size() * sizeof(int));
+    memcpy(img + T.off[1], T.ent_o.data(), T.ent_o.size() * sizeof(int2));
+    memcpy(img + T.off[2], T.ent_f.data(), T.ent_f.size() * sizeof(float));
+    memcpy(img + T.off[3], T.ent_w.data(), T.ent_w.size() * sizeof(double));
+}
+
+bpk::FgArgs args(const bp_fgraph* F, bool dense) {
+    bpk::FgArgs a;
+    memset(&a, 0, sizeof a);
+    const Tables& T = dense ? F->dense : F->sparse;
+    a.g = F->g;
+    a.var_ptr = reinterpret_cast<const int*>(F->ws + F->off_vptr);
+    a.var_adj = reinterpret_cast<const int*>(F->ws + F->off_vadj);
+    a.fac_type = reinterpret_cast<const int*>(F->ws + F->off_type);
+    a.tptr = reinterpret_cast<const int*>(F->ws + T.off[0]);
+    a.ent_o = reinterpret_cast<const int2*>(F->ws + T.off[1]);
+    a.ent_f = reinterpret_cast<const float*>(F->ws + T.off[2]);
+    a.ent_w = reinterpret_cast<const double*>(F->ws + T.off[3]);
+    a.m_fv = reinterpret_cast<float*>(F->ws + F->off_m);
+    a.n_vf = reinterpret_cast<float*>(F->ws + F->off_n);
+    a.n_vars = F->n_vars;
+    a.n_factors = F->n_factors;
+    a.M = F->M;
+    for (int k = 0; k < F->n_types; ++k) {
+        a.arity[k] = F->arity[k];
+        a.fbar[k] = dense ? 0.0f : F->fbar[k];
+    }
+    return a;
+}
+
+int ready(const bp_fgraph* F) {
+    if (!F) return fail(BP_EINVAL, "null factor-graph handle");
+    if (!F->ws) return fail(BP_ESTATE, "no workspace attached");
+    return BP_OK;
+}
+
+int set_dev(const bp_fgraph* F) {
+    hipError_t e = hipSetDevice(F->dev);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "hipSetDevice");
+}
+
+}  // namespace
+
+extern "C" {
+
+int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, const int32_t* factor_vars,
+               const int32_t* factor_type, int32_t n_types, const bp_factor_type* types, int32_t dense_tables,
+               void* hip_stream) {
+    if (!out) return fail(BP_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (n_vars < 1 || M < 1 || M > BP_MAX_LABELS || n_factors < 0 || (n_factors > 0 && (!factor_vars || !factor_type)))
+        return fail(BP_EINVAL, "bad sizes (n_vars >= 1, 1 <= M <= %d, n_factors >= 0)", BP_MAX_LABELS);
+    if (n_types < 1 || n_types > bpk::kFgMaxTypes || !types)
+        return fail(BP_EINVAL, "n_types must be in [1, %d]", bpk::kFgMaxTypes);
+    if ((int64_t)n_factors * 3 * M >= (int64_t(1) << 31)) return fail(BP_EINVAL, "too many factor messages");
+    int dev = -1;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+    bp_fgraph* F = new (std::nothrow) bp_fgraph();
+    if (!F) return fail(BP_ENOMEM, "host allocation failed");
+    F->dev = dev;
+    F->stream = static_cast<hipStream_t>(hip_stream);
+    F->n_vars = n_vars;
+    F->M = M;
+    F->n_factors = n_factors;
+    F->n_types = n_types;
+    std::vector<std::vector<int>> tup(n_types);
+    std::vector<std::vector<float>> val(n_types);
+    for (int k = 0; k < n_types; ++k) {
+        const bp_factor_type& t = types[k];
+        if (t.arity != 2 && t.arity != 3) { delete F; return fail(BP_EINVAL, "type %d: arity must be 2 or 3", k); }
+        if (t.n_tuples < 0 || (t.n_tuples > 0 && (!t.tuples || !t.val))) {
+            delete F;
+            return fail(BP_EINVAL, "type %d: bad tuple list", k);
+        }
+        if (!std::isfinite(t.fbar) || t.fbar < 0.0f) { delete F; return fail(BP_EINVAL, "type %d: bad fbar", k); }
+        F->arity[k] = t.arity;
+        F->fbar[k] = t.fbar;
+        F->eq11_ok[k] = true;
+        std::unordered_set<int64_t> seen;
+        for (int c = 0; c < t.n_tuples; ++c) {
+            int64_t key = 0;
+            for (int j = 0; j < t.arity; ++j) {
+                const int x = t.tuples[(size_t)c * t.arity + j];
+                if (x < 0 || x >= M) { delete F; return fail(BP_EINVAL, "type %d: label %d out of range", k, x); }
+                key = key * M + x;
+            }
+            if (!seen.insert(key).second) { delete F; return fail(BP_EINVAL, "type %d: duplicate tuple %d", k, c); }
+            if (!std::isfinite(t.val[c]) || t.val[c] < 0.0f) {
+                delete F;
+                return fail(BP_EINVAL, "type %d: values must be finite and >= 0", k);
+            }
+            if (t.val[c] < t.fbar) F->eq11_ok[k] = false;
+        }
+        tup[k].assign(t.tuples, t.tuples + (size_t)t.n_tuples * t.arity);
+        val[k].assign(t.val, t.val + t.n_tuples);
+    }
+    // variables' incident slots, in factor order
+    std::vector<std::vector<int>> adj(n_vars);
+    F->fac_type.assign(factor_type, factor_type + n_factors);
+    for (int a = 0; a < n_factors; ++a) {
+        const int k = factor_type[a];
+        if (k < 0 || k >= n_types) { delete F; return fail(BP_EINVAL, "factor %d: bad type %d", a, k); }
+        for (int i = 0; i < F->arity[k]; ++i) {
+            const int v = factor_vars[(size_t)a * 3 + i];
+            if (v < 0 || v >= n_vars) { delete F; return fail(BP_EINVAL, "factor %d: bad variable %d", a, v); }
+            for (int j = 0; j < i; ++j)
+                if (factor_vars[(size_t)a * 3 + j] == v) { delete F; return fail(BP_EINVAL, "factor %d: repeated variable", a); }
+            adj[v].push_back(a * 3 + i);
+        }
+    }
+    F->var_ptr.assign(n_vars + 1, 0);
+    for (int v = 0; v < n_vars; ++v) {
+        F->var_ptr[v + 1] = F->var_ptr[v] + (int)adj[v].size();
+        F->var_adj.insert(F->var_adj.end(), adj[v].begin(), adj[v].end());
+    }
+    build_tables(F, tup, val, F->fbar, F->sparse);
+    if (dense_tables) {
+        // every tuple listed, with its table value (fbar outside C); the
+        // fbar term of the update is then zero
+        std::vector<std::vector<int>> dt(n_types);
+        std::vector<std::vector<float>> dv(n_types);
+        float zero[bpk::kFgMaxTypes] = {};
+        for (int k = 0; k < n_types; ++k) {
+            const int K = F->arity[k];
+            size_t total = 1;
+            for (int j = 0; j < K; ++j) total *= (size_t)M;
+            if (total > (size_t)1 << 24) { delete F; return fail(BP_EUNSUPPORTED, "dense tables above 2^24 tuples"); }
+            std::vector<float> table(total, F->fbar[k]);
+            for (size_t c = 0; c < val[k].size(); ++c) {
+                size_t key = 0;
+                for (int j = 0; j < K; ++j) key = key * M + tup[k][c * K + j];
+                table[key] = val[k][c];
+            }
+            for (size_t key = 0; key < total; ++key) {
+                size_t r = key;
+                int lab[3];
+                for (int j = K - 1; j >= 0; --j) { lab[j] = (int)(r % M); r /= M; }
+                for (int j = 0; j < K; ++j) dt[k].push_back(lab[j]);
+                dv[k].push_back(table[key]);
+            }
+        }
+        build_tables(F, dt, dv, zero, F->dense);
+        F->has_dense = true;
+    }
+    size_t off = 0;
+    F->off_type = place(off, (size_t)n_factors * sizeof(int));
+    F->off_vptr = place(off, (size_t)(n_vars + 1) * sizeof(int));
+    F->off_vadj = place(off, F->var_adj.size() * sizeof(int));
+    layout_tables(F->sparse, off);
+    if (F->has_dense) layout_tables(F->dense, off);
+    const size_t tables_end = off;
+    F->off_m = place(off, (size_t)n_factors * 3 * M * sizeof(float));
+    F->off_n = place(off, (size_t)n_factors * 3 * M * sizeof(float));
+    F->total = off;
+    F->image.assign(tables_end, 0);
+    memcpy(F->image.data() + F->off_type, F->fac_type.data(), F->fac_type.size() * sizeof(int));
+    memcpy(F->image.data() + F->off_vptr, F->var_ptr.data(), F->var_ptr.size() * sizeof(int));
+    memcpy(F->image.data() + F->off_vadj, F->var_adj.data(), F->var_adj.size() * sizeof(int));
+    copy_tables(F->sparse, F->image.data());
+    if (F->has_dense) copy_tables(F->dense, F->image.data());
+    *out = F;
+    return BP_OK;
+}
+
+int64_t bp_fg_workspace_bytes(const bp_fgraph* F) {
+    if (!F) return fail(BP_EINVAL, "null factor-graph handle");
+    return (int64_t)F->total;
+}
+
+int bp_fg_attach_workspace(bp_fgraph* F, void* dev_ptr, int64_t bytes) {
+    if (!F) return fail(BP_EINVAL, "null factor-graph handle");
+    if (!dev_ptr || reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(BP_EINVAL, "workspace null or misaligned");
+    if (bytes < (int64_t)F->total) return fail(BP_ENOMEM, "workspace %lld bytes < %zu needed", (long long)bytes, F->total);
+    int st = set_dev(F);
+    if (st) return st;
+    hipError_t e = hipStreamSynchronize(F->stream);  // a previous upload may still read the image
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    F->ws = static_cast<char*>(dev_ptr);
+    F->ws_bytes = bytes;
+    e = hipMemcpyAsync(F->ws, F->image.data(), F->image.size(), hipMemcpyHostToDevice, F->stream);
+    if (e != hipSuccess) return hip_fail(e, "factor-graph table upload");
+    return bp_fg_reset_messages(F);
+}
+
+int bp_fg_set_unary(bp_fgraph* F, const float* g_dev) {
+    if (!F) return fail(BP_EINVAL, "null factor-graph handle");
+    if (!g_dev || reinterpret_cast<uintptr_t>(g_dev) % 16) return fail(BP_EINVAL, "unary null or not 16-byte aligned");
+    F->g = g_dev;
+    return BP_OK;
+}
+
+int bp_fg_set_stream(bp_fgraph* F, void* hip_stream) {
+    if (!F) return fail(BP_EINVAL, "null factor-graph handle");
+    F->stream = static_cast<hipStream_t>(hip_stream);
+    return BP_OK;
+}
+
+int bp_fg_reset_messages(bp_fgraph* F) {
+    int st = ready(F);
+    if (st) return st;
+    if ((st = set_dev(F))) return st;
+    const size_t n = (size_t)F->n_factors * 3 * F->M;
+    for (size_t o : {F->off_m, F->off_n}) {
+        hipError_t e = bpk::launch_fill(reinterpret_cast<float*>(F->ws + o), n, 1.0f / (float)F->M, F->stream);
+        if (e != hipSuccess) return hip_fail(e, "factor-graph message reset");
+    }
+    return BP_OK;
+}
+
+int bp_fg_iterate(bp_fgraph* F, int32_t mode, int32_t n_iters, int32_t dense) {
+    int st = ready(F);
+    if (st) return st;
+    if (!F->g) return fail(BP_ESTATE, "bp_fg_set_unary has not been called");
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (n_iters < 0) return fail(BP_EINVAL, "n_iters < 0");
+    if (dense && !F->has_dense) return fail(BP_ESTATE, "dense tables were not built (bp_fg_init dense_tables = 0)");
+    if (mode == BP_MAX_PRODUCT && !dense)
+        for (int k = 0; k < F->n_types; ++k)
+            if (!F->eq11_ok[k])
+                return fail(BP_EUNSUPPORTED, "type %d: max-product needs f >= fbar on the compatible tuples", k);
+    if ((st = set_dev(F))) return st;
+    const bpk::FgArgs a = args(F, dense != 0);
+    for (int t = 0; t < n_iters; ++t) {
+        hipError_t e = bpk::launch_fg_iteration(a, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax, F->stream);
+        if (e != hipSuccess) return hip_fail(e, "factor-graph launch");
+    }
+    return BP_OK;
+}
+
+int bp_fg_beliefs(bp_fgraph* F, float* beliefs_dev, int32_t* labels_dev) {
+    int st = ready(F);
+    if (st) return st;
+    if (!F->g) return fail(BP_ESTATE, "bp_fg_set_unary has not been called");
+    if (!beliefs_dev && !labels_dev) return fail(BP_EINVAL, "no output");
+    if (beliefs_dev && reinterpret_cast<uintptr_t>(beliefs_dev) % 16)
+        return fail(BP_EINVAL, "beliefs output not 16-byte aligned");
+    if ((st = set_dev(F))) return st;
+    hipError_t e = bpk::launch_fg_beliefs(args(F, false), beliefs_dev, labels_dev, F->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "factor-graph readout");
+}
+
+int bp_fg_get_messages(const bp_fgraph* F, float* m_dev, float* n_dev) {
+    int st = ready(F);
+    if (st) return st;
+    if ((st = set_dev(F))) return st;
+    const size_t bytes = (size_t)F->n_factors * 3 * F->M * sizeof(float);
+    if (m_dev) {
+        hipError_t e = hipMemcpyAsync(m_dev, F->ws + F->off_m, bytes, hipMemcpyDeviceToDevice, F->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    if (n_dev) {
+        hipError_t e = hipMemcpyAsync(n_dev, F->ws + F->off_n, bytes, hipMemcpyDeviceToDevice, F->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return BP_OK;
+}
+
+int bp_fg_destroy(bp_fgraph* F) {
+    delete F;
+    return BP_OK;
+}
+
+}  // extern "C"
+
+namespace bpk {
+namespace {
+
+template <int G, int MODE>
+hipError_t go_iteration(const FgArgs& a, hipStream_t s) {
+    constexpr int RPB = kBlock / G;
+    if (a.n_vars > 0) {
+        hipLaunchKernelGGL((fg_var_kernel<G>), dim3((a.n_vars + RPB - 1) / RPB), dim3(kBlock), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int items = a.n_factors * 3;
+    if (items > 0) {
+        hipLaunchKernelGGL((fg_factor_kernel<G, MODE>), dim3((items + RPB - 1) / RPB), dim3(kBlock), fg_lds_bytes(G), s,
+                           a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <int G>
+hipError_t go_beliefs(const FgArgs& a, float* b, int* lab, hipStream_t s) {
+    constexpr int RPB = kBlock / G;
+    hipLaunchKernelGGL((fg_belief_kernel<G>), dim3((a.n_vars + RPB - 1) / RPB), dim3(kBlock), 0, s, a, b, lab);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fg_iteration(const FgArgs& a, int mode, hipStream_t s) {
+    const bool sum = mode == kSum;
+    switch (lanes_for(a.M)) {
+        case 4: return sum ? go_iteration<4, kSum>(a, s) : go_iteration<4, kMax>(a, s);
+        case 8: return sum ? go_iteration<8, kSum>(a, s) : go_iteration<8, kMax>(a, s);
+        case 16: return sum ? go_iteration<16, kSum>(a, s) : go_iteration<16, kMax>(a, s);
+        case 32: return sum ? go_iteration<32, kSum>(a, s) : go_iteration<32, kMax>(a, s);
+        default: return sum ? go_iteration<64, kSum>(a, s) : go_iteration<64, kMax>(a, s);
+    }
+}
+
+hipError_t launch_fg_beliefs(const FgArgs& a, float* b, int* lab, hipStream_t s) {
+    switch (lanes_for(a.M)) {
+        case 4: return go_beliefs<4>(a, b, lab, s);
+        case 8: return go_beliefs<8>(a, b, lab, s);
+        case 16: return go_beliefs<16>(a, b, lab, s);
+        case 32: return go_beliefs<32>(a, b, lab, s);
+        default: return go_beliefs<64>(a, b, lab, s);
+    }
+}
+
+}  // namespace bpk

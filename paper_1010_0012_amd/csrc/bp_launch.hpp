@@ -26,6 +26,11 @@ size_t sweep_dense_lds_need(int M, int mode);
 // contract as launch_sparse.
 struct GenArgs;
 hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream);
+// Factor-graph BP (bp_factor.hip): one synchronous iteration (variable ->
+// factor, then factor -> variable), and the readout.
+struct FgArgs;
+hipError_t launch_fg_iteration(const FgArgs& a, int mode, hipStream_t stream);
+hipError_t launch_fg_beliefs(const FgArgs& a, float* beliefs, int* labels, hipStream_t stream);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

@@ -21,3 +21,4 @@ from .stereo import (  # noqa: F401
     random_unary,
     sha256_of,
 )
+from .factor import FactorGridSpec, make_factor_grid, smoothness_triples  # noqa: F401,E402

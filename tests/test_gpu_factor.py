@@ -1,0 +1,202 @@
+"""GPU parity of factor-graph BP with sparse-compatible higher-order factors
+(Sec. 7) against the oracle (oracle/factor_bp.py): FP64 and the
+float32-storage model, same rule as bp_gpu_util.check_against."""
+import numpy as np
+import pytest
+
+from bp_gpu_util import BELIEF_TOL, MAP_MARGIN, MSG_TOL, STORAGE_TOL, say
+from oracle import factor_bp as fb
+from oracle import grid_bp as gb
+
+pytestmark = pytest.mark.gpu
+
+
+def random_type(rng, M, arity, density, below=False):
+    n_all = M ** arity
+    C = max(1, int(round(density * n_all)))
+    keys = np.sort(rng.choice(n_all, size=C, replace=False))
+    tuples = np.array(np.unravel_index(keys, (M,) * arity)).T
+    fbar = np.float32(rng.uniform(0.05, 0.3))
+    lo = 0.0 if below else float(fbar)
+    vals = rng.uniform(lo, lo + 1.0, C).astype(np.float32)
+    return (arity, tuples, vals, float(fbar)), fb.FactorType(arity, tuples, vals.astype(np.float64), float(fbar))
+
+
+def grid_factor_graph(rng, H, W, M, density, below=False):
+    """Variables on an H x W grid; triples along rows and columns, pairs on
+    the diagonals; three types."""
+    pairs = [random_type(rng, M, 3, density, below), random_type(rng, M, 3, density, below),
+             random_type(rng, M, 2, min(1.0, density * M), below)]
+    fv, ft = [], []
+    idx = lambda r, c: r * W + c
+    for r in range(H):
+        for c in range(W):
+            if c + 2 < W:
+                fv.append((idx(r, c), idx(r, c + 1), idx(r, c + 2)))
+                ft.append(0)
+            if r + 2 < H:
+                fv.append((idx(r, c), idx(r + 1, c), idx(r + 2, c)))
+                ft.append(1)
+            if r + 1 < H and c + 1 < W:
+                fv.append((idx(r, c), idx(r + 1, c + 1), -1))
+                ft.append(2)
+    factors = [(tuple(v for v in vs if v >= 0), k) for vs, k in zip(fv, ft)]
+    fg = fb.FactorGraph(H * W, M, factors, [p for _, p in pairs])
+    return [c for c, _ in pairs], np.array(fv), np.array(ft), fg
+
+
+def run_gpu_fg(ctypes_types, fv, ft, n_vars, M, g32, mode, n, dense=False, dense_tables=False):
+    import torch
+    from paper_1010_0012_amd.factor import FactorGraph
+    G = FactorGraph(n_vars, M, fv, ft, ctypes_types, dense_tables=dense_tables)
+    G.set_unary(torch.from_numpy(np.ascontiguousarray(g32)).cuda())
+    G.iterate(mode, n, dense=dense)
+    m, _ = G.messages()
+    out = m.cpu().numpy(), G.beliefs().cpu().numpy(), G.map_labels().cpu().numpy()
+    torch.cuda.synchronize()
+    G.close()
+    return out
+
+
+def compare_fg(tag, gpu, fg, g32, mode, n):
+    g = g32.astype(np.float64)
+    m64, _ = fb.run(fg, g, mode, n)
+    m32, _ = fb.run(fg, g, mode, n, storage=np.float32)
+    b64, b32 = fb.beliefs(fg, g, m64), fb.beliefs(fg, g, m32)
+    m_gpu, b_gpu, lab = gpu
+
+    def msg_err(ref):
+        return max((float(np.max(np.abs(m_gpu[a, i] - ref[a][i]))) for a in range(len(ref))
+                    for i in range(len(ref[a]))), default=0.0)
+
+    dev_b = float(np.max(np.abs(b32 - b64)))
+    dev_m = max((float(np.max(np.abs(m32[a][i] - m64[a][i]))) for a in range(len(m64)) for i in range(len(m64[a]))),
+                default=0.0)
+    e32_b, e32_m = float(np.max(np.abs(b_gpu - b32))), msg_err(m32)
+    e64_b, e64_m = float(np.max(np.abs(b_gpu - b64))), msg_err(m64)
+    say(f"{tag}: vs f32-storage model max|db|={e32_b:.2e} max|dm|={e32_m:.2e}; vs FP64 max|db|={e64_b:.2e} "
+        f"max|dm|={e64_m:.2e} (storage-only deviation {dev_b:.1e})")
+    assert e32_b <= STORAGE_TOL and e32_m <= STORAGE_TOL
+    assert e64_b <= max(BELIEF_TOL, dev_b + STORAGE_TOL) and e64_m <= max(MSG_TOL, dev_m + STORAGE_TOL)
+    sure = gb.top2_margin(b64) > max(MAP_MARGIN, 2 * dev_b + STORAGE_TOL)
+    assert np.array_equal(lab[sure], np.argmax(b64, axis=-1)[sure])
+    np.testing.assert_array_equal(lab, np.argmax(b_gpu, axis=-1))
+
+
+CASES = [(3, 4, 3, 0.4), (4, 4, 5, 0.2), (3, 5, 8, 0.1), (3, 3, 16, 0.03), (2, 4, 33, 0.004)]
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "H{}W{}M{}".format(*c[:3]))
+def test_factor_graph(case, mode):
+    H, W, M, density = case
+    rng = np.random.default_rng(7000 + CASES.index(case))
+    types, fv, ft, fg = grid_factor_graph(rng, H, W, M, density)
+    g32 = rng.uniform(0.05, 1.0, (H * W, M)).astype(np.float32)
+    gpu = run_gpu_fg(types, fv, ft, H * W, M, g32, mode, 5)
+    compare_fg(f"factor {mode} H{H}W{W}M{M}", gpu, fg, g32, mode, 5)
+
+
+def test_sum_with_values_below_fbar():
+    rng = np.random.default_rng(7100)
+    types, fv, ft, fg = grid_factor_graph(rng, 3, 4, 6, 0.2, below=True)
+    g32 = rng.uniform(0.05, 1.0, (12, 6)).astype(np.float32)
+    compare_fg("factor sum below fbar", run_gpu_fg(types, fv, ft, 12, 6, g32, "sum", 5), fg, g32, "sum", 5)
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_dense_matches_sparse(mode):
+    rng = np.random.default_rng(7200)
+    types, fv, ft, fg = grid_factor_graph(rng, 4, 5, 8, 0.1)
+    g32 = rng.uniform(0.05, 1.0, (20, 8)).astype(np.float32)
+    sp = run_gpu_fg(types, fv, ft, 20, 8, g32, mode, 6, dense_tables=True)
+    dn = run_gpu_fg(types, fv, ft, 20, 8, g32, mode, 6, dense=True, dense_tables=True)
+    if mode == "max":
+        np.testing.assert_array_equal(sp[0], dn[0])
+        np.testing.assert_array_equal(sp[1], dn[1])
+    else:
+        assert np.max(np.abs(sp[1] - dn[1])) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_tree_exact(mode):
+    rng = np.random.default_rng(7300)
+    M = 3
+    pairs = [random_type(rng, M, 3, 0.4), random_type(rng, M, 2, 0.6)]
+    fv = [(0, 1, 2), (2, 3, 4), (2, 5, 6), (4, 7, -1)]
+    ft = [0, 0, 0, 1]
+    fg = fb.FactorGraph(8, M, [(tuple(v for v in vs if v >= 0), k) for vs, k in zip(fv, ft)], [p for _, p in pairs])
+    g32 = rng.uniform(0.05, 1.0, (8, M)).astype(np.float32)
+    _, b, _ = run_gpu_fg([c for c, _ in pairs], np.array(fv), np.array(ft), 8, M, g32, mode, 8)
+    exact = fb.brute_marginals(fg, g32.astype(np.float64), mode)
+    err = float(np.max(np.abs(b - exact)))
+    say(f"factor tree {mode}: max|b - exact| = {err:.2e}")
+    assert err <= BELIEF_TOL
+
+
+def test_factor_full_size_sampled():
+    """A 256 x 256 grid, M = 32, triples along rows and columns with a
+    second-order smoothness compatibility (|x_i - 2 x_j + x_k| <= 2 and
+    |x_i - x_j| <= 4): after 10 iterations every sampled factor->variable
+    message equals the oracle's sparse update of the GPU's variable->factor
+    messages (<= 1e-6)."""
+    import torch
+    from paper_1010_0012_amd.factor import FactorGraph
+    from synth_mrf import make_factor_grid
+    spec = make_factor_grid(256, 256, 32, seed=9)
+    G = FactorGraph(spec.n_vars, spec.M, spec.factor_vars, spec.factor_type, spec.types)
+    G.set_unary(torch.from_numpy(spec.unary).cuda())
+    say("factor 256x256 M=32 x10")
+    G.iterate("sum", 10)
+    m, n = G.messages()
+    m, n = m.cpu().numpy(), n.cpu().numpy()
+    torch.cuda.synchronize()
+    G.close()
+    ftypes = [fb.FactorType(a, t, v.astype(np.float64), f) for a, t, v, f in spec.types]
+    rng = np.random.default_rng(10)
+    worst = 0.0
+    for _ in range(100):
+        a = int(rng.integers(0, len(spec.factor_type)))
+        k = int(spec.factor_type[a])
+        vs = tuple(int(v) for v in spec.factor_vars[a][: ftypes[k].arity])
+        small = fb.FactorGraph(max(vs) + 1, spec.M, [(vs, 0)], [ftypes[k]])
+        nn = [[n[a, i].astype(np.float64) for i in range(len(vs))]]
+        for i in range(len(vs)):
+            want = gb.normalize(fb.factor_message_sparse(small, 0, i, nn, "sum"))
+            worst = max(worst, float(np.max(np.abs(m[a, i] - want))))
+    say(f"factor full size: sampled max|dm| = {worst:.2e}")
+    assert worst <= 1e-6
+
+
+def test_factor_errors():
+    from paper_1010_0012_amd import _lib as L
+    good = (3, np.array([[0, 1, 2], [1, 1, 1]]), np.array([1.0, 2.0]), 0.5)
+    bad = [
+        [(4, np.zeros((1, 4)), np.ones(1), 0.5)],                          # arity 4
+        [(3, np.array([[0, 1, 2], [0, 1, 2]]), np.ones(2), 0.5)],          # duplicate tuple
+        [(3, np.array([[0, 1, 9]]), np.ones(1), 0.5)],                     # label out of range
+        [(3, np.array([[0, 1, 2]]), -np.ones(1), 0.5)],                    # negative value
+    ]
+    for types in bad:
+        with pytest.raises(L.BPError) as e:
+            L.bp_fg_init(5, 4, [[0, 1, 2]], [0], types)
+        assert e.value.status == L.BP_EINVAL
+    with pytest.raises(L.BPError) as e:
+        L.bp_fg_init(5, 4, [[0, 1, 1]], [0], [good])                       # repeated variable
+    assert e.value.status == L.BP_EINVAL
+    with pytest.raises(L.BPError) as e:
+        L.bp_fg_init(5, 4, [[0, 1, 7]], [0], [good])                       # variable out of range
+    assert e.value.status == L.BP_EINVAL
+    import torch
+    from paper_1010_0012_amd.factor import FactorGraph
+    G = FactorGraph(5, 4, [[0, 1, 2]], [0], [(3, good[1], good[2], 1.5)])   # f < fbar in C
+    G.set_unary(torch.rand(5, 4, device="cuda") + 0.1)
+    G.iterate("sum", 2)
+    with pytest.raises(L.BPError) as e:
+        G.iterate("max", 1)
+    assert e.value.status == L.BP_EUNSUPPORTED
+    with pytest.raises(L.BPError) as e:
+        G.iterate("sum", 1, dense=True)                                    # no dense tables
+    assert e.value.status == L.BP_ESTATE
+    torch.cuda.synchronize()
+    G.close()
