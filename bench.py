@@ -260,6 +260,42 @@ def multiscale_leg(grid, cfg, reps=3):
     return out
 
 
+def factor_leg(reps=3, n_iters=10):
+    """Higher-order factors (Sec. 7): a 256 x 256 grid of variables, M = 32,
+    triple factors along every row and column with a second-order smoothness
+    compatibility (1094 of the 32768 triples), sum-product; the O(C + M)
+    update against the plain O(M^3) one (every triple listed) on the same
+    graph.  Updates counted as factor->variable label entries."""
+    import torch
+
+    from paper_1010_0012_amd.factor import FactorGraph
+    from synth_mrf import make_factor_grid
+    spec = make_factor_grid(256, 256, 32, seed=9)
+    G = FactorGraph(spec.n_vars, spec.M, spec.factor_vars, spec.factor_type, spec.types, dense_tables=True)
+    G.set_unary(torch.from_numpy(spec.unary).cuda())
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    updates = len(spec.factor_type) * 3 * spec.M
+    out = {"factor_workload": "256x256 variables, M=32, 130,048 triple factors, C=1094 of 32768, sum-product"}
+    for dense in (False, True):
+        G.reset()
+        G.iterate("sum", 2, dense=dense)
+        best = 1e30
+        for _ in range(reps):
+            e0.record(s)
+            G.iterate("sum", n_iters, dense=dense)
+            e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / n_iters)
+        key = "factor_dense" if dense else "factor_sparse"
+        out[key + "_ms_per_iter"] = best
+        out[key + "_updates_per_s"] = updates / (best * 1e-3)
+        log(f"bench: {key}: {best * 1e3:.1f} us per iteration, {updates / (best * 1e-3):.3e} updates/s")
+    out["factor_dense_over_sparse"] = out["factor_dense_ms_per_iter"] / out["factor_sparse_ms_per_iter"]
+    G.close()
+    return out
+
+
 def batch_leg(n_iters=30, reps=3):
     """The 32-instance batch (H, W in [64, 512], M in {16, 32, 64, 128}, T in
     [1, 8]): autotuned plan, n_iters sum-product iterations per graph replay;
@@ -401,6 +437,7 @@ def main():
     if not args.no_legs:
         extra.update(sweep_leg(grid, cfg))
         extra.update(multiscale_leg(grid, cfg))
+        extra.update(factor_leg())
         extra.update(fbar_zero_leg())
         extra.update(grad_leg())
         extra.update(batch_leg())
