@@ -43,13 +43,14 @@ def alg_bytes_per_sync_iter(cfg):
 KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
                   "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp",
                   "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update_stereo480x640.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update2_stereo480x640.json")
 
 
-def sparse_kernel_name(M, T, mode):
+def sparse_kernel_name(M, T, mode, pair=False):
     """Template instance of the sparse update that runs (M, T): lanes per pixel
     G is the smallest power of two >= ceil(M/4) in [4, 64]; the window width is
-    the smallest compiled half-width >= T."""
+    the smallest compiled half-width >= T; pair: the two-iteration launch
+    (whose last parameter says whether M = 4G)."""
     G = 4
     while G * 4 < M and G < 64:
         G *= 2
@@ -57,6 +58,8 @@ def sparse_kernel_name(M, T, mode):
     tw = next((t for t in tws if t >= T), None)
     if tw is None:
         return f"sparse_update_wide_kernel<{G}, {mode}>"
+    if pair:
+        return f"sparse_update2_kernel<{G}, {tw}, {mode}, {'true' if M == 4 * G else 'false'}>"
     return f"sparse_update_kernel<{G}, {tw}, {mode}>"
 
 
@@ -78,9 +81,10 @@ def measured_traffic():
     return rec["traffic_bytes"] if rec.get("source_sha256") == h.hexdigest() else None
 
 
-def time_launches(grid, mode, n, schedule, dense, reps):
-    """Average duration of one update launch, from HIP events on the stream
-    the library launches on (torch's current stream)."""
+def time_launches(grid, mode, n, schedule, dense, reps, iters_per_launch=1):
+    """Average duration of one update launch (covering iters_per_launch
+    iterations), from HIP events on the stream the library launches on
+    (torch's current stream)."""
     import torch
     s = torch.cuda.current_stream()
     grid.reset()
@@ -95,7 +99,7 @@ def time_launches(grid, mode, n, schedule, dense, reps):
         e1.record(s)
         e1.synchronize()
         total += e0.elapsed_time(e1)
-    return total / (reps * n)  # ms per launch
+    return total * iters_per_launch / (reps * n)  # ms per launch
 
 
 def cpu_baseline(cfg, g32):
@@ -404,26 +408,38 @@ def main():
     value = updates_per_iter * cfg.iters * args.steps / dt
     log(f"bench: sum sync {ms_per_step:.3f} ms/step, {value:.4e} updates/s")
 
-    # dominant kernel: the sparse sum-product update launch
+    # Dominant kernel: the sparse sum-product launch that runs two synchronous
+    # iterations; per launch it reads the unary and the inbox once and writes
+    # the outbox once, the same bytes as a one-iteration launch.
     reps = max(2, args.steps)
-    ms_launch = time_launches(grid, "sum", cfg.iters, "sync", False, reps)
+    ms_launch = time_launches(grid, "sum", cfg.iters, "sync", False, reps, iters_per_launch=2)
     bytes_launch = alg_bytes_per_sync_iter(cfg)
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                "kernel": sparse_kernel_name(cfg.M, cfg.T, 0),
-                "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3}
-    log(f"bench: sparse sum launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
+                "kernel": sparse_kernel_name(cfg.M, cfg.T, 0, pair=True),
+                "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3,
+                "iterations_per_launch": 2}
+    log(f"bench: sparse sum pair launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
-    extra = {"sparse_sum_sync_launch_us": ms_launch * 1e3}
+    extra = {"sparse_sum_sync_pair_launch_us": ms_launch * 1e3}
+    # one iteration per launch, for comparison
+    grid.set_sync_fusion(False)
+    ms_single = time_launches(grid, "sum", cfg.iters, "sync", False, reps)
+    grid.set_sync_fusion(True)
+    extra["sparse_sum_sync_single_launch_us"] = ms_single * 1e3
+    extra["sparse_sum_sync_single_launch_GBs"] = bytes_launch / (ms_single * 1e-3) / 1e9
+    log(f"bench: sparse sum single launch {ms_single * 1e3:.1f} us "
+        f"({bytes_launch / (ms_single * 1e-3) / 1e9:.0f} GB/s); pair launch per iteration {ms_launch * 500:.1f} us")
     if not args.no_legs:
         for mode, sched, dense in (("max", "sync", False), ("sum", "checkerboard", False),
                                    ("max", "checkerboard", False), ("sum", "sync", True),
                                    ("max", "sync", True)):
             n = cfg.iters if sched == "sync" else 2 * cfg.iters
-            ms = time_launches(grid, mode, n, sched, dense, 2)
-            per_iter = ms * (1 if sched == "sync" else 2)
+            pair = sched == "sync" and not dense
+            ms = time_launches(grid, mode, n, sched, dense, 2, iters_per_launch=2 if pair else 1)
+            per_iter = ms * (0.5 if pair else 1 if sched == "sync" else 2)
             key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
             extra[key + "_updates_per_s"] = updates_per_iter / (per_iter * 1e-3)
             extra[key + "_launch_us"] = ms * 1e3
@@ -466,7 +482,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "edge·label updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.H}x{cfg.W} grid, M={cfg.M}, T={cfg.T}, "
                                f"alpha={cfg.alpha}, {cfg.iters} synchronous sum-product iterations "

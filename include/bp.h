@@ -133,6 +133,14 @@ int bp_reset_messages(bp_grid* grid);
  * checkerboard; sweeps and bp_iterate_dense return BP_EUNSUPPORTED). */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
+/* Synchronous iterations of the window potential run two per launch by
+ * default (where a register window is compiled: T <= 16, 12 for M <= 16):
+ * each pixel computes the four messages its neighbours send it, then its
+ * own four, so the intermediate messages stay on chip.  The results are the
+ * same bits as single launches; enable = 0 selects single launches (for
+ * comparison and timing).  Errors: BP_EINVAL on a null handle. */
+int bp_set_sync_fusion(bp_grid* grid, int32_t enable);
+
 /* Same contract as bp_iterate, but each message is the plain O(M^2) sum or
  * max over all sender labels (Eq. 2 / Eq. 9) with the same potential table.
  * The comparison point for the sparse update (Sec. 6 compares the two under
@@ -192,8 +200,11 @@ int bp_set_sparse_potentials(bp_grid* grid, int32_t n_types, const bp_sparse_pot
  * buffers (level 0 uses the grid's own), or a negative status. */
 int64_t bp_multiscale_workspace_bytes(const bp_grid* grid, int32_t levels);
 
-/* Run the multi-scale solve (mode as for bp_iterate; the truncated-linear
- * potential, with f >= fbar for max-product, else BP_EUNSUPPORTED).
+/* Run the multi-scale solve (mode as for bp_iterate).  The potential is the
+ * grid's: the truncated-linear one (max-product with fbar above some f(d)
+ * runs Eq. 10 at every level), or general sparse potentials set without
+ * type maps (one potential on every edge; with type maps BP_EUNSUPPORTED,
+ * since they describe the finest grid only).
  * iters: host, [levels + 1], iters[0] for the finest level.  ms_ws: caller-
  * owned device workspace (>= bp_multiscale_workspace_bytes, 256-byte
  * aligned; unused when levels = 0), busy until the grid's stream drains. */

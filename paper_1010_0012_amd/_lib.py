@@ -76,6 +76,7 @@ _PROTOS = {
     "bp_attach_workspace": (_c_int, [_vp, _vp, _c_i64]),
     "bp_set_unary": (_c_int, [_vp, _vp]),
     "bp_reset_messages": (_c_int, [_vp]),
+    "bp_set_sync_fusion": (_c_int, [_vp, _c_i32]),
     "bp_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_iterate_dense": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_beliefs": (_c_int, [_vp, _vp]),
@@ -281,6 +282,10 @@ def bp_set_unary(handle, g):
 
 def bp_reset_messages(handle):
     _check(lib().bp_reset_messages(handle), "bp_reset_messages")
+
+
+def bp_set_sync_fusion(handle, enable):
+    _check(lib().bp_set_sync_fusion(handle, 1 if enable else 0), "bp_set_sync_fusion")
 
 
 def bp_iterate(handle, mode, n_iters, schedule):

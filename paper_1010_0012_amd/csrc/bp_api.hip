@@ -141,6 +141,17 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         }
         return BP_OK;
     }
+    // Synchronous iterations in pairs: one launch for two (the same bits as
+    // two single launches), then a single launch for an odd remainder.
+    if (schedule == BP_SCHED_SYNC && !dense && G->fuse_sync && bpk::sparse2_supported(G->M, G->T)) {
+        for (; n >= 2; n -= 2) {
+            UpdateArgs a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
+            memcpy(a.tab, tab, sizeof a.tab);
+            hipError_t e = bpk::launch_sparse2(a, kmode, G->stream);
+            if (e != hipSuccess) return hip_fail(e, "fused sparse update launch");
+            G->cur ^= 1;
+        }
+    }
     for (int t = 0; t < n; ++t) {
         UpdateArgs a;
         if (schedule == BP_SCHED_SYNC) {
@@ -165,6 +176,12 @@ size_t bp_align_up(size_t v, size_t a) { return bpi::align_up(v, a); }
 using namespace bpi;
 
 extern "C" {
+
+int bp_set_sync_fusion(bp_grid* G, int32_t enable) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    G->fuse_sync = enable != 0;
+    return BP_OK;
+}
 
 int bp_init_grid(bp_grid** out, int32_t H, int32_t W, void* hip_stream) {
     if (!out) return fail(BP_EINVAL, "null output handle pointer");

@@ -37,6 +37,8 @@ struct bp_batch {
     // launches: one or more per non-empty code path
     std::vector<bpk::BatchLaunch> launches;
     std::vector<int> launch_arm;
+    std::vector<char> launch_full;       // every instance of the launch has M = 4G
+    bool use_pairs = true;               // two iterations per launch (same bits as single launches)
     // Launches touch disjoint instances, so each launch's iterations form an
     // independent chain: the chains run on kSide streams (forked from and
     // joined back into the caller's stream by events), longest work first.
@@ -75,19 +77,25 @@ void drop_graphs(bp_batch* B) {
     B->graphs.clear();
 }
 
-// Launch plan: the instances of each code path, largest first (bytes moved,
-// pixels * M), packed into launches of up to kLaunchInst; each instance is
-// cut into workgroups of passes * kBlock/G pixels (passes per lane class).
-// The launches are then spread over the side streams, longest first.
+bool full_rows(int M) { return M == bpk::lanes_for(M) * bpk::kLpl; }
+
+// Launch plan: the instances of each code path (and whether M = 4G), largest
+// first (bytes moved, pixels * M), packed into launches of up to
+// kLaunchInst; each instance is cut into workgroups of passes * kBlock/G
+// pixels (passes per lane class).  The launches are then spread over the
+// side streams, longest first.
 void build_launches(bp_batch* B) {
     B->launches.clear();
     B->launch_arm.clear();
+    B->launch_full.clear();
     std::vector<long long> work_of;
     auto work = [&](int j) { return (long long)B->desc[j].H * B->desc[j].W * B->desc[j].M; };
-    for (int a = 0; a < bpk::kBatchArms; ++a) {
+    for (int af = 0; af < 2 * bpk::kBatchArms; ++af) {
+        const int a = af / 2;
+        const bool full = af % 2 == 0;
         std::vector<int> js;
         for (int j = 0; j < B->n; ++j)
-            if (B->arm[j] == a) js.push_back(j);
+            if (B->arm[j] == a && full_rows(B->desc[j].M) == full) js.push_back(j);
         std::stable_sort(js.begin(), js.end(), [&](int x, int y) { return work(x) > work(y); });
         for (size_t i0 = 0; i0 < js.size(); i0 += bpk::kLaunchInst) {
             bpk::BatchLaunch L;
@@ -107,6 +115,7 @@ void build_launches(bp_batch* B) {
             }
             B->launches.push_back(L);
             B->launch_arm.push_back(a);
+            B->launch_full.push_back(full);
             work_of.push_back(w);
         }
     }
@@ -159,10 +168,15 @@ hipError_t launch_arm(int arm, const bpk::BatchLaunch& L, unsigned grid, int par
     }
 }
 
-// n iterations: per iteration one launch per entry of the plan.  The
-// launches touch disjoint instances, so their chains run concurrently on
-// the side streams, forked from s after the work already queued there and
-// joined back into s.
+// Launches per entry of the plan for n iterations: with pairs, n / 2
+// two-iteration launches and a single one for an odd n.  Each launch flips
+// the buffer parity once.
+int launches_for(const bp_batch* B, int n) { return B->use_pairs ? n / 2 + (n & 1) : n; }
+
+// n iterations: per iteration (or pair of iterations) one launch per entry
+// of the plan.  The launches touch disjoint instances, so their chains run
+// concurrently on the side streams, forked from s after the work already
+// queued there and joined back into s.
 hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s) {
     hipError_t e = hipSuccess;
     const bool fork = B->n_side > 1;
@@ -172,13 +186,20 @@ hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s
         for (int i = 0; i < B->n_side; ++i)
             if ((e = hipStreamWaitEvent(B->side[i], B->ev_fork, 0)) != hipSuccess) return e;
     }
-    for (int t = 0; t < n; ++t) {
+    const int pairs = B->use_pairs ? n / 2 : 0;
+    for (int t = 0; t < launches_for(B, n); ++t) {
         const int par = (parity0 + t) & 1;
         for (size_t l = 0; l < B->launches.size(); ++l) {
             const bpk::BatchLaunch& L = B->launches[l];
             hipStream_t ls = fork ? B->side[B->launch_stream[l]] : s;
-            e = mode == bpk::kSum ? launch_arm<bpk::kSum>(B->launch_arm[l], L, launch_grid(B, L), par, ls)
-                                  : launch_arm<bpk::kMax>(B->launch_arm[l], L, launch_grid(B, L), par, ls);
+            const int arm = B->launch_arm[l];
+            const unsigned grid = launch_grid(B, L);
+            if (t < pairs)
+                e = mode == bpk::kSum ? bpk::launch_batch_pair_sum(arm, B->launch_full[l], L, grid, par, ls)
+                                      : bpk::launch_batch_pair_max(arm, B->launch_full[l], L, grid, par, ls);
+            else
+                e = mode == bpk::kSum ? launch_arm<bpk::kSum>(arm, L, grid, par, ls)
+                                      : launch_arm<bpk::kMax>(arm, L, grid, par, ls);
             if (e != hipSuccess) return e;
         }
     }
@@ -357,7 +378,7 @@ int bp_batch_iterate(bp_batch* B, int32_t mode, int32_t n_iters) {
         e = hipGraphLaunch(it->second, B->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
-    B->parity ^= (n_iters & 1);
+    B->parity ^= launches_for(B, n_iters) & 1;
     return BP_OK;
 }
 
@@ -440,7 +461,7 @@ int bp_batch_autotune(bp_batch* B, int32_t mode, int32_t trial_iters, float* bes
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) { st = hip_fail(e, "autotune trial"); break; }
-        B->parity ^= (trial_iters + 1) & 1;
+        B->parity ^= (launches_for(B, 1) + launches_for(B, trial_iters)) & 1;
         const float us = ms * 1000.0f / trial_iters;
         if (us < best) {
             best = us;

@@ -109,6 +109,28 @@ __global__ __launch_bounds__(kBlock) void batch_update_kernel(const BatchLaunch 
     }
 }
 
+// Two synchronous iterations per launch (the per-pixel work of
+// sparse_update2_kernel) over the launch's instances, msg[parity] ->
+// msg[parity ^ 1]; FULL: every instance of the launch has M = 4G.
+template <int MODE, int G, int TW, bool FULL>
+__global__ __launch_bounds__(kBlock) void batch_update2_kernel(const BatchLaunch L, int parity) {
+    constexpr int RPB = kBlock / G;
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int total = L.blocks_end[L.n_inst - 1];
+    for (int b = blockIdx.x; b < total; b += gridDim.x) {
+        const int k = launch_instance(L, b);
+        const InstDesc& d = L.inst[k];
+        const int first = (b - (k ? L.blocks_end[k - 1] : 0)) * RPB * L.passes;
+        for (int pass = 0; pass < L.passes; ++pass) {
+            const Pixel px = sync_pixel(first + pass * RPB + grp, d.H, d.W, d.N);
+            if (!px.ok) continue;  // whole groups only
+            pair_pixel<G, TW, MODE, FULL>(d.g, d.msg[parity], d.msg[parity ^ 1], d.H, d.W, d.M, px, pos, d.tab_wd,
+                                          d.fbar_d, d.tab_f, d.fbar);
+        }
+    }
+}
+
 // Beliefs (Eq. 3) and MAP labels of every instance into concatenated outputs.
 template <int G>
 __global__ __launch_bounds__(kBlock) void batch_readout_kernel(const BatchLaunch L, int parity, float* beliefs,

@@ -142,28 +142,42 @@ int build_window_tables(bp_grid* G) {
     return BP_OK;
 }
 
+namespace {
+
+bpk::GenArgs general_args(const bp_grid* G, const bpk::UpdateArgs& u) {
+    bpk::GenArgs a;
+    memset(&a, 0, sizeof a);
+    a.u = u;
+    a.type_h = G->general ? G->type_h : nullptr;
+    a.type_v = G->general ? G->type_v : nullptr;
+    a.ptr = reinterpret_cast<const int*>(G->gen_tab + G->gen_off[0]);
+    a.ent_x = reinterpret_cast<const int*>(G->gen_tab + G->gen_off[1]);
+    a.ent_f = reinterpret_cast<const float*>(G->gen_tab + G->gen_off[2]);
+    a.ent_w = reinterpret_cast<const double*>(G->gen_tab + G->gen_off[3]);
+    a.mask = reinterpret_cast<const unsigned*>(G->gen_tab + G->gen_off[4]);
+    a.mask_words = G->gen_mask_words;
+    a.n_types = G->gen_types;
+    a.top_k = G->gen_top_k;
+    for (int k = 0; k < G->gen_types; ++k) {
+        a.fbar[k] = G->gen_fbar[k];
+        a.fbar_d[k] = G->gen_fbar_d[k];
+        a.eq10[k] = G->gen_eq10[k];
+    }
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_general_update(const bp_grid* G, const bpk::UpdateArgs& u, int kmode) {
+    return bpk::launch_general(general_args(G, u), kmode, G->stream);
+}
+
 int iterate_general(bp_grid* G, int kmode, int n, int schedule) {
     for (int t = 0; t < n; ++t) {
-        bpk::GenArgs a;
-        memset(&a, 0, sizeof a);
-        if (schedule == BP_SCHED_SYNC) a.u = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
-        else a.u = base_args(G, G->msg[G->cur], G->msg[G->cur], (int)(G->cb_pass & 1));
-        a.type_h = G->general ? G->type_h : nullptr;
-        a.type_v = G->general ? G->type_v : nullptr;
-        a.ptr = reinterpret_cast<const int*>(G->gen_tab + G->gen_off[0]);
-        a.ent_x = reinterpret_cast<const int*>(G->gen_tab + G->gen_off[1]);
-        a.ent_f = reinterpret_cast<const float*>(G->gen_tab + G->gen_off[2]);
-        a.ent_w = reinterpret_cast<const double*>(G->gen_tab + G->gen_off[3]);
-        a.mask = reinterpret_cast<const unsigned*>(G->gen_tab + G->gen_off[4]);
-        a.mask_words = G->gen_mask_words;
-        a.n_types = G->gen_types;
-        a.top_k = G->gen_top_k;
-        for (int k = 0; k < G->gen_types; ++k) {
-            a.fbar[k] = G->gen_fbar[k];
-            a.fbar_d[k] = G->gen_fbar_d[k];
-            a.eq10[k] = G->gen_eq10[k];
-        }
-        hipError_t e = bpk::launch_general(a, kmode, G->stream);
+        const bpk::UpdateArgs u = schedule == BP_SCHED_SYNC
+                                      ? base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1)
+                                      : base_args(G, G->msg[G->cur], G->msg[G->cur], (int)(G->cb_pass & 1));
+        hipError_t e = launch_general_update(G, u, kmode);
         if (e != hipSuccess) return hip_fail(e, "general update launch");
         if (schedule == BP_SCHED_SYNC) G->cur ^= 1;
         else G->cb_pass++;

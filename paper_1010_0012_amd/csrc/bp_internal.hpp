@@ -27,6 +27,7 @@ struct bp_grid {
     float* msg[2] = {nullptr, nullptr};  // synchronous ping-pong buffers
     int cur = 0;                          // buffer holding the current state
     int64_t cb_pass = 0;                  // checkerboard passes since reset
+    bool fuse_sync = true;                // sync iterations run two per launch where compiled
     const float* g = nullptr;
     // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10
     // tables of the window potential built into the workspace's table region
@@ -58,6 +59,9 @@ int hip_fail(hipError_t e, const char* what);
 int check_ready(const bp_grid* G);
 int with_device(const bp_grid* G);
 void invalidate_grad(bp_grid* G);
+// True when the float32 window table has f(d) >= fbar for every |d| <= T
+// (Eq. 11 holds for max-product; otherwise Eq. 10 is needed).
+bool max_product_ok(const bp_grid* G);
 // Launch arguments for one update of G reading `in` and writing `out`
 // (colour < 0: synchronous; 0/1: checkerboard pass of that colour).
 bpk::UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int colour);
@@ -67,6 +71,9 @@ size_t window_table_bytes(int M);
 // n iterations through the general kernel (caller's tables, or the window
 // potential's Eq. 10 tables); schedule sync or checkerboard.
 int iterate_general(bp_grid* G, int kmode, int n, int schedule);
+// One launch of the general kernel with G's tables over the grid, buffers
+// and schedule that u describes (a level of the multi-scale pyramid).
+hipError_t launch_general_update(const bp_grid* G, const bpk::UpdateArgs& u, int kmode);
 // Build the window potential's tables into the workspace table region.
 int build_window_tables(bp_grid* G);
 }  // namespace bpi

@@ -217,6 +217,115 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
     }
 }
 
+// -------------------------------- two synchronous iterations per launch ----
+// Iteration t+1's outgoing messages of p need only p's unary and the four
+// messages its neighbours send it at iteration t, and each of those needs
+// only its sender's unary and three of the sender's inbox rows.  So one
+// group computes p's four incoming messages from the neighbours' inputs
+// (receiver side: every message of iteration t is still computed exactly
+// once), then p's four outgoing messages, and iteration t's messages never
+// reach HBM: a launch reads the unary and the inbox and writes the outbox
+// once for two iterations.  The neighbours' rows are read up to four times,
+// from L2: workgroups are remapped so that each XCD (its own L2) walks a
+// contiguous band of rows.  The arithmetic of both iterations is that of
+// sparse_update_kernel, so the results equal two of its launches bit for
+// bit.
+
+// h of the message a sender sends towards o (Eq. 5, the factor order of
+// make_h_d): horizontal targets ((g mU) mD) m_{opp(o)}, vertical ones
+// ((g mL) mR) m_{opp(o)}.
+__device__ __forceinline__ void sender_h_d(const float (&g)[kLpl], const float (&ma)[kLpl], const float (&mb)[kLpl],
+                                           const float (&mc)[kLpl], double (&h)[kLpl]) {
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) h[i] = (((double)g[i] * ma[i]) * mb[i]) * mc[i];
+}
+
+// Workgroups per XCD band: the hardware deals workgroups to the 8 XCDs in
+// turn, so block b runs on XCD b mod 8; logical block (b mod 8) * per + b / 8
+// gives XCD x the contiguous range [x * per, (x + 1) * per).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_band_block(int b, int per) { return (b % kXcds) * per + b / kXcds; }
+
+// One message in double from explicit tables (sum: dtab = f - fbar in
+// double, fbar_d; max: tab = float32 f, fbar).
+template <int G, int TW, int MODE>
+__device__ __forceinline__ void message_d(const double (&h)[kLpl], const double* dtab, double fbar_d,
+                                          const float* tab, float fbar, int pos, int M, int x0, bool full,
+                                          float (&m)[kLpl]) {
+    if constexpr (MODE == kSum) sum_message_d<G, TW>(h, dtab, fbar_d, pos, M, x0, full, m);
+    else max_message_d<G, TW>(h, tab, fbar, pos, M, x0, full, m);
+}
+
+// Both iterations for one pixel px of an H x W grid (in -> out).  FULL:
+// M == 4G, known at compile time so that no load or normalisation carries a
+// branch.  Loads are unconditional: a missing neighbour (or a missing row of
+// a neighbour's inbox) reads a valid row and is replaced by the factor 1,
+// which keeps every load of the pixel in one basic block.
+template <int G, int TW, int MODE, bool FULL>
+__device__ __forceinline__ void pair_pixel(const float* g, const float* in, float* out, int H, int W, int M,
+                                           const Pixel& px, int pos, const double* dtab, double fbar_d,
+                                           const float* tab, float fbar) {
+    const int x0 = pos * kLpl;
+    const size_t plane = (size_t)H * W * M;
+    // First iteration, receiver side: the message from the neighbour in
+    // direction k (inbox slot k of p).  The sender q sees p in direction
+    // opposite(k) and leaves out its own inbox row from p.
+    float rows[4][4][kLpl];  // [k][g, the two partial-product rows, the opposite row]
+    bool use[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int o = opposite(k);  // direction of p seen from q
+        const int ka = (o == kLeft || o == kRight) ? kUp : kLeft;
+        const int src[3] = {ka, ka + 1, opposite(o)};
+        const int qr = px.has[k] ? px.r + (k == kUp ? -1 : k == kDown ? 1 : 0) : px.r;
+        const int qc = px.has[k] ? px.c + (k == kLeft ? -1 : k == kRight ? 1 : 0) : px.c;
+        const bool qhas[4] = {qc > 0, qc + 1 < W, qr > 0, qr + 1 < H};
+        const size_t qoff = ((size_t)qr * W + qc) * M;
+        load_labels<false>(g + qoff, x0, M, FULL, rows[k][0], 0.0f);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            use[k][j] = qhas[src[j]];
+            load_labels<false>(in + (use[k][j] ? src[j] * plane : 0) + qoff, x0, M, FULL, rows[k][j + 1], 1.0f);
+        }
+    }
+    float gp[kLpl];
+    load_labels<false>(g + (size_t)px.p * M, x0, M, FULL, gp, 0.0f);
+    PixelInputs mid;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) rows[k][j + 1][i] = use[k][j] ? rows[k][j + 1][i] : 1.0f;
+        double h[kLpl];
+        sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
+        message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) mid.m[k][i] = px.has[k] ? mid.m[k][i] : 1.0f;
+    }
+    // Second iteration, sender side, from the messages just computed.
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
+    double h[4][kLpl];
+    make_h_d(mid, h);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        float u[kLpl];
+        message_d<G, TW, MODE>(h[o], dtab, fbar_d, tab, fbar, pos, M, x0, FULL, u);
+        store_message(out, plane, M, W, px, o, x0, FULL, u);
+    }
+}
+
+template <int G, int TW, int MODE, bool FULL>
+__global__ __launch_bounds__(kBlock) void sparse_update2_kernel(UpdateArgs a, int per) {
+    const int b = xcd_band_block(blockIdx.x, per);
+    const int pos = threadIdx.x & (G - 1);
+    const int slot = (b * kBlock + threadIdx.x) / G;
+    const Pixel px = sync_pixel(slot, a.H, a.W, a.N);
+    if (!px.ok) return;  // whole groups only
+    pair_pixel<G, TW, MODE, FULL>(a.g, a.in, a.out, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
+}
+
 // ------------------------------------- sparse update, runtime window ----
 // Same arithmetic for windows wider than the compiled register variants:
 // h is staged in LDS per pixel and the compatible states of each y are

@@ -13,6 +13,11 @@ hipError_t launch_sparse(const UpdateArgs& a, int mode, hipStream_t stream);
 // Window half-width of the register variant launch_sparse would use for
 // (M, T), or -1 for the runtime-window fallback.
 int sparse_variant_tw(int M, int T);
+// Two synchronous iterations in one launch (a.in -> a.out, a.colour < 0),
+// bitwise equal to two launch_sparse calls; sparse2_supported tells whether
+// (M, T) has a compiled register window (otherwise run single launches).
+bool sparse2_supported(int M, int T);
+hipError_t launch_sparse2(const UpdateArgs& a, int mode, hipStream_t stream);
 // Plain O(M^2) update, same contract (M <= 128); dense_lds_need gives the
 // LDS bytes one workgroup needs.
 size_t dense_lds_need(int M, int mode);
@@ -31,6 +36,13 @@ hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream);
 struct FgArgs;
 hipError_t launch_fg_iteration(const FgArgs& a, int mode, hipStream_t stream);
 hipError_t launch_fg_beliefs(const FgArgs& a, float* beliefs, int* labels, hipStream_t stream);
+// Batched two-iteration launch of one code path (bp_launch_batch_pair_*.hip);
+// full: every instance of the launch has M = 4G.
+struct BatchLaunch;
+hipError_t launch_batch_pair_sum(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
+                                 hipStream_t s);
+hipError_t launch_batch_pair_max(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
+                                 hipStream_t s);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

@@ -1,0 +1,11 @@
+// Batched two-iteration sum-product launches (Eq. 7): instantiations.
+#include "bp_batch_pair_dispatch.hpp"
+
+namespace bpk {
+
+hipError_t launch_batch_pair_sum(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
+                                 hipStream_t s) {
+    return launch_batch_pair_arm<kSum>(arm, full, L, grid, parity, s);
+}
+
+}  // namespace bpk

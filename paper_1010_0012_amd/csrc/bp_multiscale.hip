@@ -141,11 +141,14 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
     if (!iters) return fail(BP_EINVAL, "null iteration counts");
     for (int l = 0; l <= levels; ++l)
         if (iters[l] < 0) return fail(BP_EINVAL, "iters[%d] < 0", l);
-    if (G->general) return fail(BP_EUNSUPPORTED, "multi-scale BP takes the truncated-linear potential only");
-    if (mode == BP_MAX_PRODUCT)
-        for (int d = 0; d <= G->T; ++d)
-            if (!(G->tab_f[d] >= G->fbar))
-                return fail(BP_EUNSUPPORTED, "multi-scale max-product needs f >= fbar (Eq. 11)");
+    // Edge type maps describe the finest grid only; one potential shared by
+    // every edge is the same at every level.
+    if (G->general && (G->type_h || G->type_v))
+        return fail(BP_EUNSUPPORTED, "multi-scale BP takes one potential for every edge (no type maps)");
+    // Max-product of the window potential with fbar above some f(d) needs
+    // Eq. 10: the general kernel over the window's tables, as bp_iterate.
+    const bool eq10 = !G->general && mode == BP_MAX_PRODUCT && !max_product_ok(G);
+    const bool general = G->general || eq10;
     size_t need = 0;
     std::vector<Level> L = plan_levels(G, levels, &need);
     if (levels > 0) {
@@ -155,6 +158,7 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
             return fail(BP_ENOMEM, "multi-scale workspace %lld bytes < %zu needed", (long long)ms_bytes, need);
     }
     if ((st = with_device(G))) return st;
+    if (eq10 && (st = build_window_tables(G))) return st;
     const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
     char* base = static_cast<char*>(ms_ws);
     auto unary = [&](int l) { return l == 0 ? G->g : reinterpret_cast<const float*>(base + L[l].unary_off); };
@@ -187,7 +191,10 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
             }
             cur = 0;
         }
-        for (int t = 0; t < iters[l]; ++t) {
+        // synchronous iterations of this level, two per launch where the
+        // window potential has a compiled pair kernel (same bits as singles)
+        const bool pairs = !general && G->fuse_sync && bpk::sparse2_supported(G->M, G->T);
+        for (int t = 0; t < iters[l];) {
             bpk::UpdateArgs a = base_args(G, buf(l, cur), buf(l, cur ^ 1), -1);
             a.g = unary(l);
             a.H = L[l].H;
@@ -195,8 +202,15 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
             a.N = L[l].H * L[l].W;
             a.n_slots = a.N;
             a.half_w = (a.W + 1) / 2;
-            memcpy(a.tab, kmode == bpk::kSum ? G->tab_w : G->tab_f, sizeof a.tab);
-            e = bpk::launch_sparse(a, kmode, G->stream);
+            if (general) {
+                e = launch_general_update(G, a, kmode);
+                t += 1;
+            } else {
+                memcpy(a.tab, kmode == bpk::kSum ? G->tab_w : G->tab_f, sizeof a.tab);
+                const bool two = pairs && iters[l] - t >= 2;
+                e = two ? bpk::launch_sparse2(a, kmode, G->stream) : bpk::launch_sparse(a, kmode, G->stream);
+                t += two ? 2 : 1;
+            }
             if (e != hipSuccess) return hip_fail(e, "multi-scale update launch");
             cur ^= 1;
         }

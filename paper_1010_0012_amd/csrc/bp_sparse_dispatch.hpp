@@ -51,6 +51,47 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Two synchronous iterations per launch (register windows only): the grid
+// is padded to a multiple of the XCD count for the band remap, and M = 4G
+// selects the branch-free full-row instance.
+template <int G, int TW, int MODE>
+hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
+    const int nblk = (int)groups_blocks<G>(a.N);
+    const int per = (nblk + kXcds - 1) / kXcds;
+    if (a.M == G * kLpl)
+        hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, true>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
+                           0, s, a, per);
+    else
+        hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, false>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
+                           0, s, a, per);
+    return hipGetLastError();
+}
+
+template <int G, int MODE, int I = 0>
+hipError_t dispatch2_tw(const UpdateArgs& a, int tw, hipStream_t s) {
+    constexpr int n = sizeof(TwList<G>::v) / sizeof(int);
+    if constexpr (I < n) {
+        constexpr int TW = TwList<G>::v[I];
+        if (tw == TW) return go_sparse2<G, TW, MODE>(a, s);
+        return dispatch2_tw<G, MODE, I + 1>(a, tw, s);
+    } else {
+        return hipErrorInvalidValue;  // no register window: the caller runs single launches
+    }
+}
+
+template <int MODE>
+hipError_t dispatch_sparse2(const UpdateArgs& a, hipStream_t s) {
+    const int tw = sparse_tw(a.M, a.T);
+    switch (lanes_for(a.M)) {
+        case 4: return dispatch2_tw<4, MODE>(a, tw, s);
+        case 8: return dispatch2_tw<8, MODE>(a, tw, s);
+        case 16: return dispatch2_tw<16, MODE>(a, tw, s);
+        case 32: return dispatch2_tw<32, MODE>(a, tw, s);
+        case 64: return dispatch2_tw<64, MODE>(a, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int G, int MODE, int I = 0>
 hipError_t dispatch_tw(const UpdateArgs& a, int tw, hipStream_t s) {
     constexpr int n = sizeof(TwList<G>::v) / sizeof(int);

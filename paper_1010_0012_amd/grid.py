@@ -90,6 +90,10 @@ class Grid:
         self._sync_stream()
         L.bp_reset_messages(self.handle)
 
+    def set_sync_fusion(self, enable):
+        """Two synchronous iterations per launch (default on; same results)."""
+        L.bp_set_sync_fusion(self.handle, enable)
+
     def iterate(self, mode="sum", n_iters=1, schedule="sync", dense=False):
         self._sync_stream()
         fn = L.bp_iterate_dense if dense else L.bp_iterate

@@ -12,12 +12,14 @@ from synth_mrf import CONFIGS, make_config, random_unary
 pytestmark = pytest.mark.gpu
 
 
-def run_ms(g32, M, T, alpha, mode, iters):
+def run_ms(g32, M, T, alpha, mode, iters, fbar=None, csr_types=None, type_maps=None):
     import torch
     from paper_1010_0012_amd.grid import Grid
     H, W, _ = g32.shape
     grid = Grid(H, W)
-    grid.set_potential(M, T, alpha)
+    grid.set_potential(M, T, alpha, fbar)
+    if csr_types is not None:
+        grid.set_sparse_potentials(csr_types, *(type_maps or (None, None)))
     grid.set_unary(torch.from_numpy(np.ascontiguousarray(g32)).cuda())
     grid.iterate_multiscale(mode, iters)
     out = grid.get_messages().cpu().numpy(), grid.beliefs().cpu().numpy(), grid.map_labels().cpu().numpy()
@@ -53,6 +55,49 @@ def test_multiscale(case, mode):
     check_against(tag, gpu, g32, ref, ref32)
 
 
+# (H, W, M, T, alpha, fbar, iters): fbar above f(T), so max-product needs Eq. 10
+EQ10_CASES = [(9, 11, 16, 2, 1.0, 0.3, [2, 3, 4]), (13, 10, 64, 4, 0.5, 0.5, [2, 2, 2, 2]),
+              (7, 6, 128, 8, 0.3, 0.2, [2, 3]), (6, 5, 200, 10, 0.3, 0.1, [1, 2])]
+
+
+@pytest.mark.parametrize("case", EQ10_CASES, ids=lambda c: _id(c[:5] + c[6:]))
+def test_multiscale_eq10(case):
+    """Max-product with fbar above f(T): every level runs Eq. 10."""
+    H, W, M, T, alpha, fbar, iters = case
+    g32 = random_unary(H, W, M, 6100 + EQ10_CASES.index(case))
+    tag = f"multiscale max Eq. 10 {_id(case[:5] + case[6:])} fbar={fbar}"
+    say(tag)
+    gpu = run_ms(g32, M, T, alpha, "max", iters, fbar=fbar)
+    pot = library_potential(M, T, alpha, fbar, "max")
+    g = g32.astype(np.float64)
+    levels = len(iters) - 1
+    ref = oracle_result(g32, ms.run(g, pot, "max", levels, iters, impl=gb.SPLIT))
+    ref32 = oracle_result(g32, ms.run(g, pot, "max", levels, iters, impl=gb.SPLIT, storage=np.float32))
+    check_against(tag, gpu, g32, ref, ref32)
+
+
+@pytest.mark.parametrize("mode,below", [("sum", False), ("sum", True), ("max", False), ("max", True)])
+@pytest.mark.parametrize("case", [(9, 11, 16, 0.2, [2, 3, 4]), (6, 7, 64, 0.08, [2, 2, 3])],
+                         ids=lambda c: "H{}W{}M{}".format(*c[:3]))
+def test_multiscale_general_potential(case, mode, below):
+    """One general sparse-compatible potential on every edge (no type maps):
+    Eq. 7 (sum), Eq. 11 or Eq. 10 (max) at every level."""
+    from test_gpu_general import random_type
+    H, W, M, density, iters = case
+    rng = np.random.default_rng(6200 + M)
+    csr, pot = random_type(rng, M, density, below)
+    g32 = random_unary(H, W, M, 6300 + M)
+    tag = f"multiscale general {mode} below={below} H{H}W{W}M{M}"
+    say(tag)
+    gpu = run_ms(g32, M, 0, 1.0, mode, iters, csr_types=[csr])
+    impl = gb.SPARSE if mode == "sum" else gb.SPLIT
+    g = g32.astype(np.float64)
+    levels = len(iters) - 1
+    ref = oracle_result(g32, ms.run(g, pot, mode, levels, iters, impl=impl))
+    ref32 = oracle_result(g32, ms.run(g, pot, mode, levels, iters, impl=impl, storage=np.float32))
+    check_against(tag, gpu, g32, ref, ref32)
+
+
 def test_zero_levels_is_fresh_plain_solve():
     from bp_gpu_util import run_gpu
     g32 = random_unary(8, 9, 16, 77)
@@ -60,6 +105,26 @@ def test_zero_levels_is_fresh_plain_solve():
     b = run_gpu(g32, 16, 2, 1.0, None, "sum", "sync", 6)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_multiscale_pairs_equal_single_launches(mode):
+    """Levels run two synchronous iterations per launch; the result equals
+    single launches bit for bit (odd and even counts per level)."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    g32 = random_unary(37, 29, 32, 91)
+    out = []
+    for fuse in (True, False):
+        grid = Grid(37, 29)
+        grid.set_potential(32, 3, 0.7)
+        grid.set_sync_fusion(fuse)
+        grid.set_unary(torch.from_numpy(g32).cuda())
+        grid.iterate_multiscale(mode, [5, 2, 3, 4])
+        out.append(grid.get_messages().cpu().numpy())
+        torch.cuda.synchronize()
+        grid.close()
+    np.testing.assert_array_equal(out[0], out[1])
 
 
 def test_multiscale_full_size_sampled():
@@ -122,9 +187,16 @@ def test_multiscale_errors():
         L.bp_multiscale_workspace_bytes(h, 13)
     assert e.value.status == L.BP_EINVAL
     L.bp_iterate_multiscale(h, 0, [1, 1, 1], mws, mb)
-    L.bp_set_potential(h, 8, 2, 1.0, 0.9)                  # fbar above f(2)
-    with pytest.raises(L.BPError) as e:
-        L.bp_iterate_multiscale(h, 1, [1, 1, 1], mws, mb)
+    L.bp_set_potential(h, 8, 2, 1.0, 0.9)                  # fbar above f(2): Eq. 10
+    L.bp_iterate_multiscale(h, 1, [1, 1, 1], mws, mb)
+    from test_gpu_general import window_csr
+    tb = L.bp_sparse_table_bytes(h, [window_csr(8, 2, 1.0, 0.1)] * 2)
+    tabs = torch.empty(tb, dtype=torch.uint8, device="cuda")
+    th = torch.zeros(6, 5, dtype=torch.uint8, device="cuda")
+    tv = torch.ones(5, 6, dtype=torch.uint8, device="cuda")
+    L.bp_set_sparse_potentials(h, [window_csr(8, 2, 1.0, 0.1)] * 2, tabs, tb, th, tv)
+    with pytest.raises(L.BPError) as e:                    # type maps: finest level only
+        L.bp_iterate_multiscale(h, 0, [1, 1, 1], mws, mb)
     assert e.value.status == L.BP_EUNSUPPORTED
     torch.cuda.synchronize()
     L.bp_destroy(h)

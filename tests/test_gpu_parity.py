@@ -123,6 +123,21 @@ def test_checkerboard_interleaves_sync_bitwise(mode):
         np.testing.assert_array_equal(cb[k][older], sync_n1[k][older])
 
 
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("shape", SHAPES, ids=_id)
+def test_sync_pairs_equal_single_launches(shape, mode):
+    """Two synchronous iterations per launch (each pixel first computes the
+    messages sent to it) give the bits of single launches, for even and odd
+    iteration counts; shapes without a register window run single launches."""
+    H, W, M, T, alpha, fbar = shape
+    g32 = random_unary(H, W, M, 300 + SHAPES.index(shape))
+    for n in (2, 5):
+        a = run_gpu(g32, M, T, alpha, fbar, mode, "sync", n, fuse=True)
+        b = run_gpu(g32, M, T, alpha, fbar, mode, "sync", n, fuse=False)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
 def test_deterministic():
     g32 = random_unary(31, 29, 64, 9)
     a = run_gpu(g32, 64, 4, 0.5, None, "sum", "sync", 7)
@@ -257,6 +272,60 @@ def test_stereo480x640_sampled(mode, schedule):
     n = cfg.iters if schedule == "sync" else 2 * cfg.iters
     say(f"stereo480x640 {mode} {schedule} x{n}")
     _sampled_one_step(cfg, g32, mode, schedule, n)
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_stereo480x640_pair_launch_sampled(mode):
+    """The two-iteration launch at full size (the benchmark's launch): from a
+    state S after 40 iterations, one more pair; each sampled output message
+    of pixel p equals the oracle's update of p after its four incoming
+    messages are recomputed from S (rounded to float32 as stored), and the
+    whole result equals two single launches bit for bit."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    cfg = CONFIGS["stereo480x640"]
+    g32, _ = make_config(cfg)
+    H, W, M = g32.shape
+    out = {}
+    for fuse in (True, False):
+        grid = Grid(H, W)
+        grid.set_potential(M, cfg.T, cfg.alpha)
+        grid.set_sync_fusion(fuse)
+        grid.set_unary(torch.from_numpy(g32).cuda())
+        say(f"stereo480x640 {mode} pair launch fuse={fuse}")
+        grid.iterate(mode, 40)
+        prev = grid.get_messages().cpu().numpy().astype(np.float64)
+        grid.iterate(mode, 2)
+        out[fuse] = grid.get_messages().cpu().numpy()
+        torch.cuda.synchronize()
+        grid.close()
+    np.testing.assert_array_equal(out[True], out[False])
+    last = out[True]
+    from bp_gpu_util import library_potential
+    pot = library_potential(M, cfg.T, cfg.alpha, None, mode)
+    g64 = g32.astype(np.float64)
+    rng = np.random.default_rng(12)
+    worst, checked = 0.0, 0
+    while checked < 60:
+        r, c, o = int(rng.integers(0, H)), int(rng.integers(0, W)), int(rng.integers(0, 4))
+        dr, dc = gb.OFFSETS[o]
+        if not (0 <= r + dr < H and 0 <= c + dc < W):
+            continue
+        saved = prev[:, r, c].copy()
+        m1 = {}
+        for k in gb.DIRS:                      # messages into (r, c) after one iteration
+            kr, kc = gb.OFFSETS[k]
+            sr, sc = r + kr, c + kc
+            if 0 <= sr < H and 0 <= sc < W:
+                m1[k] = gb.single_update(g64, prev, pot, mode, sr, sc, gb.OPPOSITE[k])
+        for k, v in m1.items():
+            prev[k, r, c] = v.astype(np.float32).astype(np.float64)
+        want = gb.single_update(g64, prev, pot, mode, r, c, o)
+        prev[:, r, c] = saved
+        worst = max(worst, float(np.max(np.abs(last[gb.OPPOSITE[o], r + dr, c + dc] - want))))
+        checked += 1
+    say(f"stereo480x640 {mode} pair launch: sampled max|dm| = {worst:.2e}")
+    assert worst <= 1e-6
 
 
 def test_stereo480x640_max_dense_equals_sparse():
