@@ -127,10 +127,9 @@ int bp_reset_messages(bp_grid* grid);
  * Eq. 11 equals Eq. 9 only when f >= fbar on every compatible pair (Sec. 5),
  * i.e. fbar <= f(T) as rounded to float32.  Otherwise max-product runs the
  * exact Eq. 10 (the largest h outside each window times fbar) through the
- * general kernel, for the sync and checkerboard schedules; sweeps then
- * return BP_EUNSUPPORTED.  Sum-product accepts any fbar >= 0.
- * After bp_set_sparse_potentials the general kernel runs instead (sync and
- * checkerboard; sweeps and bp_iterate_dense return BP_EUNSUPPORTED). */
+ * general kernel, for every schedule.  Sum-product accepts any fbar >= 0.
+ * After bp_set_sparse_potentials the general kernel runs instead, for every
+ * schedule (bp_iterate_dense returns BP_EUNSUPPORTED). */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
 /* Synchronous iterations of the window potential run two per launch by

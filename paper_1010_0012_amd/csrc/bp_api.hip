@@ -106,8 +106,6 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     const bool eq10 = !G->general && mode == BP_MAX_PRODUCT && !max_product_ok(G) && !dense;
     if (G->general || eq10) {
         if (dense) return fail(BP_EUNSUPPORTED, "the dense kernel takes the truncated-linear potential only");
-        if (schedule == BP_SCHED_SWEEP)
-            return fail(BP_EUNSUPPORTED, "sweeps take the truncated-linear potential with f >= fbar (Eq. 11) only");
         if ((st = with_device(G))) return st;
         if (eq10 && (st = build_window_tables(G))) return st;
         return iterate_general(G, kmode, n, schedule);

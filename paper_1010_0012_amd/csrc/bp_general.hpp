@@ -19,6 +19,7 @@
 #pragma once
 
 #include "bp_kernels.hpp"
+#include "bp_sweep.hpp"
 
 namespace bpk {
 
@@ -77,21 +78,121 @@ constexpr size_t general_lds_bytes(int G) {
     return (size_t)(kBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
 }
 
+// CSR table slot of edge type k for messages travelling towards o: the
+// tables are stored per orientation (towards right/down, towards left/up).
+__device__ __forceinline__ int table_slot(int k, int o) { return 2 * k + ((o == kRight || o == kDown) ? 0 : 1); }
+
+// One message of edge type k towards o from this lane's h (Eq. 7 for sum;
+// Eq. 11, or Eq. 10 where the type needs it, for max), normalised into m.
+// hs, top_v, top_i: this group's LDS rows.  The function holds block
+// barriers, so every thread of the workgroup calls it the same number of
+// times (groups with nothing to send pass any valid type).
+template <int G, int MODE, bool EQ10>
+__device__ __forceinline__ void general_message(const GenArgs& a, int k, int o, const double (&h)[kLpl], double* hs,
+                                                double* top_v, int* top_i, int pos, float (&m)[kLpl]) {
+    const int M = a.u.M;
+    const int x0 = pos * kLpl;
+    const bool full = M == G * kLpl;
+    __syncthreads();  // the previous message is done with hs and the top list
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
+    const int ts = table_slot(k, o);
+    const int* pt = a.ptr + ts * (M + 1);
+    double u[kLpl];
+    if constexpr (MODE == kSum) {
+        __syncthreads();
+        const double base = a.fbar_d[k] * group_sum_d<G>((h[0] + h[1]) + (h[2] + h[3]));
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) {
+            const int y = x0 + i;
+            double acc = base;
+            if (y < M)
+                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(a.ent_w[e], hs[a.ent_x[e]], acc);
+            u[i] = acc;
+        }
+    } else {
+        const double hm = group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
+        const bool topk = EQ10 && a.top_k <= kTopMax;
+        if (topk) {
+            // the top_k largest entries of h, value descending, label ascending
+            double last_v = __builtin_huge_val();
+            int last_i = -1;
+            for (int r = 0; r < a.top_k; ++r) {
+                double bv = -1.0;
+                int bi = 1 << 30;
+#pragma unroll
+                for (int i = 0; i < kLpl; ++i) {
+                    const int y = x0 + i;
+                    const double v = h[i];
+                    const bool after = v < last_v || (v == last_v && y > last_i);
+                    if (y < M && after && (v > bv || (v == bv && y < bi))) { bv = v; bi = y; }
+                }
+                group_argmax_d<G>(bv, bi);
+                if (pos == 0) { top_v[r] = bv; top_i[r] = bi; }
+                last_v = bv;
+                last_i = bi;
+            }
+        }
+        __syncthreads();
+        const double fb = (double)a.fbar[k];
+        const unsigned* mrow = a.mask + (size_t)ts * M * a.mask_words;
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) {
+            const int y = x0 + i;
+            double inside = 0.0;
+            if (y < M)
+                for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)a.ent_f[e] * hs[a.ent_x[e]]);
+            double outside;
+            if (!EQ10 || !a.eq10[k]) {
+                outside = fb * hm;  // Eq. 11: f >= fbar on the list
+            } else if (y >= M) {
+                outside = 0.0;
+            } else {
+                // Eq. 10: fbar times the largest h outside list(y) (0 if the list is everything)
+                const unsigned* row = mrow + (size_t)y * a.mask_words;
+                double c = 0.0;
+                if (topk) {
+                    for (int r = 0; r < a.top_k; ++r) {
+                        const int x = top_i[r];
+                        if (x >= M) break;
+                        if (!((row[x >> 5] >> (x & 31)) & 1u)) { c = top_v[r]; break; }
+                    }
+                } else {
+                    for (int x = 0; x < M; ++x)
+                        if (!((row[x >> 5] >> (x & 31)) & 1u)) c = fmax(c, hs[x]);
+                }
+                outside = fb * c;
+            }
+            u[i] = fmax(inside, outside);
+        }
+    }
+    normalise_d<G>(u, M, x0, full, m);
+}
+
+// LDS rows of one group: h, then (per group) the top values and labels.
+template <int G>
+__device__ __forceinline__ void general_lds_rows(double* lds_d, int groups, int grp, double*& hs, double*& top_v,
+                                                 int*& top_i) {
+    constexpr int CAP = G * kLpl;
+    hs = lds_d + grp * CAP;
+    top_v = lds_d + groups * CAP + grp * kTopMax;
+    top_i = reinterpret_cast<int*>(lds_d + groups * CAP + groups * kTopMax) + grp * kTopMax;
+}
+
 template <int G, int MODE, bool EQ10>
 __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
     extern __shared__ double lds_d[];
-    constexpr int CAP = G * kLpl;
-    constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
     const Pixel px = map_slot(slot, a.u);
     const int M = a.u.M;
     const int x0 = pos * kLpl;
-    const bool full = M == CAP;
-    double* hs = lds_d + grp * CAP;
-    double* top_v = lds_d + RPB * CAP + grp * kTopMax;
-    int* top_i = reinterpret_cast<int*>(lds_d + RPB * CAP + RPB * kTopMax) + grp * kTopMax;
+    const bool full = M == G * kLpl;
+    double* hs;
+    double* top_v;
+    int* top_i;
+    general_lds_rows<G>(lds_d, kBlock / G, grp, hs, top_v, top_i);
     PixelInputs in;
     if (px.ok) load_pixel(a.u, px, x0, full, in); else dummy_pixel(in);
     double h[4][kLpl];
@@ -99,85 +200,43 @@ __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
     const size_t plane = (size_t)a.u.N * M;
 #pragma unroll 1
     for (int o = 0; o < 4; ++o) {
-        __syncthreads();  // the previous direction is done with hs and the top list
-#pragma unroll
-        for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[o][i];
         const bool live = px.ok && px.has[o];
         const int k = live ? edge_type(a, px, o) : 0;
-        const int ts = 2 * k + ((o == kRight || o == kDown) ? 0 : 1);
-        const int* pt = a.ptr + ts * (M + 1);
-        double u[kLpl];
-        if constexpr (MODE == kSum) {
-            __syncthreads();
-            const double base = a.fbar_d[k] * group_sum_d<G>((h[o][0] + h[o][1]) + (h[o][2] + h[o][3]));
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) {
-                const int y = x0 + i;
-                double acc = base;
-                if (y < M)
-                    for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(a.ent_w[e], hs[a.ent_x[e]], acc);
-                u[i] = acc;
-            }
-        } else {
-            const double hm = group_max_d<G>(fmax(fmax(h[o][0], h[o][1]), fmax(h[o][2], h[o][3])));
-            const bool topk = EQ10 && a.top_k <= kTopMax;
-            if (topk) {
-                // the top_k largest entries of h, value descending, label ascending
-                double last_v = __builtin_huge_val();
-                int last_i = -1;
-                for (int r = 0; r < a.top_k; ++r) {
-                    double bv = -1.0;
-                    int bi = 1 << 30;
-#pragma unroll
-                    for (int i = 0; i < kLpl; ++i) {
-                        const int y = x0 + i;
-                        const double v = h[o][i];
-                        const bool after = v < last_v || (v == last_v && y > last_i);
-                        if (y < M && after && (v > bv || (v == bv && y < bi))) { bv = v; bi = y; }
-                    }
-                    group_argmax_d<G>(bv, bi);
-                    if (pos == 0) { top_v[r] = bv; top_i[r] = bi; }
-                    last_v = bv;
-                    last_i = bi;
-                }
-            }
-            __syncthreads();
-            const double fb = (double)a.fbar[k];
-            const unsigned* mrow = a.mask + (size_t)ts * M * a.mask_words;
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) {
-                const int y = x0 + i;
-                double inside = 0.0;
-                if (y < M)
-                    for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)a.ent_f[e] * hs[a.ent_x[e]]);
-                double outside;
-                if (!EQ10 || !a.eq10[k]) {
-                    outside = fb * hm;  // Eq. 11: f >= fbar on the list
-                } else if (y >= M) {
-                    outside = 0.0;
-                } else {
-                    // Eq. 10: fbar times the largest h outside list(y) (0 if the list is everything)
-                    const unsigned* row = mrow + (size_t)y * a.mask_words;
-                    double c = 0.0;
-                    if (topk) {
-                        for (int r = 0; r < a.top_k; ++r) {
-                            const int x = top_i[r];
-                            if (x >= M) break;
-                            if (!((row[x >> 5] >> (x & 31)) & 1u)) { c = top_v[r]; break; }
-                        }
-                    } else {
-                        for (int x = 0; x < M; ++x)
-                            if (!((row[x >> 5] >> (x & 31)) & 1u)) c = fmax(c, hs[x]);
-                    }
-                    outside = fb * c;
-                }
-                u[i] = fmax(inside, outside);
-            }
-        }
         float m[kLpl];
-        normalise_d<G>(u, M, x0, full, m);
+        general_message<G, MODE, EQ10>(a, k, o, h[o], hs, top_v, top_i, pos, m);
         store_message(a.u.out, plane, M, a.u.W, px, o, x0, full, m);
     }
+}
+
+// One directional pass of the sweep schedule (Sec. 6) with general
+// potentials or Eq. 10 (a.u.dir = direction the messages travel, in place):
+// the scanline walk of sweep_pass_kernel with general_message per step.
+constexpr size_t general_sweep_lds_bytes(int G) {
+    return (size_t)(kSweepBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
+}
+
+template <int G, int MODE, bool EQ10>
+__global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a) {
+    extern __shared__ double lds_d[];
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    double* hs;
+    double* top_v;
+    int* top_i;
+    general_lds_rows<G>(lds_d, kSweepBlock / G, grp, hs, top_v, top_i);
+    const int dir = a.u.dir;
+    const bool horiz = dir == kLeft || dir == kRight;
+    const bool live = (int)blockIdx.x * (kSweepBlock / G) + grp < (horiz ? a.u.H : a.u.W);
+    sweep_walk<G>(a.u, [&](const double (&h)[kLpl], int r, int c, float (&m)[kLpl]) {
+        int k = 0;  // groups past the last scanline pass any valid type
+        if (live) {
+            Pixel px;
+            px.r = r;
+            px.c = c;
+            k = edge_type(a, px, dir);  // the sender always has a neighbour towards dir
+        }
+        general_message<G, MODE, EQ10>(a, k, dir, h, hs, top_v, top_i, pos, m);
+    });
 }
 
 }  // namespace bpk

@@ -69,7 +69,7 @@ bpk::UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int col
 // workspace (Eq. 10 fallback of max-product when fbar exceeds f).
 size_t window_table_bytes(int M);
 // n iterations through the general kernel (caller's tables, or the window
-// potential's Eq. 10 tables); schedule sync or checkerboard.
+// potential's Eq. 10 tables); schedule sync, checkerboard or sweep.
 int iterate_general(bp_grid* G, int kmode, int n, int schedule);
 // One launch of the general kernel with G's tables over the grid, buffers
 // and schedule that u describes (a level of the multi-scale pyramid).

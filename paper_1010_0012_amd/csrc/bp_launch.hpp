@@ -31,6 +31,8 @@ size_t sweep_dense_lds_need(int M, int mode);
 // contract as launch_sparse.
 struct GenArgs;
 hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream);
+// One directional sweep pass with general potentials (a.u.dir, in place).
+hipError_t launch_general_sweep(const GenArgs& a, int mode, hipStream_t stream);
 // Factor-graph BP (bp_factor.hip): one synchronous iteration (variable ->
 // factor, then factor -> variable), and the readout.
 struct FgArgs;

@@ -25,7 +25,34 @@ hipError_t general_g(const GenArgs& a, hipStream_t s) {
     }
 }
 
+template <int G, int MODE, bool EQ10>
+hipError_t go_general_sweep(const GenArgs& a, hipStream_t s) {
+    constexpr int LPB = kSweepBlock / G;
+    const int n_lines = (a.u.dir == kLeft || a.u.dir == kRight) ? a.u.H : a.u.W;
+    const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB);
+    hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10>), dim3(blocks), dim3(kSweepBlock),
+                       general_sweep_lds_bytes(G), s, a);
+    return hipGetLastError();
+}
+
+template <int MODE, bool EQ10>
+hipError_t general_sweep_g(const GenArgs& a, hipStream_t s) {
+    switch (lanes_for(a.u.M)) {
+        case 4: return go_general_sweep<4, MODE, EQ10>(a, s);
+        case 8: return go_general_sweep<8, MODE, EQ10>(a, s);
+        case 16: return go_general_sweep<16, MODE, EQ10>(a, s);
+        case 32: return go_general_sweep<32, MODE, EQ10>(a, s);
+        case 64: return go_general_sweep<64, MODE, EQ10>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_general_sweep(const GenArgs& a, int mode, hipStream_t stream) {
+    if (mode == kSum) return general_sweep_g<kSum, false>(a, stream);
+    return a.top_k > 0 ? general_sweep_g<kMax, true>(a, stream) : general_sweep_g<kMax, false>(a, stream);
+}
 
 hipError_t launch_general(const GenArgs& a, int mode, hipStream_t stream) {
     if (a.u.n_slots <= 0) return hipSuccess;

@@ -33,11 +33,15 @@ constexpr size_t sweep_lds_bytes(int G, int M, int mode, int kind) {
                         : (size_t)M * G * kLpl * sizeof(float) + hbytes;
 }
 
-template <int G, int TW, int MODE, int KIND>
-__global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
+// The walk of one pass: group grp of the workgroup takes scanline
+// blockIdx.x * (kSweepBlock / G) + grp.  msg(h, r, c, m) turns the h of the
+// sender at (r, c) into its message m; it may hold block barriers, since
+// every group of the workgroup makes the same number of steps (groups past
+// the last scanline run on dummy inputs and store nothing).
+template <int G, typename Msg>
+__device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     constexpr int CAP = G * kLpl;
     constexpr int LPB = kSweepBlock / G;  // scanlines per workgroup
-    extern __shared__ double lds_d[];
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int dir = a.dir;
@@ -46,7 +50,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
     const int n_lines = horiz ? a.H : a.W;
     const int len = horiz ? a.W : a.H;
     const int line = blockIdx.x * LPB + grp;
-    const bool live = line < n_lines;  // other groups run on dummy inputs and store nothing
+    const bool live = line < n_lines;
     const int x0 = pos * kLpl;
     const bool full = a.M == CAP;
     const size_t plane = (size_t)a.N * a.M;
@@ -55,6 +59,63 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
     const bool has0 = line > 0;                       // up (rows) / left (columns) neighbour
     const bool has1 = line + 1 < (horiz ? a.H : a.W);  // down / right neighbour
     const int step_q = dir == kLeft ? -1 : dir == kRight ? 1 : dir == kUp ? -a.W : a.W;
+
+    auto along = [&](int t) { return forward ? t : len - 1 - t; };  // position of the t-th sender
+    auto sender = [&](int t) {  // pixel index of the t-th sender of this scanline
+        const int s = along(t);
+        return horiz ? line * a.W + s : s * a.W + line;
+    };
+    auto load_raw = [&](int t, float (&gv)[kLpl], float (&m0)[kLpl], float (&m1)[kLpl]) {
+        const size_t off = (size_t)sender(t) * a.M;
+        load_labels<kUnaryNT>(a.g + off, x0, a.M, full, gv, 0.0f);
+        if (has0) load_labels<kMsgNT>(a.in + side0 * plane + off, x0, a.M, full, m0, 1.0f);
+        if (has1) load_labels<kMsgNT>(a.in + side1 * plane + off, x0, a.M, full, m1, 1.0f);
+    };
+
+    const int steps = len - 1;  // the last node of the scanline sends nothing this way
+    // Inputs of the next kAhead senders in flight: a ring of registers,
+    // statically indexed by unrolling the step loop by kAhead.
+    constexpr int kAhead = 4;
+    float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j)
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) rg[j][i] = r0[j][i] = r1[j][i] = 1.0f;
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j)
+        if (live && j < steps) load_raw(j, rg[j], r0[j], r1[j]);
+    for (int t0 = 0; t0 < steps; t0 += kAhead) {
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) {
+            const int t = t0 + j;
+            if (t >= steps) break;  // the same for every group of the workgroup
+            double h[kLpl];  // Eq. 5, in double as in the other updates
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
+            if (live && t + kAhead < steps) load_raw(t + kAhead, rg[j], r0[j], r1[j]);
+            float m[kLpl];
+            const int s = along(t);
+            msg(h, horiz ? line : s, horiz ? s : line, m);
+            if (live) {
+                const int q = sender(t) + step_q;
+                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
+            }
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
+        }
+    }
+}
+
+template <int G, int TW, int MODE, int KIND>
+__global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
+    constexpr int CAP = G * kLpl;
+    extern __shared__ double lds_d[];
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int x0 = pos * kLpl;
+    const bool full = a.M == CAP;
 
     // tables in LDS for the LDS-window and dense forms
     double* dtab = lds_d;                                    // kSweepLds sum: w(d); dense sum: f(d)
@@ -90,103 +151,62 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
         __syncthreads();
     }
 
-    auto sender = [&](int t) {  // pixel index of the t-th sender of this scanline
-        const int s = forward ? t : len - 1 - t;
-        return horiz ? line * a.W + s : s * a.W + line;
-    };
-    auto load_raw = [&](int t, float (&gv)[kLpl], float (&m0)[kLpl], float (&m1)[kLpl]) {
-        const size_t off = (size_t)sender(t) * a.M;
-        load_labels<kUnaryNT>(a.g + off, x0, a.M, full, gv, 0.0f);
-        if (has0) load_labels<kMsgNT>(a.in + side0 * plane + off, x0, a.M, full, m0, 1.0f);
-        if (has1) load_labels<kMsgNT>(a.in + side1 * plane + off, x0, a.M, full, m1, 1.0f);
-    };
-
-    const int steps = len - 1;  // the last node of the scanline sends nothing this way
-    // Inputs of the next kAhead senders in flight: a ring of registers,
-    // statically indexed by unrolling the step loop by kAhead.
-    constexpr int kAhead = 4;
-    float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
+    sweep_walk<G>(a, [&](const double (&h)[kLpl], int, int, float (&m)[kLpl]) {
+        if constexpr (KIND == kSweepReg) {
+            if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
+            else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
+        } else {
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j)
+            for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
+            __syncthreads();
+            double u[kLpl];
+            if constexpr (MODE == kSum) {
+                if constexpr (KIND == kSweepLds) {
+                    double s = (h[0] + h[1]) + (h[2] + h[3]);
+                    s = group_sum_d<G>(s);
+                    const double base = a.fbar_d * s;
 #pragma unroll
-        for (int i = 0; i < kLpl; ++i) rg[j][i] = r0[j][i] = r1[j][i] = 1.0f;
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
-#pragma unroll
-    for (int j = 0; j < kAhead; ++j)
-        if (live && j < steps) load_raw(j, rg[j], r0[j], r1[j]);
-    for (int t0 = 0; t0 < steps; t0 += kAhead) {
-#pragma unroll
-        for (int j = 0; j < kAhead; ++j) {
-            const int t = t0 + j;
-            if (t >= steps) break;  // the same for every group of the workgroup
-            double h[kLpl];  // Eq. 5, in double as in the other updates
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
-            if (live && t + kAhead < steps) load_raw(t + kAhead, rg[j], r0[j], r1[j]);
-            float m[kLpl];
-            if constexpr (KIND == kSweepReg) {
-                if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
-                else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
-            } else {
-#pragma unroll
-                for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
-                __syncthreads();
-                double u[kLpl];
-                if constexpr (MODE == kSum) {
-                    if constexpr (KIND == kSweepLds) {
-                        double s = (h[0] + h[1]) + (h[2] + h[3]);
-                        s = group_sum_d<G>(s);
-                        const double base = a.fbar_d * s;
-#pragma unroll
-                        for (int i = 0; i < kLpl; ++i) {
-                            const int y = x0 + i;
-                            const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                            double acc = base;
-                            for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], hs[x], acc);
-                            u[i] = acc;
-                        }
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
-                        for (int x = 0; x < a.M; ++x) {
-                            const double hx = hs[x];
-#pragma unroll
-                            for (int i = 0; i < kLpl; ++i) u[i] = fma(Fd[x * CAP + x0 + i], hx, u[i]);
-                        }
+                    for (int i = 0; i < kLpl; ++i) {
+                        const int y = x0 + i;
+                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                        double acc = base;
+                        for (int x = lo; x <= hi; ++x) acc = fma(dtab[x > y ? x - y : y - x], hs[x], acc);
+                        u[i] = acc;
                     }
                 } else {
-                    if constexpr (KIND == kSweepLds) {
-                        const double base = (double)a.fbar * group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
 #pragma unroll
-                        for (int i = 0; i < kLpl; ++i) {
-                            const int y = x0 + i;
-                            const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
-                            double acc = base;
-                            for (int x = lo; x <= hi; ++x) acc = fmax(acc, (double)tab[x > y ? x - y : y - x] * hs[x]);
-                            u[i] = acc;
-                        }
-                    } else {
+                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                    for (int x = 0; x < a.M; ++x) {
+                        const double hx = hs[x];
 #pragma unroll
-                        for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
-                        for (int x = 0; x < a.M; ++x) {
-                            const double hx = hs[x];
-#pragma unroll
-                            for (int i = 0; i < kLpl; ++i) u[i] = fmax(u[i], (double)F[x * CAP + x0 + i] * hx);
-                        }
+                        for (int i = 0; i < kLpl; ++i) u[i] = fma(Fd[x * CAP + x0 + i], hx, u[i]);
                     }
                 }
-                normalise_d<G>(u, a.M, x0, full, m);
-                __syncthreads();  // every group done reading hs before the next step writes it
-            }
-            if (live) {
-                const int q = sender(t) + step_q;
-                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
-            }
+            } else {
+                if constexpr (KIND == kSweepLds) {
+                    const double base = (double)a.fbar * group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
 #pragma unroll
-            for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
+                    for (int i = 0; i < kLpl; ++i) {
+                        const int y = x0 + i;
+                        const int lo = max(0, y - a.T), hi = min(a.M - 1, y + a.T);
+                        double acc = base;
+                        for (int x = lo; x <= hi; ++x) acc = fmax(acc, (double)tab[x > y ? x - y : y - x] * hs[x]);
+                        u[i] = acc;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) u[i] = 0.0;
+                    for (int x = 0; x < a.M; ++x) {
+                        const double hx = hs[x];
+#pragma unroll
+                        for (int i = 0; i < kLpl; ++i) u[i] = fmax(u[i], (double)F[x * CAP + x0 + i] * hx);
+                    }
+                }
+            }
+            normalise_d<G>(u, a.M, x0, full, m);
+            __syncthreads();  // every group done reading hs before the next step writes it
         }
-    }
+    });
 }
 
 }  // namespace bpk

@@ -70,7 +70,7 @@ def _id(c):
     return "H{}W{}M{}K{}".format(*c[:4])
 
 
-@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard", "sweep"])
 @pytest.mark.parametrize("mode,below", [("sum", False), ("sum", True), ("max", False), ("max", True)])
 @pytest.mark.parametrize("case", CASES, ids=_id)
 def test_general_potentials(case, mode, below, schedule):
@@ -81,7 +81,7 @@ def test_general_potentials(case, mode, below, schedule):
     tv = rng.integers(0, K, (H - 1, W))
     pot = gb.EdgePotentials([p for _, p in pairs], th, tv)
     g32 = random_unary(H, W, M, 2000 + CASES.index(case))
-    n = 4 if schedule == "sync" else 6
+    n = {"sync": 4, "checkerboard": 6, "sweep": 2}[schedule]
     tag = f"general {mode} below={below} {schedule} {_id(case)}"
     say(tag)
     gpu = run_general(g32, [c for c, _ in pairs], th, tv, mode, schedule, n)
@@ -89,8 +89,9 @@ def test_general_potentials(case, mode, below, schedule):
     check(tag, gpu, g32, M, 0, 1.0, None, mode, schedule, n, impl, pot=pot)
 
 
+@pytest.mark.parametrize("schedule", ["sync", "sweep"])
 @pytest.mark.parametrize("M,T,alpha", [(16, 2, 1.0), (64, 4, 0.5), (128, 8, 0.3), (20, 5, 0.6)])
-def test_window_max_eq10(M, T, alpha):
+def test_window_max_eq10(M, T, alpha, schedule):
     """Truncated-linear max-product with fbar above f(T): Eq. 11 would be
     wrong, the library runs Eq. 10; equal to the oracle's Eq. 10 and, bit
     for bit, to the dense Eq. 9 kernel."""
@@ -98,11 +99,12 @@ def test_window_max_eq10(M, T, alpha):
     H, W = 6, 7
     g32 = random_unary(H, W, M, 3000 + M)
     fbar = float(np.float32(np.exp(-alpha * T) * 1.5 + 0.01))
-    say(f"window max Eq. 10 M={M} T={T} fbar={fbar:.4f}")
-    gs = run_gpu(g32, M, T, alpha, fbar, "max", "sync", 5)
-    check(f"window Eq. 10 M={M}", gs, g32, M, T, alpha, fbar, "max", "sync", 5, gb.SPLIT)
+    n = 5 if schedule == "sync" else 2
+    say(f"window max Eq. 10 {schedule} M={M} T={T} fbar={fbar:.4f}")
+    gs = run_gpu(g32, M, T, alpha, fbar, "max", schedule, n)
+    check(f"window Eq. 10 {schedule} M={M}", gs, g32, M, T, alpha, fbar, "max", schedule, n, gb.SPLIT)
     if M <= 128:
-        gd = run_gpu(g32, M, T, alpha, fbar, "max", "sync", 5, dense=True)
+        gd = run_gpu(g32, M, T, alpha, fbar, "max", schedule, n, dense=True)
         np.testing.assert_array_equal(gs[0], gd[0])
         np.testing.assert_array_equal(gs[1], gd[1])
 
@@ -159,10 +161,10 @@ def test_general_errors():
     L.bp_set_sparse_potentials(h, [good, good], tab, tb, None, None)
     L.bp_iterate(h, L.BP_SUM_PRODUCT, 2, L.BP_SCHED_SYNC)
     L.bp_iterate(h, L.BP_MAX_PRODUCT, 2, L.BP_SCHED_CHECKERBOARD)
-    for fn, sched in ((L.bp_iterate, L.BP_SCHED_SWEEP), (L.bp_iterate_dense, L.BP_SCHED_SYNC)):
-        with pytest.raises(L.BPError) as e:
-            fn(h, L.BP_SUM_PRODUCT, 1, sched)
-        assert e.value.status == L.BP_EUNSUPPORTED
+    L.bp_iterate(h, L.BP_SUM_PRODUCT, 1, L.BP_SCHED_SWEEP)
+    with pytest.raises(L.BPError) as e:
+        L.bp_iterate_dense(h, L.BP_SUM_PRODUCT, 1, L.BP_SCHED_SYNC)
+    assert e.value.status == L.BP_EUNSUPPORTED
     L.bp_set_potential(h, 8, 2, 1.0, L.BP_FBAR_TIED)                      # back to the window
     L.bp_iterate_dense(h, L.BP_SUM_PRODUCT, 1, L.BP_SCHED_SYNC)
     torch.cuda.synchronize()
