@@ -64,6 +64,7 @@ struct UpdateArgs {
     int n_slots;           // pixels (or checkerboard slots) covered by the launch
     int T;                 // truncation (used by the runtime-window kernels)
     int dir;               // sweep pass: direction the messages travel (kLeft .. kDown)
+    int both;              // sweep: 1 = the second half of the grid runs the opposite direction
     float fbar;            // potential outside the window (float32, max-product)
     float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)
     // Sum-product works in double end to end: the potential in double and

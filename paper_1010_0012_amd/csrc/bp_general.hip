@@ -174,12 +174,13 @@ hipError_t launch_general_update(const bp_grid* G, const bpk::UpdateArgs& u, int
 
 int iterate_general(bp_grid* G, int kmode, int n, int schedule) {
     if (schedule == BP_SCHED_SWEEP) {
-        // one sweep = passes with messages travelling left, right, up, down
-        static const int kOrder[4] = {bpk::kLeft, bpk::kRight, bpk::kUp, bpk::kDown};
+        // one sweep = passes left, right, up, down; each axis's two passes
+        // are independent and run as one launch (as in bp_iterate)
         for (int t = 0; t < n; ++t)
-            for (int dir : kOrder) {
+            for (int dir : {bpk::kLeft, bpk::kUp}) {
                 bpk::UpdateArgs u = base_args(G, G->msg[G->cur], G->msg[G->cur], -1);
                 u.dir = dir;
+                u.both = 1;
                 hipError_t e = bpk::launch_general_sweep(general_args(G, u), kmode, G->stream);
                 if (e != hipSuccess) return hip_fail(e, "general sweep pass launch");
             }

@@ -224,10 +224,11 @@ __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a) {
     double* top_v;
     int* top_i;
     general_lds_rows<G>(lds_d, kSweepBlock / G, grp, hs, top_v, top_i);
-    const int dir = a.u.dir;
-    const bool horiz = dir == kLeft || dir == kRight;
-    const bool live = (int)blockIdx.x * (kSweepBlock / G) + grp < (horiz ? a.u.H : a.u.W);
-    sweep_walk<G>(a.u, [&](const double (&h)[kLpl], int r, int c, float (&m)[kLpl]) {
+    int blk, dir0;
+    sweep_block_dir(a.u, blk, dir0);
+    const bool horiz = dir0 == kLeft || dir0 == kRight;
+    const bool live = blk * (kSweepBlock / G) + grp < (horiz ? a.u.H : a.u.W);
+    sweep_walk<G>(a.u, [&](const double (&h)[kLpl], int r, int c, int dir, float (&m)[kLpl]) {
         int k = 0;  // groups past the last scanline pass any valid type
         if (live) {
             Pixel px;

@@ -29,7 +29,7 @@ template <int G, int MODE, bool EQ10>
 hipError_t go_general_sweep(const GenArgs& a, hipStream_t s) {
     constexpr int LPB = kSweepBlock / G;
     const int n_lines = (a.u.dir == kLeft || a.u.dir == kRight) ? a.u.H : a.u.W;
-    const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB);
+    const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB) * (a.u.both ? 2 : 1);
     hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10>), dim3(blocks), dim3(kSweepBlock),
                        general_sweep_lds_bytes(G), s, a);
     return hipGetLastError();

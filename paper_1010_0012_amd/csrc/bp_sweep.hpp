@@ -11,7 +11,8 @@
 // later passes and the readout.  The unary and the two perpendicular inbox
 // messages of a sender do not depend on the carry and are loaded four steps
 // ahead.  A pass writes only the inbox plane opposite to its direction
-// and reads only the two perpendicular planes, so it runs in place.
+// and reads only the two perpendicular planes, so it runs in place, and the
+// two passes of one axis run together in one launch.
 #pragma once
 
 #include "bp_kernels.hpp"
@@ -33,23 +34,36 @@ constexpr size_t sweep_lds_bytes(int G, int M, int mode, int kind) {
                         : (size_t)M * G * kLpl * sizeof(float) + hbytes;
 }
 
+// Direction and scanline block of this workgroup.  The two passes of one
+// axis (left and right, or up and down) read only the two perpendicular
+// inbox planes and write different planes, so one launch can run both:
+// with a.both the second half of the grid runs opposite(a.dir).
+__device__ __forceinline__ void sweep_block_dir(const UpdateArgs& a, int& blk, int& dir) {
+    const int half = a.both ? (int)gridDim.x / 2 : (int)gridDim.x;
+    const bool second = (int)blockIdx.x >= half;
+    blk = second ? (int)blockIdx.x - half : (int)blockIdx.x;
+    dir = second ? opposite(a.dir) : a.dir;
+}
+
 // The walk of one pass: group grp of the workgroup takes scanline
-// blockIdx.x * (kSweepBlock / G) + grp.  msg(h, r, c, m) turns the h of the
-// sender at (r, c) into its message m; it may hold block barriers, since
-// every group of the workgroup makes the same number of steps (groups past
-// the last scanline run on dummy inputs and store nothing).
+// blk * (kSweepBlock / G) + grp (sweep_block_dir).  msg(h, r, c, dir, m)
+// turns the h of the sender at (r, c), sending towards dir, into its message
+// m; it may hold block barriers, since every group of the workgroup makes
+// the same number of steps (groups past the last scanline run on dummy
+// inputs and store nothing).
 template <int G, typename Msg>
 __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     constexpr int CAP = G * kLpl;
     constexpr int LPB = kSweepBlock / G;  // scanlines per workgroup
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int dir = a.dir;
+    int blk, dir;
+    sweep_block_dir(a, blk, dir);
     const bool horiz = dir == kLeft || dir == kRight;
     const bool forward = dir == kRight || dir == kDown;  // senders in increasing index
     const int n_lines = horiz ? a.H : a.W;
     const int len = horiz ? a.W : a.H;
-    const int line = blockIdx.x * LPB + grp;
+    const int line = blk * LPB + grp;
     const bool live = line < n_lines;
     const int x0 = pos * kLpl;
     const bool full = a.M == CAP;
@@ -97,7 +111,7 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
             if (live && t + kAhead < steps) load_raw(t + kAhead, rg[j], r0[j], r1[j]);
             float m[kLpl];
             const int s = along(t);
-            msg(h, horiz ? line : s, horiz ? s : line, m);
+            msg(h, horiz ? line : s, horiz ? s : line, dir, m);
             if (live) {
                 const int q = sender(t) + step_q;
                 store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
@@ -151,7 +165,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
         __syncthreads();
     }
 
-    sweep_walk<G>(a, [&](const double (&h)[kLpl], int, int, float (&m)[kLpl]) {
+    sweep_walk<G>(a, [&](const double (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
         if constexpr (KIND == kSweepReg) {
             if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
             else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);

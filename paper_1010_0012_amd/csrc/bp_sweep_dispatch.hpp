@@ -18,7 +18,7 @@ hipError_t go_sweep(const UpdateArgs& a, hipStream_t s) {
     }
     const int n_lines = (a.dir == kLeft || a.dir == kRight) ? a.H : a.W;
     constexpr int LPB = kSweepBlock / G;
-    const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB);
+    const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB) * (a.both ? 2 : 1);
     hipLaunchKernelGGL((sweep_pass_kernel<G, TW, MODE, KIND>), dim3(blocks), dim3(kSweepBlock), lds, s, a);
     return hipGetLastError();
 }
