@@ -18,6 +18,12 @@ factor analogue of Eq. 6 / Eq. 7) gives
   max: max(fbar * prod_{j != i} H_j, max over C with t_i = x of
        f(t) * prod_{j != i} n_j(t_j)),                 H_j = max_x n_j(x),
 O(C + M) per message; the max form needs f >= fbar on C (as Eq. 11).
+Without that condition the split form (the factor analogue of Eq. 6 /
+Eq. 10) is exact for max-product:
+  max: max(max over C with t_i = x of f(t) * prod_{j != i} n_j(t_j),
+           fbar * max over the completions with t_i = x outside C of
+           prod_{j != i} n_j(t_j)),
+written here by enumerating the completions outside C.
 Schedule: synchronous, every variable->factor message from the current
 factor->variable messages, then every factor->variable message.
 """
@@ -31,7 +37,7 @@ import numpy as np
 from .grid_bp import normalize, stored
 
 SUM, MAX = "sum", "max"
-DENSE, SPARSE = "dense", "sparse"
+DENSE, SPARSE, SPLIT = "dense", "sparse", "split"
 
 
 @dataclass
@@ -133,8 +139,35 @@ def factor_message_sparse(fg, a, i, n, mode):
     return u
 
 
+def factor_message_split(fg, a, i, n, mode):
+    """Max-product: the compatible tuples with their own f, and fbar times the
+    largest product over the completions outside C (enumerated), each
+    product taken left to right as in the dense form.  Sum-product is the
+    sparse form (Eq. 7's analogue is exact for any fbar)."""
+    if mode == SUM:
+        return factor_message_sparse(fg, a, i, n, mode)
+    vs, k = fg.factors[a]
+    ft = fg.types[k]
+    others = [j for j in range(len(vs)) if j != i]
+    listed = {tuple(t) for t in ft.tuples}
+    u = np.zeros(fg.M)
+    for t, f in zip(ft.tuples, ft.values):
+        p = f
+        for j in others:
+            p = p * n[a][j][t[j]]
+        u[t[i]] = max(u[t[i]], p)
+    for t in itertools.product(range(fg.M), repeat=len(vs)):
+        if t in listed:
+            continue
+        p = ft.fbar
+        for j in others:
+            p = p * n[a][j][t[j]]
+        u[t[i]] = max(u[t[i]], p)
+    return u
+
+
 def factor_to_var(fg, n, mode, impl, storage=None):
-    form = factor_message_dense if impl == DENSE else factor_message_sparse
+    form = {DENSE: factor_message_dense, SPARSE: factor_message_sparse, SPLIT: factor_message_split}[impl]
     return [[stored(normalize(form(fg, a, i, n, mode)), storage) for i in range(len(vs))]
             for a, (vs, _) in enumerate(fg.factors)]
 

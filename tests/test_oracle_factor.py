@@ -81,3 +81,44 @@ def test_dense_equals_sparse_on_loopy_graph(mode):
                 np.testing.assert_array_equal(md[a][i], ms_[a][i])
             else:
                 np.testing.assert_allclose(md[a][i], ms_[a][i], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("M,seed", [(2, 11), (3, 12), (3, 13)])
+def test_split_tree_exact_with_values_below_fbar(M, seed):
+    """Max-product with compatible values below fbar: the split form (Eq. 10's
+    factor analogue) gives the exact max-marginals on a tree."""
+    rng = np.random.default_rng(seed)
+    types = [random_type(rng, M, 3, below=True), random_type(rng, M, 3, below=True),
+             random_type(rng, M, 2, below=True)]
+    factors = [((0, 1, 2), 0), ((2, 3, 4), 1), ((2, 5, 6), 0), ((4, 7), 2)]
+    fg = fb.FactorGraph(8, M, factors, types)
+    g = rng.uniform(0.05, 1.0, (8, M))
+    m, _ = fb.run(fg, g, fb.MAX, 8, fb.SPLIT)
+    exact = fb.brute_marginals(fg, g, fb.MAX)
+    np.testing.assert_allclose(fb.beliefs(fg, g, m), exact, atol=1e-12)
+
+
+def test_split_equals_dense_bitwise_below_fbar():
+    rng = np.random.default_rng(14)
+    M = 4
+    types = [random_type(rng, M, 3, 0.3, below=True), random_type(rng, M, 2, 0.5, below=True)]
+    factors = [((0, 1, 2), 0), ((1, 2, 3), 0), ((3, 4, 0), 0), ((4, 1), 1), ((2, 4), 1)]
+    fg = fb.FactorGraph(5, M, factors, types)
+    g = rng.uniform(0.05, 1.0, (5, M))
+    md, _ = fb.run(fg, g, fb.MAX, 6, fb.DENSE)
+    msp, _ = fb.run(fg, g, fb.MAX, 6, fb.SPLIT)
+    for a in range(len(factors)):
+        for i in range(len(factors[a][0])):
+            np.testing.assert_array_equal(md[a][i], msp[a][i])
+
+
+def test_eq11_form_needs_f_at_least_fbar():
+    """A pair factor that is 1 everywhere except f(0, 0) = 0: the message to
+    slot 0 at label 0 is the best n_1 outside label 0.  The split form gets
+    it; the fbar * max n_1 shortcut (valid only for f >= fbar) does not."""
+    t = fb.FactorType(2, np.array([[0, 0]]), np.array([0.0]), 1.0)
+    fg = fb.FactorGraph(2, 2, [((0, 1), 0)], [t])
+    n = [[None, np.array([0.9, 0.1])]]
+    assert fb.factor_message_dense(fg, 0, 0, n, fb.MAX)[0] == pytest.approx(0.1)
+    assert fb.factor_message_split(fg, 0, 0, n, fb.MAX)[0] == pytest.approx(0.1)
+    assert fb.factor_message_sparse(fg, 0, 0, n, fb.MAX)[0] == pytest.approx(0.9)
