@@ -217,7 +217,8 @@ int bp_iterate_multiscale(bp_grid* grid, int32_t mode, int32_t levels, const int
  *   sum: fbar * prod_{j != i} S_j + sum over the tuples with x_i = x of
  *        (f - fbar) * prod_{j != i} n_j(x_j),   S_j = sum of n_j;
  *   max: max(fbar * prod_{j != i} max n_j, max over those tuples of
- *        f * prod_{j != i} n_j(x_j))   (needs f >= fbar on C).
+ *        f * prod_{j != i} n_j(x_j))   (when f >= fbar on C; otherwise the
+ *        split form of bp_fg_iterate).
  * Variable-to-factor messages n are g times the variable's other incoming
  * factor messages (factor order).  One iteration computes every n from the
  * current factor messages, then every factor message (synchronous); every
@@ -250,8 +251,11 @@ int bp_fg_attach_workspace(bp_fgraph* fg, void* dev_ptr, int64_t bytes);
 int bp_fg_set_unary(bp_fgraph* fg, const float* g_dev);
 int bp_fg_reset_messages(bp_fgraph* fg);
 /* n_iters synchronous iterations; dense = 1 visits every tuple (the O(M^K)
- * comparison).  Max-product with some f < fbar in C: BP_EUNSUPPORTED unless
- * dense. */
+ * comparison).  Max-product with some f < fbar in C runs the split form
+ * (Eq. 10's analogue: the listed tuples with their own f, and fbar times
+ * the largest product over the completions outside C), exact and equal to
+ * the dense form bit for bit; it needs at most 31 listed labels of a slot's
+ * other slots per label (else BP_EUNSUPPORTED). */
 int bp_fg_iterate(bp_fgraph* fg, int32_t mode, int32_t n_iters, int32_t dense);
 /* Beliefs (device [n_vars][M], rows sum to 1) and/or MAP labels (device
  * [n_vars] int32, lowest label on ties); either may be NULL. */

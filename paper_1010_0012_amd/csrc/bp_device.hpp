@@ -195,6 +195,46 @@ __device__ __forceinline__ void group_argmax(float& best, int& arg) {
     if constexpr (G >= 64) take(xor32(best), xor32_i(arg));
 }
 
+// (value, label) tournament in double: larger value wins, the lower label
+// breaks ties; the same result on every lane of the group.
+template <int G>
+__device__ __forceinline__ void group_argmax_d(double& best, int& arg) {
+    auto take = [&](double ob, int oa) {
+        if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
+    };
+    take(dpp_d<kQuad1032>(best), dpp_i<kQuad1032>(arg));
+    take(dpp_d<kQuad2301>(best), dpp_i<kQuad2301>(arg));
+    if constexpr (G >= 8) take(dpp_d<kRowHalfMirror>(best), dpp_i<kRowHalfMirror>(arg));
+    if constexpr (G >= 16) take(dpp_d<kRowMirror>(best), dpp_i<kRowMirror>(arg));
+    if constexpr (G >= 32) take(xor16_d(best), xor16_i(arg));
+    if constexpr (G >= 64) take(xor32_d(best), xor32_i(arg));
+}
+
+// The k largest entries of the group's label vector (this lane holds labels
+// x0 .. x0+3 of v, labels >= M ignored), value descending and label
+// ascending on ties; lane 0 of the group writes them to top_v / top_i.  k
+// rounds of the tournament, each taking the best entry after the previous.
+template <int G>
+__device__ __forceinline__ void group_top_k(const double (&v)[kLpl], int M, int x0, int pos, int k, double* top_v,
+                                            int* top_i) {
+    double last_v = __builtin_huge_val();
+    int last_i = -1;
+    for (int r = 0; r < k; ++r) {
+        double bv = -1.0;
+        int bi = 1 << 30;
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) {
+            const int y = x0 + i;
+            const bool after = v[i] < last_v || (v[i] == last_v && y > last_i);
+            if (y < M && after && (v[i] > bv || (v[i] == bv && y < bi))) { bv = v[i]; bi = y; }
+        }
+        group_argmax_d<G>(bv, bi);
+        if (pos == 0) { top_v[r] = bv; top_i[r] = bi; }
+        last_v = bv;
+        last_i = bi;
+    }
+}
+
 // Label shifts inside the group: lane pos receives lane pos-J (from_lower)
 // or pos+J (from_upper) of the same pixel, 0 where that lane does not exist.
 template <int G, int J>

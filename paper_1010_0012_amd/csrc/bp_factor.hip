@@ -2,6 +2,7 @@
 // host-side graph, tables, workspace and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -22,7 +23,9 @@ struct Tables {  // one CSR set (sparse, or the complete dense lists)
     std::vector<int2> ent_o;
     std::vector<float> ent_f;
     std::vector<double> ent_w;
-    size_t off[4] = {};               // device offsets: tptr, ent_o, ent_f, ent_w
+    std::vector<int2> ent_s;          // each row's other-slot labels sorted by (a, b)
+    int top[bpk::kFgMaxTypes][3][2] = {};  // split form's top-list lengths per type and slot
+    size_t off[5] = {};               // device offsets: tptr, ent_o, ent_f, ent_w, ent_s
 };
 
 }  // namespace
@@ -56,6 +59,7 @@ void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const 
     T.ent_o.clear();
     T.ent_f.clear();
     T.ent_w.clear();
+    T.ent_s.clear();
     for (int k = 0; k < F->n_types; ++k) {
         const int K = F->arity[k];
         const size_t C = val[k].size();
@@ -79,6 +83,27 @@ void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const 
                 }
             }
             row[M] = (int)T.ent_o.size();
+            // Sorted copy for the split form's membership tests, and its
+            // top-list lengths: one more than the most first labels listed
+            // in a row (pairs: the most entries), and one more than the
+            // longest run of one first label; at most M.
+            int most_a = 0, most_run = 0;
+            for (int x = 0; x < M; ++x) {
+                std::vector<int2> r(T.ent_o.begin() + row[x], T.ent_o.begin() + row[x + 1]);
+                std::sort(r.begin(), r.end(), [](int2 p, int2 q) { return p.x != q.x ? p.x < q.x : p.y < q.y; });
+                int distinct = 0;
+                for (size_t e = 0; e < r.size();) {
+                    size_t f = e;
+                    while (f < r.size() && r[f].x == r[e].x) ++f;
+                    ++distinct;
+                    most_run = std::max(most_run, (int)(f - e));
+                    e = f;
+                }
+                most_a = std::max(most_a, distinct);
+                T.ent_s.insert(T.ent_s.end(), r.begin(), r.end());
+            }
+            T.top[k][i][0] = std::min(M, most_a + 1);
+            T.top[k][i][1] = K == 3 ? std::min(M, most_run + 1) : 0;
         }
     }
 }
@@ -94,6 +119,7 @@ void layout_tables(Tables& T, size_t& off) {
     T.off[1] = place(off, T.ent_o.size() * sizeof(int2));
     T.off[2] = place(off, T.ent_f.size() * sizeof(float));
     T.off[3] = place(off, T.ent_w.size() * sizeof(double));
+    T.off[4] = place(off, T.ent_s.size() * sizeof(int2));
 }
 
 void copy_tables(const Tables& T, char* img) {
@@ -101,6 +127,7 @@ void copy_tables(const Tables& T, char* img) {
     memcpy(img + T.off[1], T.ent_o.data(), T.ent_o.size() * sizeof(int2));
     memcpy(img + T.off[2], T.ent_f.data(), T.ent_f.size() * sizeof(float));
     memcpy(img + T.off[3], T.ent_w.data(), T.ent_w.size() * sizeof(double));
+    memcpy(img + T.off[4], T.ent_s.data(), T.ent_s.size() * sizeof(int2));
 }
 
 bpk::FgArgs args(const bp_fgraph* F, bool dense) {
@@ -115,6 +142,7 @@ bpk::FgArgs args(const bp_fgraph* F, bool dense) {
     a.ent_o = reinterpret_cast<const int2*>(F->ws + T.off[1]);
     a.ent_f = reinterpret_cast<const float*>(F->ws + T.off[2]);
     a.ent_w = reinterpret_cast<const double*>(F->ws + T.off[3]);
+    a.ent_s = reinterpret_cast<const int2*>(F->ws + T.off[4]);
     a.m_fv = reinterpret_cast<float*>(F->ws + F->off_m);
     a.n_vf = reinterpret_cast<float*>(F->ws + F->off_n);
     a.n_vars = F->n_vars;
@@ -123,6 +151,9 @@ bpk::FgArgs args(const bp_fgraph* F, bool dense) {
     for (int k = 0; k < F->n_types; ++k) {
         a.arity[k] = F->arity[k];
         a.fbar[k] = dense ? 0.0f : F->fbar[k];
+        a.eq10[k] = !dense && !F->eq11_ok[k];  // the complete lists have fbar = 0 <= every f
+        for (int i = 0; i < 3; ++i)
+            for (int q = 0; q < 2; ++q) a.top[k][i][q] = T.top[k][i][q];
     }
     return a;
 }
@@ -314,14 +345,21 @@ int bp_fg_iterate(bp_fgraph* F, int32_t mode, int32_t n_iters, int32_t dense) {
     if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
     if (n_iters < 0) return fail(BP_EINVAL, "n_iters < 0");
     if (dense && !F->has_dense) return fail(BP_ESTATE, "dense tables were not built (bp_fg_init dense_tables = 0)");
+    bool split = false;  // max-product with some f < fbar: the split form (Eq. 10's analogue)
     if (mode == BP_MAX_PRODUCT && !dense)
         for (int k = 0; k < F->n_types; ++k)
-            if (!F->eq11_ok[k])
-                return fail(BP_EUNSUPPORTED, "type %d: max-product needs f >= fbar on the compatible tuples", k);
+            if (!F->eq11_ok[k]) {
+                split = true;
+                for (int i = 0; i < F->arity[k]; ++i)
+                    if (F->sparse.top[k][i][0] > bpk::kFgTop || F->sparse.top[k][i][1] > bpk::kFgTop)
+                        return fail(BP_EUNSUPPORTED,
+                                    "type %d: the split form needs at most %d listed labels per slot and label",
+                                    k, bpk::kFgTop - 1);
+            }
     if ((st = set_dev(F))) return st;
     const bpk::FgArgs a = args(F, dense != 0);
     for (int t = 0; t < n_iters; ++t) {
-        hipError_t e = bpk::launch_fg_iteration(a, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax, F->stream);
+        hipError_t e = bpk::launch_fg_iteration(a, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax, split, F->stream);
         if (e != hipSuccess) return hip_fail(e, "factor-graph launch");
     }
     return BP_OK;
@@ -365,7 +403,7 @@ int bp_fg_destroy(bp_fgraph* F) {
 namespace bpk {
 namespace {
 
-template <int G, int MODE>
+template <int G, int MODE, bool SPLIT>
 hipError_t go_iteration(const FgArgs& a, hipStream_t s) {
     constexpr int RPB = kBlock / G;
     if (a.n_vars > 0) {
@@ -375,8 +413,8 @@ hipError_t go_iteration(const FgArgs& a, hipStream_t s) {
     }
     const int items = a.n_factors * 3;
     if (items > 0) {
-        hipLaunchKernelGGL((fg_factor_kernel<G, MODE>), dim3((items + RPB - 1) / RPB), dim3(kBlock), fg_lds_bytes(G), s,
-                           a);
+        hipLaunchKernelGGL((fg_factor_kernel<G, MODE, SPLIT>), dim3((items + RPB - 1) / RPB), dim3(kBlock),
+                           fg_lds_bytes(G), s, a);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -389,16 +427,21 @@ hipError_t go_beliefs(const FgArgs& a, float* b, int* lab, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int G>
+hipError_t iteration_g(const FgArgs& a, int mode, bool split, hipStream_t s) {
+    if (mode == kSum) return go_iteration<G, kSum, false>(a, s);
+    return split ? go_iteration<G, kMax, true>(a, s) : go_iteration<G, kMax, false>(a, s);
+}
+
 }  // namespace
 
-hipError_t launch_fg_iteration(const FgArgs& a, int mode, hipStream_t s) {
-    const bool sum = mode == kSum;
+hipError_t launch_fg_iteration(const FgArgs& a, int mode, bool split, hipStream_t s) {
     switch (lanes_for(a.M)) {
-        case 4: return sum ? go_iteration<4, kSum>(a, s) : go_iteration<4, kMax>(a, s);
-        case 8: return sum ? go_iteration<8, kSum>(a, s) : go_iteration<8, kMax>(a, s);
-        case 16: return sum ? go_iteration<16, kSum>(a, s) : go_iteration<16, kMax>(a, s);
-        case 32: return sum ? go_iteration<32, kSum>(a, s) : go_iteration<32, kMax>(a, s);
-        default: return sum ? go_iteration<64, kSum>(a, s) : go_iteration<64, kMax>(a, s);
+        case 4: return iteration_g<4>(a, mode, split, s);
+        case 8: return iteration_g<8>(a, mode, split, s);
+        case 16: return iteration_g<16>(a, mode, split, s);
+        case 32: return iteration_g<32>(a, mode, split, s);
+        default: return iteration_g<64>(a, mode, split, s);
     }
 }
 

@@ -11,6 +11,15 @@
 // with S_j = sum n_j and H_j = max n_j (the factor analogue of Eq. 7 and
 // Eq. 11; the max form needs f >= fbar on C).  Products run left to right
 // in double; every message is normalised in double and rounded once.
+// Max-product with some f < fbar in C takes the split form (Eq. 10's
+// analogue): fbar times the largest product over the completions outside
+// C.  With the other slots j < k, that maximum is, over first labels a, the
+// product with the largest n_k(b) such that (a, b) is not listed: for an a
+// with no listed tuple it is max n_k, and the best such a is the first
+// entry of n_j's top list outside the listed a's; for a listed a it is the
+// first entry of n_k's top list outside that a's listed b's.  Products keep
+// the dense form's order, (fbar n_j(a)) n_k(b), and rounding is monotone, so
+// the result equals the dense O(M^K) max bit for bit.
 //
 // Tables: per type and slot i, the tuples grouped by their label at slot i
 // (CSR rows, tuple order kept within a row); each entry holds the labels of
@@ -24,6 +33,7 @@
 namespace bpk {
 
 constexpr int kFgMaxTypes = 16;
+constexpr int kFgTop = 32;  // longest top list of the split form
 
 struct FgArgs {
     const float* g;          // [n_vars][M]
@@ -34,11 +44,14 @@ struct FgArgs {
     const int2* ent_o;       // labels of the other slots (second is -1 for arity 2)
     const float* ent_f;      // f(tuple)
     const double* ent_w;     // f(tuple) - fbar
+    const int2* ent_s;       // the other slots' labels of each row sorted (a, b), for membership tests
     float* m_fv;             // [n_factors * 3][M] factor -> variable
     float* n_vf;             // [n_factors * 3][M] variable -> factor
     int n_vars, n_factors, M;
     int arity[kFgMaxTypes];
     float fbar[kFgMaxTypes];
+    int eq10[kFgMaxTypes];          // max-product takes the split form (some f < fbar in C)
+    int top[kFgMaxTypes][3][2];     // per slot: top-list lengths for the first and second other slot
 };
 
 // variable -> factor: one group of G lanes per variable.
@@ -69,14 +82,65 @@ __global__ __launch_bounds__(kBlock) void fg_var_kernel(FgArgs a) {
     }
 }
 
-constexpr size_t fg_lds_bytes(int G) { return (size_t)(kBlock / G) * 2 * G * kLpl * sizeof(double); }
+// Per group: the other slots' messages (2 x 4G doubles), then the split
+// form's two top lists (values, then labels).
+constexpr size_t fg_lds_bytes(int G) {
+    return (size_t)(kBlock / G) * (2 * G * kLpl * sizeof(double) + 2 * kFgTop * (sizeof(double) + sizeof(int)));
+}
+
+// Is label x among the first slot's labels (w = 0) or the second's (w = 1)
+// of entries [e0, e1) of the sorted list?
+__device__ __forceinline__ bool listed(const int2* s, int e0, int e1, int x, int w) {
+    for (int e = e0; e < e1; ++e)
+        if ((w ? s[e].y : s[e].x) == x) return true;
+    return false;
+}
 
 // factor -> variable: one group per (factor, slot); the other slots' incoming
 // messages are staged in LDS for the tuple gathers.
-template <int G, int MODE>
+// The split form's second term for one label of slot i: fbar times the
+// largest product over the completions outside the label's listed tuples
+// [e0, e1) (ent_s, sorted by (a, b)), or 0 when every completion is listed.
+// top_v / top_i: the other slots' top lists ([0]: first other slot, [kFgTop]:
+// second), n0: the first other slot's message.
+__device__ __forceinline__ double split_outside(const FgArgs& a, int k, int i, int e0, int e1, int n_oth,
+                                               const double* n0, const double* top_v, const int* top_i) {
+    const double fb = (double)a.fbar[k];
+    const int2* s = a.ent_s;
+    double best = 0.0;
+    // first labels a with no listed tuple: the best is the first of the first
+    // other slot's list outside the listed a's, with the largest n_k
+    for (int r = 0; r < a.top[k][i][0]; ++r) {
+        if (!listed(s, e0, e1, top_i[r], 0)) {
+            double p = fb * top_v[r];
+            if (n_oth == 2) p *= top_v[kFgTop];
+            best = fmax(best, p);
+            break;
+        }
+    }
+    if (n_oth == 2) {
+        // each listed a: the first of the second slot's list outside its b's
+        for (int e = e0; e < e1;) {
+            const int x = s[e].x;
+            int f = e;
+            while (f < e1 && s[f].x == x) ++f;
+            for (int r = 0; r < a.top[k][i][1]; ++r) {
+                if (!listed(s, e, f, top_i[kFgTop + r], 1)) {
+                    best = fmax(best, (fb * n0[x]) * top_v[kFgTop + r]);
+                    break;
+                }
+            }
+            e = f;
+        }
+    }
+    return best;
+}
+
+template <int G, int MODE, bool EQ10>
 __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     extern __shared__ double lds_d[];
     constexpr int CAP = G * kLpl;
+    constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int item = (blockIdx.x * kBlock + threadIdx.x) / G;  // a * 3 + i
@@ -88,6 +152,9 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     const int x0 = pos * kLpl;
     const bool full = a.M == CAP;
     double* nj[2] = {lds_d + (size_t)grp * 2 * CAP, lds_d + (size_t)grp * 2 * CAP + CAP};
+    double* top_v = lds_d + (size_t)RPB * 2 * CAP + (size_t)grp * 2 * kFgTop;  // [2][kFgTop]
+    int* top_i = reinterpret_cast<int*>(lds_d + (size_t)RPB * 2 * CAP + (size_t)RPB * 2 * kFgTop) + grp * 2 * kFgTop;
+    const bool split = EQ10 && MODE == kMax && a.eq10[k];
     // the other slots in slot order
     const int j0 = i == 0 ? 1 : 0;
     const int j1 = i == 2 ? 1 : 2;
@@ -102,6 +169,10 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
                                 : fmax(fmax((double)v[0], (double)v[1]), fmax((double)v[2], (double)v[3]));
         r = MODE == kSum ? group_sum_d<G>(r) : group_max_d<G>(r);
         agg[q] = r;
+        if (split && q < n_oth) {  // this slot's top list, value descending
+            const double vd[kLpl] = {v[0], v[1], v[2], v[3]};
+            group_top_k<G>(vd, a.M, x0, pos, a.top[k][i][q], top_v + q * kFgTop, top_i + q * kFgTop);
+        }
     }
     __syncthreads();
     if (!live) return;  // after the only barrier
@@ -113,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
 #pragma unroll
     for (int l = 0; l < kLpl; ++l) {
         const int x = x0 + l;
-        double acc = base;
+        double acc = split ? 0.0 : base;  // the split form replaces the fbar * prod H term
         if (x < a.M) {
             for (int e = row[x]; e < row[x + 1]; ++e) {
                 const int2 o = a.ent_o[e];
@@ -122,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
                 if (n_oth == 2) p *= nj[1][o.y];
                 acc = MODE == kSum ? acc + p : fmax(acc, p);
             }
+            if (split) acc = fmax(acc, split_outside(a, k, i, row[x], row[x + 1], n_oth, nj[0], top_v, top_i));
         }
         u[l] = acc;
     }

@@ -58,21 +58,6 @@ __device__ __forceinline__ int edge_type(const GenArgs& a, const Pixel& px, int 
     return t < a.n_types ? t : a.n_types - 1;
 }
 
-// (value, label) tournament in double: larger value wins, the lower label
-// breaks ties; the same result on every lane of the group.
-template <int G>
-__device__ __forceinline__ void group_argmax_d(double& best, int& arg) {
-    auto take = [&](double ob, int oa) {
-        if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
-    };
-    take(dpp_d<kQuad1032>(best), dpp_i<kQuad1032>(arg));
-    take(dpp_d<kQuad2301>(best), dpp_i<kQuad2301>(arg));
-    if constexpr (G >= 8) take(dpp_d<kRowHalfMirror>(best), dpp_i<kRowHalfMirror>(arg));
-    if constexpr (G >= 16) take(dpp_d<kRowMirror>(best), dpp_i<kRowMirror>(arg));
-    if constexpr (G >= 32) take(xor16_d(best), xor16_i(arg));
-    if constexpr (G >= 64) take(xor32_d(best), xor32_i(arg));
-}
-
 constexpr size_t general_lds_bytes(int G) {
     // per group: h (4G doubles), the top values (kTopMax doubles) and labels (kTopMax ints)
     return (size_t)(kBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
@@ -113,26 +98,7 @@ __device__ __forceinline__ void general_message(const GenArgs& a, int k, int o, 
     } else {
         const double hm = group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
         const bool topk = EQ10 && a.top_k <= kTopMax;
-        if (topk) {
-            // the top_k largest entries of h, value descending, label ascending
-            double last_v = __builtin_huge_val();
-            int last_i = -1;
-            for (int r = 0; r < a.top_k; ++r) {
-                double bv = -1.0;
-                int bi = 1 << 30;
-#pragma unroll
-                for (int i = 0; i < kLpl; ++i) {
-                    const int y = x0 + i;
-                    const double v = h[i];
-                    const bool after = v < last_v || (v == last_v && y > last_i);
-                    if (y < M && after && (v > bv || (v == bv && y < bi))) { bv = v; bi = y; }
-                }
-                group_argmax_d<G>(bv, bi);
-                if (pos == 0) { top_v[r] = bv; top_i[r] = bi; }
-                last_v = bv;
-                last_i = bi;
-            }
-        }
+        if (topk) group_top_k<G>(h, M, x0, pos, a.top_k, top_v, top_i);  // the top_k largest entries of h
         __syncthreads();
         const double fb = (double)a.fbar[k];
         const unsigned* mrow = a.mask + (size_t)ts * M * a.mask_words;

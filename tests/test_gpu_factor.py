@@ -58,10 +58,10 @@ def run_gpu_fg(ctypes_types, fv, ft, n_vars, M, g32, mode, n, dense=False, dense
     return out
 
 
-def compare_fg(tag, gpu, fg, g32, mode, n):
+def compare_fg(tag, gpu, fg, g32, mode, n, impl=fb.SPARSE):
     g = g32.astype(np.float64)
-    m64, _ = fb.run(fg, g, mode, n)
-    m32, _ = fb.run(fg, g, mode, n, storage=np.float32)
+    m64, _ = fb.run(fg, g, mode, n, impl)
+    m32, _ = fb.run(fg, g, mode, n, impl, storage=np.float32)
     b64, b32 = fb.beliefs(fg, g, m64), fb.beliefs(fg, g, m32)
     m_gpu, b_gpu, lab = gpu
 
@@ -102,6 +102,23 @@ def test_sum_with_values_below_fbar():
     types, fv, ft, fg = grid_factor_graph(rng, 3, 4, 6, 0.2, below=True)
     g32 = rng.uniform(0.05, 1.0, (12, 6)).astype(np.float32)
     compare_fg("factor sum below fbar", run_gpu_fg(types, fv, ft, 12, 6, g32, "sum", 5), fg, g32, "sum", 5)
+
+
+@pytest.mark.parametrize("case", [(3, 4, 3, 0.4), (4, 4, 5, 0.2), (3, 5, 8, 0.1), (3, 3, 16, 0.03)],
+                         ids=lambda c: "H{}W{}M{}".format(*c[:3]))
+def test_max_split_form_with_values_below_fbar(case):
+    """Max-product with compatible values below fbar runs the split form
+    (Eq. 10's factor analogue): equal to the oracle's split form and, bit for
+    bit, to the dense O(M^K) kernel."""
+    H, W, M, density = case
+    rng = np.random.default_rng(7400 + M)
+    types, fv, ft, fg = grid_factor_graph(rng, H, W, M, density, below=True)
+    g32 = rng.uniform(0.05, 1.0, (H * W, M)).astype(np.float32)
+    sp = run_gpu_fg(types, fv, ft, H * W, M, g32, "max", 5, dense_tables=True)
+    compare_fg(f"factor max split H{H}W{W}M{M}", sp, fg, g32, "max", 5, fb.SPLIT)
+    dn = run_gpu_fg(types, fv, ft, H * W, M, g32, "max", 5, dense=True, dense_tables=True)
+    np.testing.assert_array_equal(sp[0], dn[0])
+    np.testing.assert_array_equal(sp[1], dn[1])
 
 
 @pytest.mark.parametrize("mode", ["sum", "max"])
@@ -192,9 +209,7 @@ def test_factor_errors():
     G = FactorGraph(5, 4, [[0, 1, 2]], [0], [(3, good[1], good[2], 1.5)])   # f < fbar in C
     G.set_unary(torch.rand(5, 4, device="cuda") + 0.1)
     G.iterate("sum", 2)
-    with pytest.raises(L.BPError) as e:
-        G.iterate("max", 1)
-    assert e.value.status == L.BP_EUNSUPPORTED
+    G.iterate("max", 1)                                                    # the split form
     with pytest.raises(L.BPError) as e:
         G.iterate("sum", 1, dense=True)                                    # no dense tables
     assert e.value.status == L.BP_ESTATE
