@@ -2,6 +2,7 @@
 // pass over unrolled synchronous sum-product BP.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -49,10 +50,10 @@ int grad_checks(const bp_grid* G, int n, int k) {
     return BP_OK;
 }
 
-hipError_t sync_sum_step(bp_grid* G, const float* in, float* out) {
+hipError_t sync_sum_step(bp_grid* G, const float* in, float* out, bool pair = false) {
     bpk::UpdateArgs a = base_args(G, in, out, -1);
     memcpy(a.tab, G->tab_w, sizeof a.tab);
-    return bpk::launch_sparse(a, bpk::kSum, G->stream);
+    return pair ? bpk::launch_sparse2(a, bpk::kSum, G->stream) : bpk::launch_sparse(a, bpk::kSum, G->stream);
 }
 
 }  // namespace
@@ -76,18 +77,24 @@ int bp_forward_ckpt(bp_grid* G, int32_t n_iters, int32_t ckpt_every, void* gws, 
         return fail(BP_ENOMEM, "gradient workspace %lld bytes < %zu needed", (long long)bytes, L.total);
     if ((st = bp_reset_messages(G))) return st;  // also clears any previous gradient state
     char* ws = static_cast<char*>(gws);
-    // Route outputs: the state after iteration t+1 = j*k goes straight into
-    // checkpoint j-1, every other state into a ping-pong buffer, so the
-    // checkpoints cost no copies.
+    // Route outputs: the state after iteration j*k goes straight into
+    // checkpoint j-1, every other kept state into a ping-pong buffer, so the
+    // checkpoints cost no copies.  Between checkpoints no state is kept, so
+    // iterations run two per launch where the pair kernel is compiled (the
+    // same bits as single launches).
+    const bool pairs = G->fuse_sync && bpk::sparse2_supported(G->M, G->T);
     float* src = G->msg[0];
-    for (int t = 0; t < n_iters; ++t) {
-        const int done = t + 1;
+    for (int t = 0; t < n_iters;) {
+        const int boundary = std::min(n_iters, (t / ckpt_every + 1) * ckpt_every);  // next kept state
+        const int step = (pairs && boundary - t >= 2) ? 2 : 1;
+        const int done = t + step;
         float* dst;
         if (done % ckpt_every == 0 && done < n_iters) dst = L.ckpt(ws, done / ckpt_every - 1);
         else dst = (src == G->msg[0]) ? G->msg[1] : G->msg[0];
-        hipError_t e = sync_sum_step(G, src, dst);
+        hipError_t e = sync_sum_step(G, src, dst, step == 2);
         if (e != hipSuccess) return hip_fail(e, "forward update launch");
         src = dst;
+        t = done;
     }
     G->cur = (src == G->msg[0]) ? 0 : 1;
     G->grad_ready = true;
