@@ -154,11 +154,16 @@ __device__ __forceinline__ void window_max_d(const double (&v)[kLpl], const floa
         lo[i] = hi[i] = v[i];
     }
     fill_window_d<G, K, 1>(v, win, pos, lo, hi);
+    // f(d) = f(-d) >= 0 and rounding is monotone, so fl(f * max(a, b)) =
+    // max(fl(f * a), fl(f * b)): the two taps at +-d share one product (the
+    // same bits as taking every tap separately, with 3T+2 instead of 4T+2
+    // double operations per label).
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) {
-        double acc = base;
+        double acc = fmax(base, (double)tab[0] * win[K * kLpl + i]);
 #pragma unroll
-        for (int d = -TW; d <= TW; ++d) acc = fmax(acc, (double)tab[d < 0 ? -d : d] * win[K * kLpl + i + d]);
+        for (int d = 1; d <= TW; ++d)
+            acc = fmax(acc, (double)tab[d] * fmax(win[K * kLpl + i - d], win[K * kLpl + i + d]));
         u[i] = acc;
     }
 }
