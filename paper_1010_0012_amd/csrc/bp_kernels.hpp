@@ -251,6 +251,17 @@ __device__ __forceinline__ void sender_h_d(const float (&g)[kLpl], const float (
 constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_band_block(int b, int per) { return (b % kXcds) * per + b / kXcds; }
 
+// A read-only row of ones: a missing inbox row is loaded from here instead
+// of being replaced after the load (one address select per row instead of
+// one value select per label).
+struct OnesRow {
+    float v[kMaxTab];
+    constexpr OnesRow() : v() {
+        for (int i = 0; i < kMaxTab; ++i) v[i] = 1.0f;
+    }
+};
+static __device__ OnesRow kOnesRow = OnesRow();  // never written
+
 // One message in double from explicit tables (sum: dtab = f - fbar in
 // double, fbar_d; max: tab = float32 f, fbar).
 template <int G, int TW, int MODE>
@@ -276,7 +287,6 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
     // direction k (inbox slot k of p).  The sender q sees p in direction
     // opposite(k) and leaves out its own inbox row from p.
     float rows[4][4][kLpl];  // [k][g, the two partial-product rows, the opposite row]
-    bool use[4][3];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int o = opposite(k);  // direction of p seen from q
@@ -289,8 +299,8 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
         load_labels<false>(g + qoff, x0, M, FULL, rows[k][0], 0.0f);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            use[k][j] = qhas[src[j]];
-            load_labels<false>(in + (use[k][j] ? src[j] * plane : 0) + qoff, x0, M, FULL, rows[k][j + 1], 1.0f);
+            const float* row = qhas[src[j]] ? in + src[j] * plane + qoff : kOnesRow.v;
+            load_labels<false>(row, x0, M, FULL, rows[k][j + 1], 1.0f);
         }
     }
     float gp[kLpl];
@@ -298,10 +308,6 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
     PixelInputs mid;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) rows[k][j + 1][i] = use[k][j] ? rows[k][j + 1][i] : 1.0f;
         double h[kLpl];
         sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
         message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
