@@ -25,6 +25,7 @@ struct Tables {  // one CSR set (sparse, or the complete dense lists)
     std::vector<double> ent_w;
     std::vector<int2> ent_s;          // each row's other-slot labels sorted by (a, b)
     int top[bpk::kFgMaxTypes][3][2] = {};  // split form's top-list lengths per type and slot
+    int most_entries = 0;             // largest (type, slot) table: the entries a workgroup stages
     size_t off[5] = {};               // device offsets: tptr, ent_o, ent_f, ent_w, ent_s
 };
 
@@ -35,6 +36,7 @@ struct bp_fgraph {
     hipStream_t stream = nullptr;
     int n_vars = 0, M = 0, n_factors = 0, n_types = 0;
     std::vector<int> fac_type, var_ptr, var_adj;
+    std::vector<int> items;           // factor messages grouped by (type, slot), runs padded to workgroups
     int arity[bpk::kFgMaxTypes] = {};
     float fbar[bpk::kFgMaxTypes] = {};
     bool eq11_ok[bpk::kFgMaxTypes] = {};  // every compatible f >= fbar
@@ -43,7 +45,7 @@ struct bp_fgraph {
     // device
     char* ws = nullptr;
     int64_t ws_bytes = 0;
-    size_t off_type = 0, off_vptr = 0, off_vadj = 0, off_m = 0, off_n = 0, total = 0;
+    size_t off_type = 0, off_vptr = 0, off_vadj = 0, off_items = 0, off_m = 0, off_n = 0, total = 0;
     std::vector<char> image;          // host source of the table upload
     const float* g = nullptr;
 };
@@ -60,6 +62,7 @@ void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const 
     T.ent_f.clear();
     T.ent_w.clear();
     T.ent_s.clear();
+    T.most_entries = 0;
     for (int k = 0; k < F->n_types; ++k) {
         const int K = F->arity[k];
         const size_t C = val[k].size();
@@ -104,6 +107,7 @@ void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const 
             }
             T.top[k][i][0] = std::min(M, most_a + 1);
             T.top[k][i][1] = K == 3 ? std::min(M, most_run + 1) : 0;
+            T.most_entries = std::max(T.most_entries, row[M] - row[0]);
         }
     }
 }
@@ -143,6 +147,8 @@ bpk::FgArgs args(const bp_fgraph* F, bool dense) {
     a.ent_f = reinterpret_cast<const float*>(F->ws + T.off[2]);
     a.ent_w = reinterpret_cast<const double*>(F->ws + T.off[3]);
     a.ent_s = reinterpret_cast<const int2*>(F->ws + T.off[4]);
+    a.items = reinterpret_cast<const int*>(F->ws + F->off_items);
+    a.n_items = (int)F->items.size();
     a.m_fv = reinterpret_cast<float*>(F->ws + F->off_m);
     a.n_vf = reinterpret_cast<float*>(F->ws + F->off_n);
     a.n_vars = F->n_vars;
@@ -239,6 +245,22 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
             adj[v].push_back(a * 3 + i);
         }
     }
+    // Factor messages grouped by (type, slot), factor order inside a group,
+    // each run padded with -1 to whole workgroups of the factor kernel.
+    const int rpb = bpk::kBlock / bpk::lanes_for(M);
+    for (int k = 0; k < n_types; ++k)
+        for (int i = 0; i < F->arity[k]; ++i) {
+            size_t n = 0;
+            for (int a = 0; a < n_factors; ++a)
+                if (factor_type[a] == k) {
+                    F->items.push_back(a * 3 + i);
+                    ++n;
+                }
+            while (n % rpb) {
+                F->items.push_back(-1);
+                ++n;
+            }
+        }
     F->var_ptr.assign(n_vars + 1, 0);
     for (int v = 0; v < n_vars; ++v) {
         F->var_ptr[v + 1] = F->var_ptr[v] + (int)adj[v].size();
@@ -277,6 +299,7 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
     F->off_type = place(off, (size_t)n_factors * sizeof(int));
     F->off_vptr = place(off, (size_t)(n_vars + 1) * sizeof(int));
     F->off_vadj = place(off, F->var_adj.size() * sizeof(int));
+    F->off_items = place(off, F->items.size() * sizeof(int));
     layout_tables(F->sparse, off);
     if (F->has_dense) layout_tables(F->dense, off);
     const size_t tables_end = off;
@@ -287,6 +310,7 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
     memcpy(F->image.data() + F->off_type, F->fac_type.data(), F->fac_type.size() * sizeof(int));
     memcpy(F->image.data() + F->off_vptr, F->var_ptr.data(), F->var_ptr.size() * sizeof(int));
     memcpy(F->image.data() + F->off_vadj, F->var_adj.data(), F->var_adj.size() * sizeof(int));
+    memcpy(F->image.data() + F->off_items, F->items.data(), F->items.size() * sizeof(int));
     copy_tables(F->sparse, F->image.data());
     if (F->has_dense) copy_tables(F->dense, F->image.data());
     *out = F;
@@ -359,7 +383,8 @@ int bp_fg_iterate(bp_fgraph* F, int32_t mode, int32_t n_iters, int32_t dense) {
     if ((st = set_dev(F))) return st;
     const bpk::FgArgs a = args(F, dense != 0);
     for (int t = 0; t < n_iters; ++t) {
-        hipError_t e = bpk::launch_fg_iteration(a, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax, split, F->stream);
+        hipError_t e = bpk::launch_fg_iteration(a, mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax, split,
+                                                dense ? F->dense.most_entries : F->sparse.most_entries, F->stream);
         if (e != hipSuccess) return hip_fail(e, "factor-graph launch");
     }
     return BP_OK;
@@ -403,18 +428,25 @@ int bp_fg_destroy(bp_fgraph* F) {
 namespace bpk {
 namespace {
 
+// The factor kernel stages its table in LDS when the largest (type, slot)
+// table fits (most_entries <= fg_stage_entries).
 template <int G, int MODE, bool SPLIT>
-hipError_t go_iteration(const FgArgs& a, hipStream_t s) {
+hipError_t go_iteration(const FgArgs& a, int most_entries, hipStream_t s) {
     constexpr int RPB = kBlock / G;
+    constexpr bool kTops = SPLIT && MODE == kMax;
     if (a.n_vars > 0) {
         hipLaunchKernelGGL((fg_var_kernel<G>), dim3((a.n_vars + RPB - 1) / RPB), dim3(kBlock), 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int items = a.n_factors * 3;
-    if (items > 0) {
-        hipLaunchKernelGGL((fg_factor_kernel<G, MODE, SPLIT>), dim3((items + RPB - 1) / RPB), dim3(kBlock),
-                           fg_lds_bytes(G), s, a);
+    if (a.n_items > 0) {
+        const unsigned blocks = (unsigned)(a.n_items / RPB);
+        if ((size_t)most_entries <= fg_stage_entries(G, kTops))
+            hipLaunchKernelGGL((fg_factor_kernel<G, MODE, SPLIT, true>), dim3(blocks), dim3(kBlock),
+                               fg_lds_bytes(G, kTops) + (size_t)most_entries * (sizeof(double) + sizeof(int2)), s, a);
+        else
+            hipLaunchKernelGGL((fg_factor_kernel<G, MODE, SPLIT, false>), dim3(blocks), dim3(kBlock),
+                               fg_lds_bytes(G, kTops), s, a);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -428,20 +460,20 @@ hipError_t go_beliefs(const FgArgs& a, float* b, int* lab, hipStream_t s) {
 }
 
 template <int G>
-hipError_t iteration_g(const FgArgs& a, int mode, bool split, hipStream_t s) {
-    if (mode == kSum) return go_iteration<G, kSum, false>(a, s);
-    return split ? go_iteration<G, kMax, true>(a, s) : go_iteration<G, kMax, false>(a, s);
+hipError_t iteration_g(const FgArgs& a, int mode, bool split, int most_entries, hipStream_t s) {
+    if (mode == kSum) return go_iteration<G, kSum, false>(a, most_entries, s);
+    return split ? go_iteration<G, kMax, true>(a, most_entries, s) : go_iteration<G, kMax, false>(a, most_entries, s);
 }
 
 }  // namespace
 
-hipError_t launch_fg_iteration(const FgArgs& a, int mode, bool split, hipStream_t s) {
+hipError_t launch_fg_iteration(const FgArgs& a, int mode, bool split, int most_entries, hipStream_t s) {
     switch (lanes_for(a.M)) {
-        case 4: return iteration_g<4>(a, mode, split, s);
-        case 8: return iteration_g<8>(a, mode, split, s);
-        case 16: return iteration_g<16>(a, mode, split, s);
-        case 32: return iteration_g<32>(a, mode, split, s);
-        default: return iteration_g<64>(a, mode, split, s);
+        case 4: return iteration_g<4>(a, mode, split, most_entries, s);
+        case 8: return iteration_g<8>(a, mode, split, most_entries, s);
+        case 16: return iteration_g<16>(a, mode, split, most_entries, s);
+        case 32: return iteration_g<32>(a, mode, split, most_entries, s);
+        default: return iteration_g<64>(a, mode, split, most_entries, s);
     }
 }
 

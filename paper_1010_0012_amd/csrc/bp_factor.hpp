@@ -47,6 +47,9 @@ struct FgArgs {
     const int2* ent_s;       // the other slots' labels of each row sorted (a, b), for membership tests
     float* m_fv;             // [n_factors * 3][M] factor -> variable
     float* n_vf;             // [n_factors * 3][M] variable -> factor
+    const int* items;        // factor messages a * 3 + i grouped by (type, slot), each run padded with -1
+                             // to whole workgroups, so a workgroup's messages share one table
+    int n_items;
     int n_vars, n_factors, M;
     int arity[kFgMaxTypes];
     float fbar[kFgMaxTypes];
@@ -83,9 +86,16 @@ __global__ __launch_bounds__(kBlock) void fg_var_kernel(FgArgs a) {
 }
 
 // Per group: the other slots' messages (2 x 4G doubles), then the split
-// form's two top lists (values, then labels).
-constexpr size_t fg_lds_bytes(int G) {
-    return (size_t)(kBlock / G) * (2 * G * kLpl * sizeof(double) + 2 * kFgTop * (sizeof(double) + sizeof(int)));
+// form's two top lists (values, then labels); after them, when the
+// workgroup stages its table, the values (double) and the other slots'
+// labels of its (type, slot) rows.
+constexpr size_t fg_lds_bytes(int G, bool split) {
+    return (size_t)(kBlock / G) * (2 * G * kLpl * sizeof(double) +
+                                   (split ? 2 * kFgTop * (sizeof(double) + sizeof(int)) : 0));
+}
+constexpr size_t kFgStageBytes = 64 * 1024;  // LDS per workgroup when the table is staged
+constexpr size_t fg_stage_entries(int G, bool split) {
+    return (kFgStageBytes - fg_lds_bytes(G, split)) / (sizeof(double) + sizeof(int2));
 }
 
 // Is label x among the first slot's labels (w = 0) or the second's (w = 1)
@@ -136,25 +146,40 @@ __device__ __forceinline__ double split_outside(const FgArgs& a, int k, int i, i
     return best;
 }
 
-template <int G, int MODE, bool EQ10>
+// STAGE: the workgroup first copies its (type, slot) table rows to LDS
+// (values as double: f - fbar for sum, f for max), so the per-entry reads of
+// every message are LDS reads, shared by all of its groups.
+template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     extern __shared__ double lds_d[];
     constexpr int CAP = G * kLpl;
     constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int item = (blockIdx.x * kBlock + threadIdx.x) / G;  // a * 3 + i
-    const int fa = item / 3, i = item - 3 * (item / 3);
-    const bool live_f = fa < a.n_factors;
-    const int k = live_f ? a.fac_type[fa] : 0;
+    const int item = a.items[blockIdx.x * RPB + grp];  // a * 3 + i, or -1
+    const bool live = item >= 0;
+    const int fa = live ? item / 3 : 0, i = live ? item - 3 * (item / 3) : 0;
+    const int k = live ? a.fac_type[fa] : 0;
     const int K = a.arity[k];
-    const bool live = live_f && i < K;
     const int x0 = pos * kLpl;
     const bool full = a.M == CAP;
     double* nj[2] = {lds_d + (size_t)grp * 2 * CAP, lds_d + (size_t)grp * 2 * CAP + CAP};
+    constexpr bool kTops = EQ10 && MODE == kMax;
     double* top_v = lds_d + (size_t)RPB * 2 * CAP + (size_t)grp * 2 * kFgTop;  // [2][kFgTop]
     int* top_i = reinterpret_cast<int*>(lds_d + (size_t)RPB * 2 * CAP + (size_t)RPB * 2 * kFgTop) + grp * 2 * kFgTop;
-    const bool split = EQ10 && MODE == kMax && a.eq10[k];
+    const bool split = kTops && a.eq10[k];
+    // the workgroup's table: every run of items starts a workgroup with a real item
+    const int first = a.items[blockIdx.x * RPB];
+    const int* row0 = a.tptr + ((size_t)a.fac_type[first / 3] * 3 + first % 3) * (a.M + 1);
+    const int e_base = row0[0];
+    double* st_w = lds_d + fg_lds_bytes(G, kTops) / sizeof(double);
+    int2* st_o = reinterpret_cast<int2*>(st_w + (row0[a.M] - e_base));
+    if constexpr (STAGE) {
+        for (int e = threadIdx.x; e < row0[a.M] - e_base; e += kBlock) {
+            st_w[e] = MODE == kSum ? a.ent_w[e_base + e] : (double)a.ent_f[e_base + e];
+            st_o[e] = a.ent_o[e_base + e];
+        }
+    }
     // the other slots in slot order
     const int j0 = i == 0 ? 1 : 0;
     const int j1 = i == 2 ? 1 : 2;
@@ -187,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
         double acc = split ? 0.0 : base;  // the split form replaces the fbar * prod H term
         if (x < a.M) {
             for (int e = row[x]; e < row[x + 1]; ++e) {
-                const int2 o = a.ent_o[e];
-                double p = MODE == kSum ? a.ent_w[e] : (double)a.ent_f[e];
+                const int2 o = STAGE ? st_o[e - e_base] : a.ent_o[e];
+                double p = STAGE ? st_w[e - e_base] : MODE == kSum ? a.ent_w[e] : (double)a.ent_f[e];
                 p *= nj[0][o.x];
                 if (n_oth == 2) p *= nj[1][o.y];
                 acc = MODE == kSum ? acc + p : fmax(acc, p);

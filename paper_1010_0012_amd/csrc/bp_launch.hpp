@@ -36,8 +36,10 @@ hipError_t launch_general_sweep(const GenArgs& a, int mode, hipStream_t stream);
 // Factor-graph BP (bp_factor.hip): one synchronous iteration (variable ->
 // factor, then factor -> variable), and the readout.
 struct FgArgs;
-// split: max-product with the split form (some f < fbar in C).
-hipError_t launch_fg_iteration(const FgArgs& a, int mode, bool split, hipStream_t stream);
+// split: max-product with the split form (some f < fbar in C);
+// most_entries: entries of the largest (type, slot) table (staged in LDS when
+// it fits).
+hipError_t launch_fg_iteration(const FgArgs& a, int mode, bool split, int most_entries, hipStream_t stream);
 hipError_t launch_fg_beliefs(const FgArgs& a, float* beliefs, int* labels, hipStream_t stream);
 // Batched two-iteration launch of one code path (bp_launch_batch_pair_*.hip);
 // full: every instance of the launch has M = 4G.
