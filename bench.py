@@ -266,6 +266,73 @@ def multiscale_leg(grid, cfg, reps=3):
     return out
 
 
+def general_leg(g, cfg, n_iters=20, reps=2):
+    """General sparse compatibility (Sec. 4, Sec. 7) on the benchmark grid:
+    the general kernel on (a) the truncated-linear potential given as a CSR
+    table (against the window kernel on the same problem), (b) four random
+    potential types on the edges, each with about 2T+1 compatible labels
+    per label, and (c) max-product with fbar above f(T) (Eq. 10)."""
+    import numpy as np
+    import torch
+
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M, T = cfg.H, cfg.W, cfg.M, cfg.T
+    updates = cfg.n_directed_edges * M
+    a32 = float(np.float32(cfg.alpha))
+    fbar = float(np.float32(np.exp(-a32 * T)))
+
+    def window_csr(fb):
+        col_ptr, row_idx, val = [0], [], []
+        for y in range(M):
+            for x in range(max(0, y - T), min(M - 1, y + T) + 1):
+                row_idx.append(x)
+                val.append(np.float32(np.exp(-a32 * abs(x - y))))
+            col_ptr.append(len(row_idx))
+        return np.array(col_ptr), np.array(row_idx), np.array(val, dtype=np.float32), fb
+
+    rng = np.random.default_rng(17)
+
+    def random_csr():
+        col_ptr, row_idx, val = [0], [], []
+        for y in range(M):
+            xs = np.sort(rng.choice(M, size=2 * T + 1, replace=False))
+            row_idx += xs.tolist()
+            val += rng.uniform(0.3, 1.0, len(xs)).astype(np.float32).tolist()
+            col_ptr.append(len(row_idx))
+        return np.array(col_ptr), np.array(row_idx), np.array(val, dtype=np.float32), 0.1
+
+    th = torch.from_numpy(rng.integers(0, 4, (H, W - 1)).astype(np.uint8)).cuda()
+    tv = torch.from_numpy(rng.integers(0, 4, (H - 1, W)).astype(np.uint8)).cuda()
+    cases = [("window_as_csr_sum", "sum", None, [window_csr(fbar)], None),
+             ("window_as_csr_max", "max", None, [window_csr(fbar)], None),
+             ("four_types_sum", "sum", None, [random_csr() for _ in range(4)], (th, tv)),
+             ("four_types_max", "max", None, [random_csr() for _ in range(4)], (th, tv)),
+             ("eq10_window_max", "max", 1.5 * fbar, None, None)]
+    out = {}
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, mode, fb, types, maps in cases:
+        grid = Grid(H, W)
+        grid.set_potential(M, T, cfg.alpha, fb)
+        if types is not None:
+            grid.set_sparse_potentials(types, *(maps or (None, None)))
+        grid.set_unary(g)
+        grid.iterate(mode, 2)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            e0.record(s)
+            grid.iterate(mode, n_iters)
+            e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / n_iters)
+        grid.close()
+        out[f"general_{name}_us_per_iter"] = best * 1e3
+        out[f"general_{name}_updates_per_s"] = updates / (best * 1e-3)
+        log(f"bench: general {name}: {best * 1e3:.1f} us per iteration, {updates / (best * 1e-3):.3e} updates/s")
+    return out
+
+
 def factor_leg(reps=3, n_iters=10):
     """Higher-order factors (Sec. 7): a 256 x 256 grid of variables, M = 32,
     triple factors along every row and column with a second-order smoothness
@@ -455,6 +522,7 @@ def main():
     if not args.no_legs:
         extra.update(sweep_leg(grid, cfg))
         extra.update(multiscale_leg(grid, cfg))
+        extra.update(general_leg(g, cfg))
         extra.update(factor_leg())
         extra.update(fbar_zero_leg())
         extra.update(grad_leg())

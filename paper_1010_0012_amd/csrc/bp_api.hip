@@ -100,14 +100,16 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         return fail(BP_EINVAL, "bad schedule %d", schedule);
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
     const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
-    // General sparse potentials, and max-product of the window potential
-    // when fbar exceeds f somewhere (Eq. 11 does not hold; Eq. 10 does), run
-    // the general kernel.
+    // Max-product of the window potential when fbar exceeds f somewhere
+    // (Eq. 11 does not hold; Eq. 10 does) runs the window kernels' Eq. 10
+    // form where a register window is compiled, else the general kernel on
+    // the window's tables; general sparse potentials run the general kernel.
     const bool eq10 = !G->general && mode == BP_MAX_PRODUCT && !max_product_ok(G) && !dense;
-    if (G->general || eq10) {
+    const bool eq10_general = eq10 && bpk::sparse_variant_tw(G->M, G->T) < 0;
+    if (G->general || eq10_general) {
         if (dense) return fail(BP_EUNSUPPORTED, "the dense kernel takes the truncated-linear potential only");
         if ((st = with_device(G))) return st;
-        if (eq10 && (st = build_window_tables(G))) return st;
+        if (eq10_general && (st = build_window_tables(G))) return st;
         return iterate_general(G, kmode, n, schedule);
     }
     if (dense && G->M > 128) return fail(BP_EUNSUPPORTED, "dense kernel supports M <= 128");
@@ -135,6 +137,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
                 UpdateArgs a = base_args(G, G->msg[G->cur], G->msg[G->cur], -1);
                 a.dir = dir;
                 a.both = 1;
+                a.eq10 = eq10;
                 memcpy(a.tab, tab, sizeof a.tab);
                 hipError_t e = bpk::launch_sweep(a, kmode, dense, G->stream);
                 if (e != hipSuccess) return hip_fail(e, "sweep pass launch");
@@ -144,7 +147,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     }
     // Synchronous iterations in pairs: one launch for two (the same bits as
     // two single launches), then a single launch for an odd remainder.
-    if (schedule == BP_SCHED_SYNC && !dense && G->fuse_sync && bpk::sparse2_supported(G->M, G->T)) {
+    if (schedule == BP_SCHED_SYNC && !dense && !eq10 && G->fuse_sync && bpk::sparse2_supported(G->M, G->T)) {
         for (; n >= 2; n -= 2) {
             UpdateArgs a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
             memcpy(a.tab, tab, sizeof a.tab);
@@ -161,6 +164,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
             a = base_args(G, G->msg[G->cur], G->msg[G->cur], (int)(G->cb_pass & 1));
         }
         memcpy(a.tab, tab, sizeof a.tab);
+        a.eq10 = eq10;
         hipError_t e = dense ? bpk::launch_dense(a, kmode, G->stream)
                              : bpk::launch_sparse(a, kmode, G->stream);
         if (e != hipSuccess) return hip_fail(e, dense ? "dense update launch" : "sparse update launch");

@@ -65,6 +65,7 @@ struct UpdateArgs {
     int T;                 // truncation (used by the runtime-window kernels)
     int dir;               // sweep pass: direction the messages travel (kLeft .. kDown)
     int both;              // sweep: 1 = the second half of the grid runs the opposite direction
+    int eq10;              // max-product: some f(d) < fbar, so Eq. 10 (not Eq. 11) holds
     float fbar;            // potential outside the window (float32, max-product)
     float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)
     // Sum-product works in double end to end: the potential in double and
@@ -208,6 +209,15 @@ __device__ __forceinline__ void group_argmax_d(double& best, int& arg) {
     if constexpr (G >= 16) take(dpp_d<kRowMirror>(best), dpp_i<kRowMirror>(arg));
     if constexpr (G >= 32) take(xor16_d(best), xor16_i(arg));
     if constexpr (G >= 64) take(xor32_d(best), xor32_i(arg));
+}
+
+// Order this wave's LDS accesses: writes before the call are visible to
+// every lane of the wave after it.  Enough wherever only the lanes of one
+// G-lane group (G <= 64, so inside one wave) share an LDS row.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // The k largest entries of the group's label vector (this lane holds labels

@@ -96,6 +96,7 @@ void build_image(bp_grid* G, const std::vector<HostType>& types, size_t entries,
     }
     G->gen_types = nt;
     G->gen_mask_words = mw;
+    G->gen_entries = (int)(2 * entries);
     G->gen_top_k = longest_eq10 > 0 ? longest_eq10 + 1 : 0;
     for (int i = 0; i < 5; ++i) G->gen_off[i] = L.off[i];
     G->gen_tab = dev_dst;
@@ -156,6 +157,7 @@ bpk::GenArgs general_args(const bp_grid* G, const bpk::UpdateArgs& u) {
     a.ent_w = reinterpret_cast<const double*>(G->gen_tab + G->gen_off[3]);
     a.mask = reinterpret_cast<const unsigned*>(G->gen_tab + G->gen_off[4]);
     a.mask_words = G->gen_mask_words;
+    a.n_entries = G->gen_entries;
     a.n_types = G->gen_types;
     a.top_k = G->gen_top_k;
     for (int k = 0; k < G->gen_types; ++k) {

@@ -37,6 +37,7 @@ struct GenArgs {
     const unsigned* mask;       // [n_types * 2][M][mask_words]: bit x of row y set iff x in list(y)
     int mask_words;
     int n_types;
+    int n_entries;              // entries of both orientations (ent_x, ent_f, ent_w lengths)
     int top_k;                  // K of the Eq. 10 types (0: none needs Eq. 10)
     float fbar[kMaxTypes];
     double fbar_d[kMaxTypes];
@@ -58,6 +59,62 @@ __device__ __forceinline__ int edge_type(const GenArgs& a, const Pixel& px, int 
     return t < a.n_types ? t : a.n_types - 1;
 }
 
+// The tables a kernel reads: the global arrays, or the copy a workgroup
+// staged in LDS once (labels as bytes, M <= 256; f - fbar for sum, f for
+// max).  Staged, every entry of a row costs LDS reads instead of dependent
+// global loads.
+template <bool STAGE>
+struct GenView {
+    const int* ptr;
+    const double* w;
+    const float* f;
+    const int* x32;
+    const unsigned char* x8;
+    __device__ __forceinline__ int x(int e) const {
+        if constexpr (STAGE) return x8[e];
+        else return x32[e];
+    }
+};
+
+// LDS bytes of the staged tables: row starts, values, labels (8-byte aligned).
+constexpr size_t gen_stage_bytes(int n_types, int M, int n_entries, int mode) {
+    const size_t ptr = ((size_t)n_types * 2 * (M + 1) * sizeof(int) + 7) / 8 * 8;
+    const size_t vals = (size_t)n_entries * (mode == kSum ? sizeof(double) : sizeof(float));
+    return (ptr + vals + (size_t)n_entries + 7) / 8 * 8;
+}
+
+// Stage the tables into LDS at base (all threads of the workgroup; the
+// caller's barrier publishes them), or view the global arrays.
+template <bool STAGE, int MODE, int NT>
+__device__ __forceinline__ GenView<STAGE> gen_view(const GenArgs& a, char* base) {
+    GenView<STAGE> v;
+    if constexpr (STAGE) {
+        const int n_ptr = a.n_types * 2 * (a.u.M + 1);
+        int* ptr = reinterpret_cast<int*>(base);
+        char* vals = base + ((size_t)n_ptr * sizeof(int) + 7) / 8 * 8;
+        unsigned char* x8 =
+            reinterpret_cast<unsigned char*>(vals + (size_t)a.n_entries * (MODE == kSum ? sizeof(double) : sizeof(float)));
+        for (int i = threadIdx.x; i < n_ptr; i += NT) ptr[i] = a.ptr[i];
+        for (int e = threadIdx.x; e < a.n_entries; e += NT) {
+            if constexpr (MODE == kSum) reinterpret_cast<double*>(vals)[e] = a.ent_w[e];
+            else reinterpret_cast<float*>(vals)[e] = a.ent_f[e];
+            x8[e] = (unsigned char)a.ent_x[e];
+        }
+        v.ptr = ptr;
+        v.w = reinterpret_cast<const double*>(vals);
+        v.f = reinterpret_cast<const float*>(vals);
+        v.x8 = x8;
+        v.x32 = nullptr;
+    } else {
+        v.ptr = a.ptr;
+        v.w = a.ent_w;
+        v.f = a.ent_f;
+        v.x32 = a.ent_x;
+        v.x8 = nullptr;
+    }
+    return v;
+}
+
 constexpr size_t general_lds_bytes(int G) {
     // per group: h (4G doubles), the top values (kTopMax doubles) and labels (kTopMax ints)
     return (size_t)(kBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
@@ -69,37 +126,38 @@ __device__ __forceinline__ int table_slot(int k, int o) { return 2 * k + ((o == 
 
 // One message of edge type k towards o from this lane's h (Eq. 7 for sum;
 // Eq. 11, or Eq. 10 where the type needs it, for max), normalised into m.
-// hs, top_v, top_i: this group's LDS rows.  The function holds block
-// barriers, so every thread of the workgroup calls it the same number of
-// times (groups with nothing to send pass any valid type).
-template <int G, int MODE, bool EQ10>
-__device__ __forceinline__ void general_message(const GenArgs& a, int k, int o, const double (&h)[kLpl], double* hs,
-                                                double* top_v, int* top_i, int pos, float (&m)[kLpl]) {
+// hs, top_v, top_i: this group's LDS rows, shared only by the group's lanes
+// (one wave), so wave-level ordering suffices and groups need not call it
+// together.
+template <int G, int MODE, bool EQ10, bool STAGE>
+__device__ __forceinline__ void general_message(const GenArgs& a, const GenView<STAGE>& v, int k, int o,
+                                                const double (&h)[kLpl], double* hs, double* top_v, int* top_i,
+                                                int pos, float (&m)[kLpl]) {
     const int M = a.u.M;
     const int x0 = pos * kLpl;
     const bool full = M == G * kLpl;
-    __syncthreads();  // the previous message is done with hs and the top list
+    wave_sync();  // the previous message is done with hs and the top list
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
     const int ts = table_slot(k, o);
-    const int* pt = a.ptr + ts * (M + 1);
+    const int* pt = v.ptr + ts * (M + 1);
     double u[kLpl];
     if constexpr (MODE == kSum) {
-        __syncthreads();
+        wave_sync();
         const double base = a.fbar_d[k] * group_sum_d<G>((h[0] + h[1]) + (h[2] + h[3]));
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) {
             const int y = x0 + i;
             double acc = base;
             if (y < M)
-                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(a.ent_w[e], hs[a.ent_x[e]], acc);
+                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(v.w[e], hs[v.x(e)], acc);
             u[i] = acc;
         }
     } else {
         const double hm = group_max_d<G>(fmax(fmax(h[0], h[1]), fmax(h[2], h[3])));
         const bool topk = EQ10 && a.top_k <= kTopMax;
         if (topk) group_top_k<G>(h, M, x0, pos, a.top_k, top_v, top_i);  // the top_k largest entries of h
-        __syncthreads();
+        wave_sync();
         const double fb = (double)a.fbar[k];
         const unsigned* mrow = a.mask + (size_t)ts * M * a.mask_words;
 #pragma unroll
@@ -107,7 +165,7 @@ __device__ __forceinline__ void general_message(const GenArgs& a, int k, int o, 
             const int y = x0 + i;
             double inside = 0.0;
             if (y < M)
-                for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)a.ent_f[e] * hs[a.ent_x[e]]);
+                for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)v.f[e] * hs[v.x(e)]);
             double outside;
             if (!EQ10 || !a.eq10[k]) {
                 outside = fb * hm;  // Eq. 11: f >= fbar on the list
@@ -145,9 +203,11 @@ __device__ __forceinline__ void general_lds_rows(double* lds_d, int groups, int 
     top_i = reinterpret_cast<int*>(lds_d + groups * CAP + groups * kTopMax) + grp * kTopMax;
 }
 
-template <int G, int MODE, bool EQ10>
-__global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
+template <int G, int MODE, bool EQ10, bool STAGE>
+__global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
+    const GenView<STAGE> v = gen_view<STAGE, MODE, kBlock>(a, reinterpret_cast<char*>(lds_d));
+    if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
@@ -158,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
     double* hs;
     double* top_v;
     int* top_i;
-    general_lds_rows<G>(lds_d, kBlock / G, grp, hs, top_v, top_i);
+    general_lds_rows<G>(lds_d + stage_bytes / sizeof(double), kBlock / G, grp, hs, top_v, top_i);
     PixelInputs in;
     if (px.ok) load_pixel(a.u, px, x0, full, in); else dummy_pixel(in);
     double h[4][kLpl];
@@ -169,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a) {
         const bool live = px.ok && px.has[o];
         const int k = live ? edge_type(a, px, o) : 0;
         float m[kLpl];
-        general_message<G, MODE, EQ10>(a, k, o, h[o], hs, top_v, top_i, pos, m);
+        general_message<G, MODE, EQ10, STAGE>(a, v, k, o, h[o], hs, top_v, top_i, pos, m);
         store_message(a.u.out, plane, M, a.u.W, px, o, x0, full, m);
     }
 }
@@ -181,15 +241,17 @@ constexpr size_t general_sweep_lds_bytes(int G) {
     return (size_t)(kSweepBlock / G) * (G * kLpl * sizeof(double) + kTopMax * (sizeof(double) + sizeof(int)));
 }
 
-template <int G, int MODE, bool EQ10>
-__global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a) {
+template <int G, int MODE, bool EQ10, bool STAGE>
+__global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
+    const GenView<STAGE> v = gen_view<STAGE, MODE, kSweepBlock>(a, reinterpret_cast<char*>(lds_d));
+    if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     double* hs;
     double* top_v;
     int* top_i;
-    general_lds_rows<G>(lds_d, kSweepBlock / G, grp, hs, top_v, top_i);
+    general_lds_rows<G>(lds_d + stage_bytes / sizeof(double), kSweepBlock / G, grp, hs, top_v, top_i);
     int blk, dir0;
     sweep_block_dir(a.u, blk, dir0);
     const bool horiz = dir0 == kLeft || dir0 == kRight;
@@ -202,7 +264,7 @@ __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a) {
             px.c = c;
             k = edge_type(a, px, dir);  // the sender always has a neighbour towards dir
         }
-        general_message<G, MODE, EQ10>(a, k, dir, h, hs, top_v, top_i, pos, m);
+        general_message<G, MODE, EQ10, STAGE>(a, v, k, dir, h, hs, top_v, top_i, pos, m);
     });
 }
 

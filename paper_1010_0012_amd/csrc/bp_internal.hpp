@@ -33,6 +33,7 @@ struct bp_grid {
     // tables of the window potential built into the workspace's table region
     bool general = false;                 // bp_iterate runs the general kernel on the caller's tables
     int gen_types = 0, gen_top_k = 0, gen_mask_words = 0;
+    int gen_entries = 0;                  // table entries of both orientations
     float gen_fbar[16] = {};
     double gen_fbar_d[16] = {};
     int gen_eq10[16] = {};

@@ -183,6 +183,55 @@ __device__ __forceinline__ void max_message_d(const double (&h)[kLpl], const flo
     normalise_d<G>(u, M, x0, full, m);
 }
 
+// Eq. 10 for the window potential (some f(d) < fbar): u(y) = max(max over
+// |d| <= T of f(d) h(y+d), fbar * max over |x - y| > T of h(x)).  The
+// complement maximum is max(P(y - T - 1), S(y + T + 1)), P and S the prefix
+// and suffix maxima of h over the labels (0 past either end).  The lanes'
+// block maxima go through the group's LDS row (G reads per lane for the
+// scans), then P and S go through it for the shifted reads.  Both parts are
+// maxima of the rounded products Eq. 9's max takes (fbar * max h = max of
+// fbar * h, rounding being monotone), so the result equals the dense
+// kernel's bit for bit.
+constexpr int eq10_row_doubles(int G) { return G + 2 * G * kLpl; }
+
+template <int G, int TW>
+__device__ __forceinline__ void max_message_eq10_d(const double (&h)[kLpl], const float* tab, float fbar, int T,
+                                                   int pos, int M, int x0, bool full, double* row, float (&m)[kLpl]) {
+    constexpr int CAP = G * kLpl;
+    double* lm = row;     // [G] block maxima
+    double* P = row + G;  // [CAP] prefix maxima
+    double* S = P + CAP;  // [CAP] suffix maxima
+    wave_sync();          // the previous message is done with the row
+    lm[pos] = fmax(fmax(h[0], h[1]), fmax(h[2], h[3]));
+    wave_sync();
+    double before = 0.0, after = 0.0;
+    for (int j = 0; j < G; ++j) {
+        const double v = lm[j];
+        if (j < pos) before = fmax(before, v);
+        if (j > pos) after = fmax(after, v);
+    }
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        before = fmax(before, h[i]);
+        P[x0 + i] = before;
+    }
+#pragma unroll
+    for (int i = kLpl - 1; i >= 0; --i) {
+        after = fmax(after, h[i]);
+        S[x0 + i] = after;
+    }
+    wave_sync();
+    double u[kLpl];
+    window_max_d<G, TW>(h, tab, 0.0, pos, u);
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        const int lo = x0 + i - T - 1, hi = x0 + i + T + 1;
+        const double out = fmax(lo >= 0 ? P[lo] : 0.0, hi < M ? S[hi] : 0.0);
+        u[i] = fmax(u[i], (double)fbar * out);
+    }
+    normalise_d<G>(u, M, x0, full, m);
+}
+
 // Double weights w(d) = f(d) - fbar for d <= T (f(d) = exp(-alpha d)) built
 // on the device, for kernels whose windows reach past the argument table.
 __device__ __forceinline__ double weight_d(const UpdateArgs& a, int d) {
@@ -200,8 +249,10 @@ __device__ __forceinline__ float group_total(const float (&v)[kLpl]) {
 
 // Grid-wide update, register window.  One group of G lanes per sending
 // pixel; a wave's load and store instructions cover 64/G consecutive pixels.
-template <int G, int TW, int MODE>
+// EQ10: max-product with Eq. 10 (max_message_eq10_d, one LDS row per group).
+template <int G, int TW, int MODE, bool EQ10 = false>
 __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
+    extern __shared__ double lds_d[];
     const int pos = threadIdx.x & (G - 1);
     const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
     const Pixel px = map_slot(slot, a);
@@ -217,6 +268,9 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
     for (int o = 0; o < 4; ++o) {
         float u[kLpl];
         if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], a.dtab, a.fbar_d, pos, a.M, x0, full, u);
+        else if constexpr (EQ10)
+            max_message_eq10_d<G, TW>(h[o], a.tab, a.fbar, a.T, pos, a.M, x0, full,
+                                      lds_d + (threadIdx.x / G) * eq10_row_doubles(G), u);
         else max_message_d<G, TW>(h[o], a.tab, a.fbar, pos, a.M, x0, full, u);
         store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
     }

@@ -5,11 +5,20 @@
 namespace bpk {
 namespace {
 
+// Tables are staged in LDS when they fit beside the per-group rows within
+// this budget per workgroup.
+constexpr size_t kGenLdsBudget = 64 * 1024;
+
 template <int G, int MODE, bool EQ10>
 hipError_t go_general(const GenArgs& a, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.u.n_slots + (kBlock / G) - 1) / (kBlock / G));
-    hipLaunchKernelGGL((general_update_kernel<G, MODE, EQ10>), dim3(blocks), dim3(kBlock), general_lds_bytes(G), s,
-                       a);
+    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries, MODE);
+    if (st + general_lds_bytes(G) <= kGenLdsBudget)
+        hipLaunchKernelGGL((general_update_kernel<G, MODE, EQ10, true>), dim3(blocks), dim3(kBlock),
+                           st + general_lds_bytes(G), s, a, (int)st);
+    else
+        hipLaunchKernelGGL((general_update_kernel<G, MODE, EQ10, false>), dim3(blocks), dim3(kBlock),
+                           general_lds_bytes(G), s, a, 0);
     return hipGetLastError();
 }
 
@@ -30,8 +39,13 @@ hipError_t go_general_sweep(const GenArgs& a, hipStream_t s) {
     constexpr int LPB = kSweepBlock / G;
     const int n_lines = (a.u.dir == kLeft || a.u.dir == kRight) ? a.u.H : a.u.W;
     const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB) * (a.u.both ? 2 : 1);
-    hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10>), dim3(blocks), dim3(kSweepBlock),
-                       general_sweep_lds_bytes(G), s, a);
+    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries, MODE);
+    if (st + general_sweep_lds_bytes(G) <= kGenLdsBudget)
+        hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10, true>), dim3(blocks), dim3(kSweepBlock),
+                           st + general_sweep_lds_bytes(G), s, a, (int)st);
+    else
+        hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10, false>), dim3(blocks), dim3(kSweepBlock),
+                           general_sweep_lds_bytes(G), s, a, 0);
     return hipGetLastError();
 }
 

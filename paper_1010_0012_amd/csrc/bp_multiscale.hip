@@ -146,9 +146,11 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
     if (G->general && (G->type_h || G->type_v))
         return fail(BP_EUNSUPPORTED, "multi-scale BP takes one potential for every edge (no type maps)");
     // Max-product of the window potential with fbar above some f(d) needs
-    // Eq. 10: the general kernel over the window's tables, as bp_iterate.
+    // Eq. 10: the window kernel's Eq. 10 form, or the general kernel over
+    // the window's tables beyond the register windows (as bp_iterate).
     const bool eq10 = !G->general && mode == BP_MAX_PRODUCT && !max_product_ok(G);
-    const bool general = G->general || eq10;
+    const bool eq10_general = eq10 && bpk::sparse_variant_tw(G->M, G->T) < 0;
+    const bool general = G->general || eq10_general;
     size_t need = 0;
     std::vector<Level> L = plan_levels(G, levels, &need);
     if (levels > 0) {
@@ -158,7 +160,7 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
             return fail(BP_ENOMEM, "multi-scale workspace %lld bytes < %zu needed", (long long)ms_bytes, need);
     }
     if ((st = with_device(G))) return st;
-    if (eq10 && (st = build_window_tables(G))) return st;
+    if (eq10_general && (st = build_window_tables(G))) return st;
     const int kmode = mode == BP_SUM_PRODUCT ? bpk::kSum : bpk::kMax;
     char* base = static_cast<char*>(ms_ws);
     auto unary = [&](int l) { return l == 0 ? G->g : reinterpret_cast<const float*>(base + L[l].unary_off); };
@@ -193,7 +195,7 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
         }
         // synchronous iterations of this level, two per launch where the
         // window potential has a compiled pair kernel (same bits as singles)
-        const bool pairs = !general && G->fuse_sync && bpk::sparse2_supported(G->M, G->T);
+        const bool pairs = !general && !eq10 && G->fuse_sync && bpk::sparse2_supported(G->M, G->T);
         for (int t = 0; t < iters[l];) {
             bpk::UpdateArgs a = base_args(G, buf(l, cur), buf(l, cur ^ 1), -1);
             a.g = unary(l);
@@ -207,6 +209,7 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
                 t += 1;
             } else {
                 memcpy(a.tab, kmode == bpk::kSum ? G->tab_w : G->tab_f, sizeof a.tab);
+                a.eq10 = eq10;
                 const bool two = pairs && iters[l] - t >= 2;
                 e = two ? bpk::launch_sparse2(a, kmode, G->stream) : bpk::launch_sparse(a, kmode, G->stream);
                 t += two ? 2 : 1;

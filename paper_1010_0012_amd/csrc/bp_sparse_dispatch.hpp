@@ -39,6 +39,13 @@ unsigned groups_blocks(int n_slots) {
 
 template <int G, int TW, int MODE>
 hipError_t go_sparse(const UpdateArgs& a, hipStream_t s) {
+    if constexpr (MODE == kMax) {
+        if (a.eq10) {  // Eq. 10: one LDS row per group
+            hipLaunchKernelGGL((sparse_update_kernel<G, TW, kMax, true>), dim3(groups_blocks<G>(a.n_slots)),
+                               dim3(kBlock), (size_t)(kBlock / G) * eq10_row_doubles(G) * sizeof(double), s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((sparse_update_kernel<G, TW, MODE>), dim3(groups_blocks<G>(a.n_slots)), dim3(kBlock), 0,
                        s, a);
     return hipGetLastError();
@@ -46,6 +53,7 @@ hipError_t go_sparse(const UpdateArgs& a, hipStream_t s) {
 
 template <int G, int MODE>
 hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
+    if (a.eq10) return hipErrorInvalidValue;  // Eq. 10 beyond the register windows runs the general kernel
     hipLaunchKernelGGL((sparse_update_wide_kernel<G, MODE>), dim3(groups_blocks<G>(a.n_slots)), dim3(kBlock),
                        wide_lds_bytes(G), s, a);
     return hipGetLastError();

@@ -22,13 +22,15 @@ namespace bpk {
 constexpr int kSweepBlock = 64;  // one wave per workgroup: a pass has only H (or W) scanlines
 
 // How a sender's message is computed: register window (the O(mM) update),
-// LDS window with a runtime bound (wide T), or the dense O(M^2) form.
-enum SweepKind { kSweepReg = 0, kSweepLds = 1, kSweepDense = 2 };
+// LDS window with a runtime bound (wide T), the dense O(M^2) form, or the
+// register window with Eq. 10 for max-product (max_message_eq10_d).
+enum SweepKind { kSweepReg = 0, kSweepLds = 1, kSweepDense = 2, kSweepRegEq10 = 3 };
 
 // LDS: the potential tables and each group's h (double).
 constexpr size_t sweep_lds_bytes(int G, int M, int mode, int kind) {
     const size_t hbytes = (size_t)kSweepBlock * kLpl * sizeof(double);
     return kind == kSweepReg ? 0
+         : kind == kSweepRegEq10 ? (size_t)(kSweepBlock / G) * eq10_row_doubles(G) * sizeof(double)
          : kind == kSweepLds ? kMaxTab * sizeof(double) + kMaxTab * sizeof(float) + hbytes
          : mode == kSum ? kMaxTab * sizeof(double) + (size_t)M * G * kLpl * sizeof(double) + hbytes
                         : (size_t)M * G * kLpl * sizeof(float) + hbytes;
@@ -166,7 +168,9 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
     }
 
     sweep_walk<G>(a, [&](const double (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
-        if constexpr (KIND == kSweepReg) {
+        if constexpr (KIND == kSweepRegEq10) {
+            max_message_eq10_d<G, TW>(h, a.tab, a.fbar, a.T, pos, a.M, x0, full, lds_d + grp * eq10_row_doubles(G), m);
+        } else if constexpr (KIND == kSweepReg) {
             if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);
             else max_message_d<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
         } else {

@@ -28,9 +28,14 @@ hipError_t sweep_tw(const UpdateArgs& a, int tw, hipStream_t s) {
     constexpr int n = sizeof(TwList<G>::v) / sizeof(int);
     if constexpr (I < n) {
         constexpr int TW = TwList<G>::v[I];
-        if (tw == TW) return go_sweep<G, TW, MODE, kSweepReg>(a, s);
+        if (tw == TW) {
+            if constexpr (MODE == kMax)
+                if (a.eq10) return go_sweep<G, TW, kMax, kSweepRegEq10>(a, s);
+            return go_sweep<G, TW, MODE, kSweepReg>(a, s);
+        }
         return sweep_tw<G, MODE, I + 1>(a, tw, s);
     } else {
+        if (a.eq10) return hipErrorInvalidValue;  // Eq. 10 beyond the register windows runs the general kernel
         return go_sweep<G, 0, MODE, kSweepLds>(a, s);
     }
 }

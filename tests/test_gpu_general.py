@@ -89,17 +89,19 @@ def test_general_potentials(case, mode, below, schedule):
     check(tag, gpu, g32, M, 0, 1.0, None, mode, schedule, n, impl, pot=pot)
 
 
-@pytest.mark.parametrize("schedule", ["sync", "sweep"])
-@pytest.mark.parametrize("M,T,alpha", [(16, 2, 1.0), (64, 4, 0.5), (128, 8, 0.3), (20, 5, 0.6)])
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard", "sweep"])
+@pytest.mark.parametrize("M,T,alpha", [(16, 2, 1.0), (64, 4, 0.5), (128, 8, 0.3), (20, 5, 0.6), (200, 10, 0.2),
+                                       (64, 20, 0.1)])
 def test_window_max_eq10(M, T, alpha, schedule):
     """Truncated-linear max-product with fbar above f(T): Eq. 11 would be
-    wrong, the library runs Eq. 10; equal to the oracle's Eq. 10 and, bit
-    for bit, to the dense Eq. 9 kernel."""
+    wrong, the library runs Eq. 10 (the window kernels' prefix/suffix-max
+    form, or the general kernel beyond the register windows, T = 20); equal
+    to the oracle's Eq. 10 and, bit for bit, to the dense Eq. 9 kernel."""
     from bp_gpu_util import run_gpu
     H, W = 6, 7
     g32 = random_unary(H, W, M, 3000 + M)
     fbar = float(np.float32(np.exp(-alpha * T) * 1.5 + 0.01))
-    n = 5 if schedule == "sync" else 2
+    n = {"sync": 5, "checkerboard": 6, "sweep": 2}[schedule]
     say(f"window max Eq. 10 {schedule} M={M} T={T} fbar={fbar:.4f}")
     gs = run_gpu(g32, M, T, alpha, fbar, "max", schedule, n)
     check(f"window Eq. 10 {schedule} M={M}", gs, g32, M, T, alpha, fbar, "max", schedule, n, gb.SPLIT)
