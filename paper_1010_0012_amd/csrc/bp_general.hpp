@@ -60,9 +60,10 @@ __device__ __forceinline__ int edge_type(const GenArgs& a, const Pixel& px, int 
 }
 
 // The tables a kernel reads: the global arrays, or the copy a workgroup
-// staged in LDS once (labels as bytes, M <= 256; f - fbar for sum, f for
-// max).  Staged, every entry of a row costs LDS reads instead of dependent
-// global loads.
+// staged in LDS once (f as float32, labels as bytes, M <= 256).  Staged,
+// every entry of a row costs LDS reads instead of dependent global loads;
+// sum-product then forms f - fbar as (double)f - fbar_d, the same bits as
+// the global double table.
 template <bool STAGE>
 struct GenView {
     const int* ptr;
@@ -74,35 +75,36 @@ struct GenView {
         if constexpr (STAGE) return x8[e];
         else return x32[e];
     }
+    __device__ __forceinline__ double weight(int e, double fbar_d) const {
+        if constexpr (STAGE) return (double)f[e] - fbar_d;
+        else return w[e];
+    }
 };
 
-// LDS bytes of the staged tables: row starts, values, labels (8-byte aligned).
-constexpr size_t gen_stage_bytes(int n_types, int M, int n_entries, int mode) {
+// LDS bytes of the staged tables: row starts, f, labels (8-byte aligned).
+constexpr size_t gen_stage_bytes(int n_types, int M, int n_entries) {
     const size_t ptr = ((size_t)n_types * 2 * (M + 1) * sizeof(int) + 7) / 8 * 8;
-    const size_t vals = (size_t)n_entries * (mode == kSum ? sizeof(double) : sizeof(float));
-    return (ptr + vals + (size_t)n_entries + 7) / 8 * 8;
+    return (ptr + (size_t)n_entries * (sizeof(float) + 1) + 7) / 8 * 8;
 }
 
 // Stage the tables into LDS at base (all threads of the workgroup; the
 // caller's barrier publishes them), or view the global arrays.
-template <bool STAGE, int MODE, int NT>
+template <bool STAGE, int NT>
 __device__ __forceinline__ GenView<STAGE> gen_view(const GenArgs& a, char* base) {
     GenView<STAGE> v;
     if constexpr (STAGE) {
         const int n_ptr = a.n_types * 2 * (a.u.M + 1);
         int* ptr = reinterpret_cast<int*>(base);
-        char* vals = base + ((size_t)n_ptr * sizeof(int) + 7) / 8 * 8;
-        unsigned char* x8 =
-            reinterpret_cast<unsigned char*>(vals + (size_t)a.n_entries * (MODE == kSum ? sizeof(double) : sizeof(float)));
+        float* f = reinterpret_cast<float*>(base + ((size_t)n_ptr * sizeof(int) + 7) / 8 * 8);
+        unsigned char* x8 = reinterpret_cast<unsigned char*>(f + a.n_entries);
         for (int i = threadIdx.x; i < n_ptr; i += NT) ptr[i] = a.ptr[i];
         for (int e = threadIdx.x; e < a.n_entries; e += NT) {
-            if constexpr (MODE == kSum) reinterpret_cast<double*>(vals)[e] = a.ent_w[e];
-            else reinterpret_cast<float*>(vals)[e] = a.ent_f[e];
+            f[e] = a.ent_f[e];
             x8[e] = (unsigned char)a.ent_x[e];
         }
         v.ptr = ptr;
-        v.w = reinterpret_cast<const double*>(vals);
-        v.f = reinterpret_cast<const float*>(vals);
+        v.w = nullptr;
+        v.f = f;
         v.x8 = x8;
         v.x32 = nullptr;
     } else {
@@ -150,7 +152,7 @@ __device__ __forceinline__ void general_message(const GenArgs& a, const GenView<
             const int y = x0 + i;
             double acc = base;
             if (y < M)
-                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(v.w[e], hs[v.x(e)], acc);
+                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(v.weight(e, a.fbar_d[k]), hs[v.x(e)], acc);
             u[i] = acc;
         }
     } else {
@@ -206,7 +208,7 @@ __device__ __forceinline__ void general_lds_rows(double* lds_d, int groups, int 
 template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
-    const GenView<STAGE> v = gen_view<STAGE, MODE, kBlock>(a, reinterpret_cast<char*>(lds_d));
+    const GenView<STAGE> v = gen_view<STAGE, kBlock>(a, reinterpret_cast<char*>(lds_d));
     if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
@@ -244,7 +246,7 @@ constexpr size_t general_sweep_lds_bytes(int G) {
 template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
-    const GenView<STAGE> v = gen_view<STAGE, MODE, kSweepBlock>(a, reinterpret_cast<char*>(lds_d));
+    const GenView<STAGE> v = gen_view<STAGE, kSweepBlock>(a, reinterpret_cast<char*>(lds_d));
     if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;

@@ -12,7 +12,7 @@ constexpr size_t kGenLdsBudget = 64 * 1024;
 template <int G, int MODE, bool EQ10>
 hipError_t go_general(const GenArgs& a, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.u.n_slots + (kBlock / G) - 1) / (kBlock / G));
-    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries, MODE);
+    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries);
     if (st + general_lds_bytes(G) <= kGenLdsBudget)
         hipLaunchKernelGGL((general_update_kernel<G, MODE, EQ10, true>), dim3(blocks), dim3(kBlock),
                            st + general_lds_bytes(G), s, a, (int)st);
@@ -39,7 +39,7 @@ hipError_t go_general_sweep(const GenArgs& a, hipStream_t s) {
     constexpr int LPB = kSweepBlock / G;
     const int n_lines = (a.u.dir == kLeft || a.u.dir == kRight) ? a.u.H : a.u.W;
     const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB) * (a.u.both ? 2 : 1);
-    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries, MODE);
+    const size_t st = gen_stage_bytes(a.n_types, a.u.M, a.n_entries);
     if (st + general_sweep_lds_bytes(G) <= kGenLdsBudget)
         hipLaunchKernelGGL((general_sweep_kernel<G, MODE, EQ10, true>), dim3(blocks), dim3(kSweepBlock),
                            st + general_sweep_lds_bytes(G), s, a, (int)st);
