@@ -61,12 +61,13 @@ def test_per_edge_chain_max(vertical, below, n, M, seed):
     rng = np.random.default_rng(seed)
     g, pot, P = chain(rng, n, M, vertical, random_types(rng, M, 3, below_fbar=below))
     want = brute.max_marginals(P)
-    for impl in (gb.DENSE, gb.SPLIT):           # Eq. 9 and Eq. 10: exact for any fbar
-        st = gb.run(g, pot, gb.MAX, n + 1, gb.SYNC, impl)
-        np.testing.assert_allclose(gb.beliefs(g, st).reshape(n, M), want, rtol=0, atol=1e-12)
-    if not below:                                # Eq. 11 needs f >= fbar (Sec. 5)
-        st = gb.run(g, pot, gb.MAX, n + 1, gb.SYNC, gb.SPARSE)
-        np.testing.assert_allclose(gb.beliefs(g, st).reshape(n, M), want, rtol=0, atol=1e-12)
+    for schedule, iters in ((gb.SYNC, n + 1), (gb.SWEEP, 1)):   # one sweep is exact on a chain
+        for impl in (gb.DENSE, gb.SPLIT):           # Eq. 9 and Eq. 10: exact for any fbar
+            st = gb.run(g, pot, gb.MAX, iters, schedule, impl)
+            np.testing.assert_allclose(gb.beliefs(g, st).reshape(n, M), want, rtol=0, atol=1e-12)
+        if not below:                                # Eq. 11 needs f >= fbar (Sec. 5)
+            st = gb.run(g, pot, gb.MAX, iters, schedule, gb.SPARSE)
+            np.testing.assert_allclose(gb.beliefs(g, st).reshape(n, M), want, rtol=0, atol=1e-12)
 
 
 @pytest.mark.parametrize("mode", [gb.SUM, gb.MAX])
