@@ -57,7 +57,11 @@ struct FgArgs {
     int top[kFgMaxTypes][3][2];     // per slot: top-list lengths for the first and second other slot
 };
 
-// variable -> factor: one group of G lanes per variable.
+// variable -> factor: one group of G lanes per variable.  Up to kFgCache
+// incoming messages are loaded once into registers (statically indexed);
+// the products keep the adjacency order either way.
+constexpr int kFgCache = 8;
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void fg_var_kernel(FgArgs a) {
     const int pos = threadIdx.x & (G - 1);
@@ -68,6 +72,27 @@ __global__ __launch_bounds__(kBlock) void fg_var_kernel(FgArgs a) {
     float gv[kLpl];
     load_labels<false>(a.g + (size_t)v * a.M, x0, a.M, full, gv, 0.0f);
     const int b0 = a.var_ptr[v], b1 = a.var_ptr[v + 1];
+    const int deg = b1 - b0;
+    if (deg <= kFgCache) {
+        float c[kFgCache][kLpl];
+#pragma unroll
+        for (int q = 0; q < kFgCache; ++q)
+            if (q < deg) load_labels<false>(a.m_fv + (size_t)a.var_adj[b0 + q] * a.M, x0, a.M, full, c[q], 0.0f);
+        for (int s = 0; s < deg; ++s) {
+            double p[kLpl];
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) p[i] = gv[i];
+#pragma unroll
+            for (int q = 0; q < kFgCache; ++q)
+                if (q < deg && q != s)
+#pragma unroll
+                    for (int i = 0; i < kLpl; ++i) p[i] *= c[q][i];
+            float n[kLpl];
+            normalise_d<G>(p, a.M, x0, full, n);
+            store_labels<false>(a.n_vf + (size_t)a.var_adj[b0 + s] * a.M, x0, a.M, full, n);
+        }
+        return;
+    }
     for (int s = b0; s < b1; ++s) {
         double p[kLpl];
 #pragma unroll
