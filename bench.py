@@ -505,14 +505,20 @@ def main():
         for mode, sched, dense in (("max", "sync", False), ("sum", "checkerboard", False),
                                    ("max", "checkerboard", False), ("sum", "sync", True),
                                    ("max", "sync", True)):
+            # sparse launches run two iterations (sync) or two passes
+            # (checkerboard) each; dense launches run one
             n = cfg.iters if sched == "sync" else 2 * cfg.iters
-            pair = sched == "sync" and not dense
-            ms = time_launches(grid, mode, n, sched, dense, 2, iters_per_launch=2 if pair else 1)
-            per_iter = ms * (0.5 if pair else 1 if sched == "sync" else 2)
+            per_launch = 1 if dense else 2
+            ms = time_launches(grid, mode, n, sched, dense, 2, iters_per_launch=per_launch)
+            step = ms / per_launch                                   # one iteration or one pass
+            per_iter = step * (1 if sched == "sync" else 2)          # every message updated once
+            unit = "iteration" if sched == "sync" else "pass"
             key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
             extra[key + "_updates_per_s"] = updates_per_iter / (per_iter * 1e-3)
             extra[key + "_launch_us"] = ms * 1e3
-            log(f"bench: {key}: {ms * 1e3:.1f} us/launch, {updates_per_iter / (per_iter * 1e-3):.4e} updates/s")
+            extra[key + f"_us_per_{unit}"] = step * 1e3
+            log(f"bench: {key}: {ms * 1e3:.1f} us per launch, {step * 1e3:.1f} us per {unit}, "
+                f"{updates_per_iter / (per_iter * 1e-3):.4e} updates/s")
         for mode in ("sum", "max"):
             sp = extra.get(f"sparse_{mode}_sync_updates_per_s", value if mode == "sum" else None)
             dn = extra.get(f"dense_{mode}_sync_updates_per_s")

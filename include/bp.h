@@ -132,11 +132,13 @@ int bp_reset_messages(bp_grid* grid);
  * schedule (bp_iterate_dense returns BP_EUNSUPPORTED). */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
-/* Synchronous iterations of the window potential run two per launch by
- * default (where a register window is compiled: T <= 16, 12 for M <= 16):
- * each pixel computes the four messages its neighbours send it, then its
- * own four, so the intermediate messages stay on chip.  The results are the
- * same bits as single launches; enable = 0 selects single launches (for
+/* Synchronous iterations and checkerboard passes of the window potential
+ * run two per launch by default (where a register window is compiled: T <=
+ * 16, 12 for M <= 16; not for Eq. 10): each pixel computes the four
+ * messages its neighbours send it, then its own four, so the intermediate
+ * messages stay on chip.  A checkerboard pair writes the grid's other
+ * message buffer in full (single passes stay in place).  The results are
+ * the same bits as single launches; enable = 0 selects single launches (for
  * comparison and timing).  Errors: BP_EINVAL on a null handle. */
 int bp_set_sync_fusion(bp_grid* grid, int32_t enable);
 

@@ -145,15 +145,25 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         }
         return BP_OK;
     }
-    // Synchronous iterations in pairs: one launch for two (the same bits as
-    // two single launches), then a single launch for an odd remainder.
-    if (schedule == BP_SCHED_SYNC && !dense && !eq10 && G->fuse_sync && bpk::sparse2_supported(G->M, G->T)) {
+    // Iterations (sync) or passes (checkerboard) in pairs: one launch for two
+    // (the same bits as two single launches), then a single launch for an
+    // odd remainder.  A checkerboard pair writes the other buffer in full, so
+    // it flips the current buffer; single passes stay in place.
+    if (!dense && !eq10 && G->fuse_sync && bpk::sparse2_supported(G->M, G->T)) {
         for (; n >= 2; n -= 2) {
-            UpdateArgs a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
+            UpdateArgs a;
+            if (schedule == BP_SCHED_SYNC) {
+                a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], -1);
+            } else {
+                // passes of colours c, 1 - c: the launch runs the colour 1 - c senders
+                a = base_args(G, G->msg[G->cur], G->msg[G->cur ^ 1], (int)((G->cb_pass + 1) & 1));
+                a.mid = G->msg[G->cur ^ 1];
+            }
             memcpy(a.tab, tab, sizeof a.tab);
             hipError_t e = bpk::launch_sparse2(a, kmode, G->stream);
             if (e != hipSuccess) return hip_fail(e, "fused sparse update launch");
             G->cur ^= 1;
+            if (schedule == BP_SCHED_CHECKERBOARD) G->cb_pass += 2;
         }
     }
     for (int t = 0; t < n; ++t) {

@@ -125,8 +125,8 @@ __global__ __launch_bounds__(kBlock) void batch_update2_kernel(const BatchLaunch
         for (int pass = 0; pass < L.passes; ++pass) {
             const Pixel px = sync_pixel(first + pass * RPB + grp, d.H, d.W, d.N);
             if (!px.ok) continue;  // whole groups only
-            pair_pixel<G, TW, MODE, FULL>(d.g, d.msg[parity], d.msg[parity ^ 1], d.H, d.W, d.M, px, pos, d.tab_wd,
-                                          d.fbar_d, d.tab_f, d.fbar);
+            pair_pixel<G, TW, MODE, FULL>(d.g, d.msg[parity], d.msg[parity ^ 1], nullptr, d.H, d.W, d.M, px, pos,
+                                          d.tab_wd, d.fbar_d, d.tab_f, d.fbar);
         }
     }
 }

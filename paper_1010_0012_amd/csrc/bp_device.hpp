@@ -66,6 +66,7 @@ struct UpdateArgs {
     int dir;               // sweep pass: direction the messages travel (kLeft .. kDown)
     int both;              // sweep: 1 = the second half of the grid runs the opposite direction
     int eq10;              // max-product: some f(d) < fbar, so Eq. 10 (not Eq. 11) holds
+    float* mid;            // two-iteration launches: where the first iteration's messages go, or null
     float fbar;            // potential outside the window (float32, max-product)
     float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)
     // Sum-product works in double end to end: the potential in double and

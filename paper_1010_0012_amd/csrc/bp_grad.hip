@@ -50,9 +50,12 @@ int grad_checks(const bp_grid* G, int n, int k) {
     return BP_OK;
 }
 
-hipError_t sync_sum_step(bp_grid* G, const float* in, float* out, bool pair = false) {
+// One synchronous sum-product iteration in -> out, or two (pair) with the
+// intermediate state into mid (null: not kept).
+hipError_t sync_sum_step(bp_grid* G, const float* in, float* out, bool pair = false, float* mid = nullptr) {
     bpk::UpdateArgs a = base_args(G, in, out, -1);
     memcpy(a.tab, G->tab_w, sizeof a.tab);
+    a.mid = mid;
     return pair ? bpk::launch_sparse2(a, bpk::kSum, G->stream) : bpk::launch_sparse(a, bpk::kSum, G->stream);
 }
 
@@ -158,11 +161,18 @@ int bp_backward(bp_grid* G, const float* dL_db, float* dtheta, float* dalpha) {
         } else {
             state0 = L.ckpt(ws, sidx - 1);
         }
-        // recompute m^{t0+1} .. m^{t0+len-1} into seg[1 .. len-1]
+        // recompute m^{t0+1} .. m^{t0+len-1} into seg[1 .. len-1], two per
+        // launch where the pair kernel is compiled (it stores the first of the
+        // two states too)
+        const bool pairs = G->fuse_sync && bpk::sparse2_supported(G->M, G->T);
         const float* prev = state0;
-        for (int i = 1; i < len; ++i) {
-            if ((e = sync_sum_step(G, prev, L.seg(ws, i))) != hipSuccess) return hip_fail(e, "recompute launch");
-            prev = L.seg(ws, i);
+        for (int i = 1; i < len;) {
+            const bool two = pairs && i + 1 < len;
+            if ((e = sync_sum_step(G, prev, L.seg(ws, two ? i + 1 : i), two, two ? L.seg(ws, i) : nullptr)) !=
+                hipSuccess)
+                return hip_fail(e, "recompute launch");
+            prev = L.seg(ws, two ? i + 1 : i);
+            i += two ? 2 : 1;
         }
         for (int i = len - 1; i >= 0; --i) {
             const int t = t0 + i;

@@ -326,14 +326,16 @@ __device__ __forceinline__ void message_d(const double (&h)[kLpl], const double*
     else max_message_d<G, TW>(h, tab, fbar, pos, M, x0, full, m);
 }
 
-// Both iterations for one pixel px of an H x W grid (in -> out).  FULL:
+// Both iterations for one pixel px of an H x W grid (in -> out); with
+// mid_out, the first iteration's messages into px are stored there too
+// (px's own inbox slots, coalesced).  FULL:
 // M == 4G, known at compile time so that no load or normalisation carries a
 // branch.  Loads are unconditional: a missing neighbour (or a missing row of
 // a neighbour's inbox) reads a valid row and is replaced by the factor 1,
 // which keeps every load of the pixel in one basic block.
 template <int G, int TW, int MODE, bool FULL>
-__device__ __forceinline__ void pair_pixel(const float* g, const float* in, float* out, int H, int W, int M,
-                                           const Pixel& px, int pos, const double* dtab, double fbar_d,
+__device__ __forceinline__ void pair_pixel(const float* g, const float* in, float* out, float* mid_out, int H, int W,
+                                           int M, const Pixel& px, int pos, const double* dtab, double fbar_d,
                                            const float* tab, float fbar) {
     const int x0 = pos * kLpl;
     const size_t plane = (size_t)H * W * M;
@@ -367,6 +369,7 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
         message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) mid.m[k][i] = px.has[k] ? mid.m[k][i] : 1.0f;
+        if (mid_out && px.has[k]) store_labels<kMsgNT>(mid_out + k * plane + (size_t)px.p * M, x0, M, FULL, mid.m[k]);
     }
     // Second iteration, sender side, from the messages just computed.
 #pragma unroll
@@ -381,14 +384,22 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
     }
 }
 
+// Synchronous (a.colour < 0): every pixel, two iterations a.in -> a.out,
+// the first iteration's state optionally into a.mid.  Checkerboard pair
+// (a.colour = c): the passes of colour 1 - c and then c, as one launch over
+// the pixels of colour c: each forms the messages its (colour 1 - c)
+// neighbours send it and stores them in its own inbox in a.out (a.mid ==
+// a.out), then sends its own into its neighbours' inboxes in a.out.  Every
+// inbox slot of a.out is written (colour-c pixels hear only from colour
+// 1 - c and vice versa), and every value equals the in-place passes'.
 template <int G, int TW, int MODE, bool FULL>
 __global__ __launch_bounds__(kBlock) void sparse_update2_kernel(UpdateArgs a, int per) {
     const int b = xcd_band_block(blockIdx.x, per);
     const int pos = threadIdx.x & (G - 1);
     const int slot = (b * kBlock + threadIdx.x) / G;
-    const Pixel px = sync_pixel(slot, a.H, a.W, a.N);
+    const Pixel px = map_slot(slot, a);
     if (!px.ok) return;  // whole groups only
-    pair_pixel<G, TW, MODE, FULL>(a.g, a.in, a.out, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
+    pair_pixel<G, TW, MODE, FULL>(a.g, a.in, a.out, a.mid, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
 }
 
 // ------------------------------------- sparse update, runtime window ----

@@ -13,8 +13,11 @@ hipError_t launch_sparse(const UpdateArgs& a, int mode, hipStream_t stream);
 // Window half-width of the register variant launch_sparse would use for
 // (M, T), or -1 for the runtime-window fallback.
 int sparse_variant_tw(int M, int T);
-// Two synchronous iterations in one launch (a.in -> a.out, a.colour < 0),
-// bitwise equal to two launch_sparse calls; sparse2_supported tells whether
+// Two iterations in one launch, bitwise equal to two launch_sparse calls:
+// synchronous (a.colour < 0: a.in -> a.out, the intermediate state into
+// a.mid unless null), or a checkerboard pass pair (a.colour = c: the passes
+// of colour 1 - c, then c, from a.in into the other buffer a.out == a.mid;
+// the launch covers the colour-c slots).  sparse2_supported tells whether
 // (M, T) has a compiled register window (otherwise run single launches).
 bool sparse2_supported(int M, int T);
 hipError_t launch_sparse2(const UpdateArgs& a, int mode, hipStream_t stream);

@@ -16,7 +16,7 @@ hipError_t launch_sparse(const UpdateArgs& a, int mode, hipStream_t stream) {
 bool sparse2_supported(int M, int T) { return sparse_tw(M, T) >= 0; }
 
 hipError_t launch_sparse2(const UpdateArgs& a, int mode, hipStream_t stream) {
-    if (a.N <= 0) return hipSuccess;
+    if (a.n_slots <= 0) return hipSuccess;
     return mode == kSum ? dispatch_sparse2<kSum>(a, stream) : launch_sparse2_max(a, stream);
 }
 

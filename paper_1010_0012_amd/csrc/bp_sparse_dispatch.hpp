@@ -64,7 +64,7 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
 // selects the branch-free full-row instance.
 template <int G, int TW, int MODE>
 hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
-    const int nblk = (int)groups_blocks<G>(a.N);
+    const int nblk = (int)groups_blocks<G>(a.n_slots);
     const int per = (nblk + kXcds - 1) / kXcds;
     if (a.M == G * kLpl)
         hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, true>), dim3((unsigned)(per * kXcds)), dim3(kBlock),

@@ -123,17 +123,19 @@ def test_checkerboard_interleaves_sync_bitwise(mode):
         np.testing.assert_array_equal(cb[k][older], sync_n1[k][older])
 
 
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
 @pytest.mark.parametrize("mode", ["sum", "max"])
 @pytest.mark.parametrize("shape", SHAPES, ids=_id)
-def test_sync_pairs_equal_single_launches(shape, mode):
-    """Two synchronous iterations per launch (each pixel first computes the
-    messages sent to it) give the bits of single launches, for even and odd
-    iteration counts; shapes without a register window run single launches."""
+def test_pairs_equal_single_launches(shape, mode, schedule):
+    """Two synchronous iterations, or two checkerboard passes, per launch
+    (each pixel first computes the messages sent to it) give the bits of
+    single launches, for even and odd counts; shapes without a register
+    window run single launches."""
     H, W, M, T, alpha, fbar = shape
     g32 = random_unary(H, W, M, 300 + SHAPES.index(shape))
-    for n in (2, 5):
-        a = run_gpu(g32, M, T, alpha, fbar, mode, "sync", n, fuse=True)
-        b = run_gpu(g32, M, T, alpha, fbar, mode, "sync", n, fuse=False)
+    for n in (2, 5, 6):
+        a = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, fuse=True)
+        b = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, fuse=False)
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
 
