@@ -499,6 +499,8 @@ def main():
     grid.set_sync_fusion(True)
     extra["sparse_sum_sync_single_launch_us"] = ms_single * 1e3
     extra["sparse_sum_sync_single_launch_GBs"] = bytes_launch / (ms_single * 1e-3) / 1e9
+    extra["sparse_sum_sync_single_launch_frac"] = bytes_launch / (ms_single * 1e-3) / 1e9 / HBM_PEAK_GBS
+    extra["pair_over_single_per_iteration"] = ms_single / (ms_launch / 2)
     log(f"bench: sparse sum single launch {ms_single * 1e3:.1f} us "
         f"({bytes_launch / (ms_single * 1e-3) / 1e9:.0f} GB/s); pair launch per iteration {ms_launch * 500:.1f} us")
     if not args.no_legs:
