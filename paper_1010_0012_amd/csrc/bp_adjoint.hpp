@@ -135,14 +135,14 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
             if (!full && x0 + i >= a.M) ud[i] = 0.0;
             zd += ud[i];
         }
-        const double inv = 1.0 / group_sum_d<G>(zd);
+        const double inv = recip_d(group_sum_d<G>(zd));  // the forward's normaliser, bit for bit
         const float S = (float)sd;
         const float sl = group_total<G, kSum>(lam);
         float ub[kLpl];
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) {
             const float mu = lam[i] - (float)(ud[i] * inv) * sl;
-            ub[i] = (full || x0 + i < a.M) ? (float)((double)mu / ud[i]) : 0.0f;
+            ub[i] = (full || x0 + i < a.M) ? (float)((double)mu * recip_d(ud[i])) : 0.0f;
         }
         const float su = group_total<G, kSum>(ub);
         float hb[kLpl];
