@@ -212,6 +212,15 @@ __device__ __forceinline__ void group_argmax_d(double& best, int& arg) {
     if constexpr (G >= 64) take(xor32_d(best), xor32_i(arg));
 }
 
+// Slot of label x in a group's LDS row of G*4 doubles: (x mod 4) * G + x / 4.
+// Lane pos owns labels 4*pos .. 4*pos+3, so its own writes (label 4*pos + i
+// at i*G + pos) and reads at a fixed offset from its labels fall on
+// consecutive doubles across the group's lanes: no bank conflicts, where the
+// plain label index (a 32-byte stride between lanes) hits a quarter of the
+// banks.
+template <int G>
+__device__ __forceinline__ int row_slot(int x) { return (x & (kLpl - 1)) * G + (x >> 2); }
+
 // Order this wave's LDS accesses: writes before the call are visible to
 // every lane of the wave after it.  Enough wherever only the lanes of one
 // G-lane group (G <= 64, so inside one wave) share an LDS row.

@@ -137,7 +137,8 @@ __device__ __forceinline__ bool listed(const int2* s, int e0, int e1, int x, int
 // largest product over the completions outside the label's listed tuples
 // [e0, e1) (ent_s, sorted by (a, b)), or 0 when every completion is listed.
 // top_v / top_i: the other slots' top lists ([0]: first other slot, [kFgTop]:
-// second), n0: the first other slot's message.
+// second), n0: the first other slot's message (row_slot layout).
+template <int G>
 __device__ __forceinline__ double split_outside(const FgArgs& a, int k, int i, int e0, int e1, int n_oth,
                                                const double* n0, const double* top_v, const int* top_i) {
     const double fb = (double)a.fbar[k];
@@ -161,7 +162,7 @@ __device__ __forceinline__ double split_outside(const FgArgs& a, int k, int i, i
             while (f < e1 && s[f].x == x) ++f;
             for (int r = 0; r < a.top[k][i][1]; ++r) {
                 if (!listed(s, e, f, top_i[kFgTop + r], 1)) {
-                    best = fmax(best, (fb * n0[x]) * top_v[kFgTop + r]);
+                    best = fmax(best, (fb * n0[row_slot<G>(x)]) * top_v[kFgTop + r]);
                     break;
                 }
             }
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
         float v[kLpl] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (live && q < n_oth) load_labels<false>(a.n_vf + ((size_t)fa * 3 + (q ? j1 : j0)) * a.M, x0, a.M, full, v, 0.0f);
 #pragma unroll
-        for (int l = 0; l < kLpl; ++l) nj[q][x0 + l] = v[l];
+        for (int l = 0; l < kLpl; ++l) nj[q][l * G + pos] = v[l];  // row_slot layout
         double r = MODE == kSum ? ((double)v[0] + (double)v[1]) + ((double)v[2] + (double)v[3])
                                 : fmax(fmax((double)v[0], (double)v[1]), fmax((double)v[2], (double)v[3]));
         r = MODE == kSum ? group_sum_d<G>(r) : group_max_d<G>(r);
@@ -239,11 +240,11 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
             for (int e = row[x]; e < row[x + 1]; ++e) {
                 const int2 o = STAGE ? st_o[e - e_base] : a.ent_o[e];
                 double p = STAGE ? st_w[e - e_base] : MODE == kSum ? a.ent_w[e] : (double)a.ent_f[e];
-                p *= nj[0][o.x];
-                if (n_oth == 2) p *= nj[1][o.y];
+                p *= nj[0][row_slot<G>(o.x)];
+                if (n_oth == 2) p *= nj[1][row_slot<G>(o.y)];
                 acc = MODE == kSum ? acc + p : fmax(acc, p);
             }
-            if (split) acc = fmax(acc, split_outside(a, k, i, row[x], row[x + 1], n_oth, nj[0], top_v, top_i));
+            if (split) acc = fmax(acc, split_outside<G>(a, k, i, row[x], row[x + 1], n_oth, nj[0], top_v, top_i));
         }
         u[l] = acc;
     }

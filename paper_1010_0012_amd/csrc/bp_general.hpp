@@ -60,7 +60,8 @@ __device__ __forceinline__ int edge_type(const GenArgs& a, const Pixel& px, int 
 }
 
 // The tables a kernel reads: the global arrays, or the copy a workgroup
-// staged in LDS once (f as float32, labels as bytes, M <= 256).  Staged,
+// staged in LDS once (f as float32, the labels' h-row slots as bytes,
+// M <= 256).  Staged,
 // every entry of a row costs LDS reads instead of dependent global loads;
 // sum-product then forms f - fbar as (double)f - fbar_d, the same bits as
 // the global double table.
@@ -71,9 +72,12 @@ struct GenView {
     const float* f;
     const int* x32;
     const unsigned char* x8;
-    __device__ __forceinline__ int x(int e) const {
+    // the slot of entry e's label in a group's h row (row_slot layout): the
+    // staged copy holds the slots themselves
+    template <int G>
+    __device__ __forceinline__ int slot(int e) const {
         if constexpr (STAGE) return x8[e];
-        else return x32[e];
+        else return row_slot<G>(x32[e]);
     }
     __device__ __forceinline__ double weight(int e, double fbar_d) const {
         if constexpr (STAGE) return (double)f[e] - fbar_d;
@@ -89,7 +93,7 @@ constexpr size_t gen_stage_bytes(int n_types, int M, int n_entries) {
 
 // Stage the tables into LDS at base (all threads of the workgroup; the
 // caller's barrier publishes them), or view the global arrays.
-template <bool STAGE, int NT>
+template <bool STAGE, int NT, int G>
 __device__ __forceinline__ GenView<STAGE> gen_view(const GenArgs& a, char* base) {
     GenView<STAGE> v;
     if constexpr (STAGE) {
@@ -100,7 +104,7 @@ __device__ __forceinline__ GenView<STAGE> gen_view(const GenArgs& a, char* base)
         for (int i = threadIdx.x; i < n_ptr; i += NT) ptr[i] = a.ptr[i];
         for (int e = threadIdx.x; e < a.n_entries; e += NT) {
             f[e] = a.ent_f[e];
-            x8[e] = (unsigned char)a.ent_x[e];
+            x8[e] = (unsigned char)row_slot<G>(a.ent_x[e]);
         }
         v.ptr = ptr;
         v.w = nullptr;
@@ -140,7 +144,7 @@ __device__ __forceinline__ void general_message(const GenArgs& a, const GenView<
     const bool full = M == G * kLpl;
     wave_sync();  // the previous message is done with hs and the top list
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) hs[x0 + i] = h[i];
+    for (int i = 0; i < kLpl; ++i) hs[i * G + pos] = h[i];  // row_slot layout
     const int ts = table_slot(k, o);
     const int* pt = v.ptr + ts * (M + 1);
     double u[kLpl];
@@ -152,7 +156,8 @@ __device__ __forceinline__ void general_message(const GenArgs& a, const GenView<
             const int y = x0 + i;
             double acc = base;
             if (y < M)
-                for (int e = pt[y]; e < pt[y + 1]; ++e) acc = fma(v.weight(e, a.fbar_d[k]), hs[v.x(e)], acc);
+                for (int e = pt[y]; e < pt[y + 1]; ++e)
+                    acc = fma(v.weight(e, a.fbar_d[k]), hs[v.template slot<G>(e)], acc);
             u[i] = acc;
         }
     } else {
@@ -167,7 +172,8 @@ __device__ __forceinline__ void general_message(const GenArgs& a, const GenView<
             const int y = x0 + i;
             double inside = 0.0;
             if (y < M)
-                for (int e = pt[y]; e < pt[y + 1]; ++e) inside = fmax(inside, (double)v.f[e] * hs[v.x(e)]);
+                for (int e = pt[y]; e < pt[y + 1]; ++e)
+                    inside = fmax(inside, (double)v.f[e] * hs[v.template slot<G>(e)]);
             double outside;
             if (!EQ10 || !a.eq10[k]) {
                 outside = fb * hm;  // Eq. 11: f >= fbar on the list
@@ -185,7 +191,7 @@ __device__ __forceinline__ void general_message(const GenArgs& a, const GenView<
                     }
                 } else {
                     for (int x = 0; x < M; ++x)
-                        if (!((row[x >> 5] >> (x & 31)) & 1u)) c = fmax(c, hs[x]);
+                        if (!((row[x >> 5] >> (x & 31)) & 1u)) c = fmax(c, hs[row_slot<G>(x)]);
                 }
                 outside = fb * c;
             }
@@ -208,7 +214,7 @@ __device__ __forceinline__ void general_lds_rows(double* lds_d, int groups, int 
 template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
-    const GenView<STAGE> v = gen_view<STAGE, kBlock>(a, reinterpret_cast<char*>(lds_d));
+    const GenView<STAGE> v = gen_view<STAGE, kBlock, G>(a, reinterpret_cast<char*>(lds_d));
     if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
@@ -246,7 +252,7 @@ constexpr size_t general_sweep_lds_bytes(int G) {
 template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
-    const GenView<STAGE> v = gen_view<STAGE, kSweepBlock>(a, reinterpret_cast<char*>(lds_d));
+    const GenView<STAGE> v = gen_view<STAGE, kSweepBlock, G>(a, reinterpret_cast<char*>(lds_d));
     if constexpr (STAGE) __syncthreads();
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
