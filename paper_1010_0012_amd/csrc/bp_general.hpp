@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, i
     sweep_block_dir(a.u, blk, dir0);
     const bool horiz = dir0 == kLeft || dir0 == kRight;
     const bool live = blk * (kSweepBlock / G) + grp < (horiz ? a.u.H : a.u.W);
-    sweep_walk<G>(a.u, [&](const double (&h)[kLpl], int r, int c, int dir, float (&m)[kLpl]) {
+    auto msg = [&](const double (&h)[kLpl], int r, int c, int dir, float (&m)[kLpl]) {
         int k = 0;  // groups past the last scanline pass any valid type
         if (live) {
             Pixel px;
@@ -273,7 +273,9 @@ __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, i
             k = edge_type(a, px, dir);  // the sender always has a neighbour towards dir
         }
         general_message<G, MODE, EQ10, STAGE>(a, v, k, dir, h, hs, top_v, top_i, pos, m);
-    });
+    };
+    if (a.u.M == G * kLpl) sweep_walk<G, true>(a.u, msg);
+    else sweep_walk<G, false>(a.u, msg);
 }
 
 }  // namespace bpk

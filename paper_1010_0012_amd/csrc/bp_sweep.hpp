@@ -10,9 +10,13 @@
 // side, so it stays in registers (the carry) as well as being stored for the
 // later passes and the readout.  The unary and the two perpendicular inbox
 // messages of a sender do not depend on the carry and are loaded four steps
-// ahead.  A pass writes only the inbox plane opposite to its direction
-// and reads only the two perpendicular planes, so it runs in place, and the
-// two passes of one axis run together in one launch.
+// ahead.  Those loads are unconditional, so that the ring of inputs in flight
+// needs no copies and no branches: groups past the last scanline read the
+// last one, the walk's tail re-reads its last sender, and a missing
+// perpendicular neighbour reads the row of ones.  A pass writes only the
+// inbox plane opposite to its direction and reads only the two perpendicular
+// planes, so it runs in place, and the two passes of one axis run together in
+// one launch.
 #pragma once
 
 #include "bp_kernels.hpp"
@@ -51,9 +55,9 @@ __device__ __forceinline__ void sweep_block_dir(const UpdateArgs& a, int& blk, i
 // blk * (kSweepBlock / G) + grp (sweep_block_dir).  msg(h, r, c, dir, m)
 // turns the h of the sender at (r, c), sending towards dir, into its message
 // m; it may hold block barriers, since every group of the workgroup makes
-// the same number of steps (groups past the last scanline run on dummy
-// inputs and store nothing).
-template <int G, typename Msg>
+// the same number of steps (groups past the last scanline run on the last
+// scanline's inputs and store nothing).  FULL: M == 4G.
+template <int G, bool FULL, typename Msg>
 __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     constexpr int CAP = G * kLpl;
     constexpr int LPB = kSweepBlock / G;  // scanlines per workgroup
@@ -65,15 +69,17 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     const bool forward = dir == kRight || dir == kDown;  // senders in increasing index
     const int n_lines = horiz ? a.H : a.W;
     const int len = horiz ? a.W : a.H;
-    const int line = blk * LPB + grp;
-    const bool live = line < n_lines;
+    const bool live = blk * LPB + grp < n_lines;
+    const int line = live ? blk * LPB + grp : n_lines - 1;  // the scanline whose inputs the group reads
     const int x0 = pos * kLpl;
-    const bool full = a.M == CAP;
     const size_t plane = (size_t)a.N * a.M;
     const int side0 = horiz ? kUp : kLeft;   // h = ((g * m_side0) * m_side1) * carry,
     const int side1 = horiz ? kDown : kRight;  // the product order of the other updates
-    const bool has0 = line > 0;                       // up (rows) / left (columns) neighbour
-    const bool has1 = line + 1 < (horiz ? a.H : a.W);  // down / right neighbour
+    // the perpendicular inbox planes (up / left, down / right), or the row of
+    // ones with a zero row stride where the scanline has no neighbour that side
+    const float* in0 = line > 0 ? a.in + side0 * plane : kOnesRow.v;
+    const float* in1 = line + 1 < n_lines ? a.in + side1 * plane : kOnesRow.v;
+    const size_t stride0 = line > 0 ? (size_t)a.M : 0, stride1 = line + 1 < n_lines ? (size_t)a.M : 0;
     const int step_q = dir == kLeft ? -1 : dir == kRight ? 1 : dir == kUp ? -a.W : a.W;
 
     auto along = [&](int t) { return forward ? t : len - 1 - t; };  // position of the t-th sender
@@ -81,27 +87,24 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
         const int s = along(t);
         return horiz ? line * a.W + s : s * a.W + line;
     };
+    const int steps = len - 1;  // the last node of the scanline sends nothing this way
+    if (steps <= 0) return;     // the same for every group
+    // inputs of the t-th sender (t clamped to the last one)
     auto load_raw = [&](int t, float (&gv)[kLpl], float (&m0)[kLpl], float (&m1)[kLpl]) {
-        const size_t off = (size_t)sender(t) * a.M;
-        load_labels<kUnaryNT>(a.g + off, x0, a.M, full, gv, 0.0f);
-        if (has0) load_labels<kMsgNT>(a.in + side0 * plane + off, x0, a.M, full, m0, 1.0f);
-        if (has1) load_labels<kMsgNT>(a.in + side1 * plane + off, x0, a.M, full, m1, 1.0f);
+        const size_t p = (size_t)sender(min(t, steps - 1));
+        load_labels<kUnaryNT>(a.g + p * a.M, x0, a.M, FULL, gv, 0.0f);
+        load_labels<kMsgNT>(in0 + p * stride0, x0, a.M, FULL, m0, 1.0f);
+        load_labels<kMsgNT>(in1 + p * stride1, x0, a.M, FULL, m1, 1.0f);
     };
 
-    const int steps = len - 1;  // the last node of the scanline sends nothing this way
     // Inputs of the next kAhead senders in flight: a ring of registers,
     // statically indexed by unrolling the step loop by kAhead.
     constexpr int kAhead = 4;
     float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j)
-#pragma unroll
-        for (int i = 0; i < kLpl; ++i) rg[j][i] = r0[j][i] = r1[j][i] = 1.0f;
-#pragma unroll
     for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j)
-        if (live && j < steps) load_raw(j, rg[j], r0[j], r1[j]);
+    for (int j = 0; j < kAhead; ++j) load_raw(j, rg[j], r0[j], r1[j]);
     for (int t0 = 0; t0 < steps; t0 += kAhead) {
 #pragma unroll
         for (int j = 0; j < kAhead; ++j) {
@@ -110,13 +113,13 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
             double h[kLpl];  // Eq. 5, in double as in the other updates
 #pragma unroll
             for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
-            if (live && t + kAhead < steps) load_raw(t + kAhead, rg[j], r0[j], r1[j]);
+            load_raw(t + kAhead, rg[j], r0[j], r1[j]);
             float m[kLpl];
             const int s = along(t);
             msg(h, horiz ? line : s, horiz ? s : line, dir, m);
             if (live) {
                 const int q = sender(t) + step_q;
-                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, full, m);
+                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, FULL, m);
             }
 #pragma unroll
             for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
@@ -124,14 +127,14 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     }
 }
 
-template <int G, int TW, int MODE, int KIND>
+template <int G, int TW, int MODE, int KIND, bool FULL>
 __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
     constexpr int CAP = G * kLpl;
     extern __shared__ double lds_d[];
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int x0 = pos * kLpl;
-    const bool full = a.M == CAP;
+    constexpr bool full = FULL;
 
     // tables in LDS for the LDS-window and dense forms
     double* dtab = lds_d;                                    // kSweepLds sum: w(d); dense sum: f(d)
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
         __syncthreads();
     }
 
-    sweep_walk<G>(a, [&](const double (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
+    sweep_walk<G, FULL>(a, [&](const double (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
         if constexpr (KIND == kSweepRegEq10) {
             max_message_eq10_d<G, TW>(h, a.tab, a.fbar, a.T, pos, a.M, x0, full, lds_d + grp * eq10_row_doubles(G), m);
         } else if constexpr (KIND == kSweepReg) {

@@ -8,10 +8,10 @@
 
 namespace bpk {
 
-template <int G, int TW, int MODE, int KIND>
-hipError_t go_sweep(const UpdateArgs& a, hipStream_t s) {
+template <int G, int TW, int MODE, int KIND, bool FULL>
+hipError_t go_sweep_full(const UpdateArgs& a, hipStream_t s) {
     const size_t lds = sweep_lds_bytes(G, a.M, MODE, KIND);
-    const void* fn = reinterpret_cast<const void*>(&sweep_pass_kernel<G, TW, MODE, KIND>);
+    const void* fn = reinterpret_cast<const void*>(&sweep_pass_kernel<G, TW, MODE, KIND, FULL>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -19,8 +19,16 @@ hipError_t go_sweep(const UpdateArgs& a, hipStream_t s) {
     const int n_lines = (a.dir == kLeft || a.dir == kRight) ? a.H : a.W;
     constexpr int LPB = kSweepBlock / G;
     const unsigned blocks = (unsigned)((n_lines + LPB - 1) / LPB) * (a.both ? 2 : 1);
-    hipLaunchKernelGGL((sweep_pass_kernel<G, TW, MODE, KIND>), dim3(blocks), dim3(kSweepBlock), lds, s, a);
+    hipLaunchKernelGGL((sweep_pass_kernel<G, TW, MODE, KIND, FULL>), dim3(blocks), dim3(kSweepBlock), lds, s, a);
     return hipGetLastError();
+}
+
+// FULL (M == 4G) is a template parameter: loads, stores and normalisation
+// then carry no per-label bounds.
+template <int G, int TW, int MODE, int KIND>
+hipError_t go_sweep(const UpdateArgs& a, hipStream_t s) {
+    return a.M == G * kLpl ? go_sweep_full<G, TW, MODE, KIND, true>(a, s)
+                           : go_sweep_full<G, TW, MODE, KIND, false>(a, s);
 }
 
 template <int G, int MODE, int I = 0>
