@@ -3,6 +3,7 @@
 // uniform messages, every finer level started from its parent's inbox.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -47,17 +48,31 @@ __global__ __launch_bounds__(kBlock) void pyramid_kernel(const float* __restrict
     store_labels<false>(coarse + (size_t)slot * M, x0, M, full, out);
 }
 
-// Initial inbox of a level: pixel (r, c) copies the inbox of block (r/2, c/2).
+// Initial inbox of a level: pixel (r, c) copies the inbox of block
+// (r/2, c/2), into fine0 in full and into fine1 either in full (all1) or
+// only in the slots of off-grid neighbours, the ones no update writes.
+// blockIdx.y walks the (slot k, row r) rows of the [4][Hf][Wf][M] buffers; a
+// thread moves VEC consecutive labels of one pixel (VEC = 4: M is a multiple
+// of 4, so rows stay 16-byte aligned).
+template <int VEC>
 __global__ __launch_bounds__(kBlock) void prolong_kernel(const float* __restrict__ coarse, int Hc, int Wc,
-                                                         float* __restrict__ fine, int Hf, int Wf, int M) {
-    const size_t n = (size_t)4 * Hf * Wf * M;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
-        const int x = (int)(i % M);
-        const size_t q = i / M;
-        const int p = (int)(q % ((size_t)Hf * Wf));
-        const int k = (int)(q / ((size_t)Hf * Wf));
-        const int r = p / Wf, c = p - (p / Wf) * Wf;
-        fine[i] = coarse[(((size_t)k * Hc + r / 2) * Wc + c / 2) * M + x];
+                                                         float* __restrict__ fine0, float* __restrict__ fine1,
+                                                         int all1, int Hf, int Wf, int M) {
+    typedef float vec_t __attribute__((ext_vector_type(VEC)));
+    const int mv = M / VEC;   // vectors per pixel
+    const int row_v = Wf * mv;  // vectors per fine row
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= row_v) return;
+    const int c = j / mv, xv = j - c * mv;
+    for (int kr = blockIdx.y; kr < 4 * Hf; kr += gridDim.y) {
+        const int k = kr / Hf, r = kr - k * Hf;
+        const size_t src = (((size_t)k * Hc + r / 2) * Wc + c / 2) * mv + xv;
+        const size_t dst = (size_t)kr * row_v + j;
+        const vec_t v = reinterpret_cast<const vec_t*>(coarse)[src];
+        reinterpret_cast<vec_t*>(fine0)[dst] = v;
+        const bool off_grid = (k == kLeft && c == 0) || (k == kRight && c == Wf - 1) || (k == kUp && r == 0) ||
+                              (k == kDown && r == Hf - 1);
+        if (all1 || off_grid) reinterpret_cast<vec_t*>(fine1)[dst] = v;
     }
 }
 
@@ -78,11 +93,17 @@ hipError_t launch_pyramid(const float* fine, int Hf, int Wf, float* coarse, int 
     }
 }
 
-hipError_t launch_prolong(const float* coarse, int Hc, int Wc, float* fine, int Hf, int Wf, int M, hipStream_t s) {
-    const size_t n = (size_t)4 * Hf * Wf * M;
-    size_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(prolong_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, coarse, Hc, Wc, fine, Hf, Wf, M);
+hipError_t launch_prolong(const float* coarse, int Hc, int Wc, float* fine0, float* fine1, bool all1, int Hf,
+                          int Wf, int M, hipStream_t s) {
+    const int vec = M % 4 == 0 ? 4 : 1;
+    const unsigned bx = (unsigned)(((size_t)Wf * (M / vec) + kBlock - 1) / kBlock);
+    const dim3 grid(bx, (unsigned)std::min(4 * Hf, 65535));
+    if (vec == 4)
+        hipLaunchKernelGGL(prolong_kernel<4>, grid, dim3(kBlock), 0, s, coarse, Hc, Wc, fine0, fine1, (int)all1, Hf, Wf,
+                           M);
+    else
+        hipLaunchKernelGGL(prolong_kernel<1>, grid, dim3(kBlock), 0, s, coarse, Hc, Wc, fine0, fine1, (int)all1, Hf, Wf,
+                           M);
     return hipGetLastError();
 }
 
@@ -186,11 +207,11 @@ int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_
             // Both buffers: slots of off-grid neighbours are never updated, and
             // a child's inbox copies its block's, off-grid slots included, so
             // they must hold the prolonged values whichever buffer is current.
-            for (int b = 0; b < 2; ++b) {
-                e = bpk::launch_prolong(buf(l + 1, cur), L[l + 1].H, L[l + 1].W, buf(l, b), L[l].H, L[l].W, G->M,
-                                        G->stream);
-                if (e != hipSuccess) return hip_fail(e, "prolongation launch");
-            }
+            // The level's first update writes every other slot of buffer 1,
+            // so with iterations to come only the off-grid ones are copied.
+            e = bpk::launch_prolong(buf(l + 1, cur), L[l + 1].H, L[l + 1].W, buf(l, 0), buf(l, 1), iters[l] == 0,
+                                    L[l].H, L[l].W, G->M, G->stream);
+            if (e != hipSuccess) return hip_fail(e, "prolongation launch");
             cur = 0;
         }
         // synchronous iterations of this level, two per launch where the
