@@ -92,8 +92,18 @@ __global__ __launch_bounds__(kBlock) void adjoint_seed_kernel(SeedArgs a) {
         if (px.has[k]) store_labels<true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, abar);
 }
 
-// One reverse synchronous step (see the header comment).
-template <int G, int TW>
+// A read-only row of zeros: the adjoint of a message that does not exist.
+struct ZeroRow {
+    float v[kMaxTab];
+};
+static __device__ ZeroRow kZeroRow = ZeroRow();  // never written
+
+// One reverse synchronous step (see the header comment).  FULL: M == 4G.
+// Loads are unconditional: a missing inbox row is read from the row of ones
+// and a missing neighbour's adjoint from the row of zeros, and a slot past
+// the last pixel reads pixel 0 (and stores nothing), so that every load of
+// the group sits in one basic block.
+template <int G, int TW, bool FULL>
 __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
     constexpr int RPB = kBlock / G;
     __shared__ float red[RPB];
@@ -102,10 +112,16 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
     const int slot = blockIdx.x * RPB + grp;
     const Pixel px = sync_pixel(slot, a.H, a.W, a.N);
     const int x0 = pos * kLpl;
-    const bool full = a.M == G * kLpl;
+    constexpr bool full = FULL;
     const size_t plane = (size_t)a.N * a.M;
+    const size_t off = px.ok ? (size_t)px.p * a.M : 0;
     PixelInputs in;
-    load_pixel_at(a.g, a.m, a.N, a.M, px, x0, full, in);
+    load_labels<kUnaryNT>(a.g + off, x0, a.M, FULL, in.g, 0.0f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float* row = px.ok && px.has[k] ? a.m + k * plane + off : kOnesRow.v;
+        load_labels<kMsgNT>(row, x0, a.M, FULL, in.m[k], 1.0f);
+    }
     float h[4][kLpl];
     make_h(in, h);
     double hd[4][kLpl];  // the forward update's h, for the recompute of u
@@ -116,12 +132,10 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
     for (int o = 0; o < 4; ++o) {
         const bool live = px.ok && px.has[o];
         float lam[kLpl];
-        if (live) {
-            const int q = neighbour(px, o, a.W);
-            load_labels<true>(a.lam_in + opposite(o) * plane + (size_t)q * a.M, x0, a.M, full, lam, 0.0f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < kLpl; ++i) lam[i] = 0.0f;
+        {
+            const float* row =
+                live ? a.lam_in + opposite(o) * plane + (size_t)neighbour(px, o, a.W) * a.M : kZeroRow.v;
+            load_labels<true>(row, x0, a.M, FULL, lam, 0.0f);
         }
         // forward recompute: u (Eq. 7), Z, m, accumulated in double as in the
         // forward update
@@ -160,11 +174,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
     if (px.ok) {
         float tb[kLpl];
         float* tp = a.theta_bar + (size_t)px.p * a.M;
-        load_labels<false>(tp, x0, a.M, full, tb, 0.0f);
+        load_labels<false>(tp, x0, a.M, FULL, tb, 0.0f);
 #pragma unroll
         for (int i = 0; i < kLpl; ++i)
             tb[i] += (eta[kLeft][i] + eta[kRight][i]) + (eta[kUp][i] + eta[kDown][i]);
-        store_labels<false>(tp, x0, a.M, full, tb);
+        store_labels<false>(tp, x0, a.M, FULL, tb);
         if (a.lam_out) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void adjoint_step_kernel(AdjointArgs a) {
                     const float ud = k < 2 ? eta[kUp][i] + eta[kDown][i] : eta[k ^ 1][i];
                     lo[i] = lr + ud;
                 }
-                store_labels<true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, full, lo);
+                store_labels<true>(a.lam_out + k * plane + (size_t)px.p * a.M, x0, a.M, FULL, lo);
             }
         }
     }

@@ -37,7 +37,11 @@ int adj_round_tw(int T) {
 
 template <int G, int TW>
 hipError_t go_step(const AdjointArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((adjoint_step_kernel<G, TW>), dim3(adjoint_blocks_g<G>(a.N)), dim3(kBlock), 0, s, a);
+    if (a.M == G * kLpl)
+        hipLaunchKernelGGL((adjoint_step_kernel<G, TW, true>), dim3(adjoint_blocks_g<G>(a.N)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((adjoint_step_kernel<G, TW, false>), dim3(adjoint_blocks_g<G>(a.N)), dim3(kBlock), 0, s,
+                           a);
     return hipGetLastError();
 }
 
