@@ -158,16 +158,46 @@ __device__ __forceinline__ double xor32_d(double v) {
                             __builtin_amdgcn_ds_bpermute(src, __double2loint(v)));
 }
 
+// The two rows of an xor-16 (or xor-32) lane pair, on the VALU: with
+// both operands v, v_permlane16_swap leaves lane i with the values of lanes
+// i & ~16 and i | 16 (v_permlane32_swap: i & ~32 and i | 32), the same pair
+// in the same order on both partners.
+__device__ __forceinline__ void rows16_d(double v, double& lo_row, double& hi_row) {
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false,
+                                                    false);
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false,
+                                                    false);
+    lo_row = __hiloint2double((int)h[0], (int)l[0]);
+    hi_row = __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ void rows32_d(double v, double& lo_half, double& hi_half) {
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false,
+                                                    false);
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false,
+                                                    false);
+    lo_half = __hiloint2double((int)h[0], (int)l[0]);
+    hi_half = __hiloint2double((int)h[1], (int)l[1]);
+}
+
 // Group sum in double (the sum-product accumulations; same butterfly, so
-// every lane ends with the same bits).
+// every lane ends with the same bits).  The steps across rows add the pair
+// from the row swaps: the same two operands as lane + partner, so the same
+// bits, without a trip through the LDS pipe.
 template <int G>
 __device__ __forceinline__ double group_sum_d(double v) {
     v += dpp_d<kQuad1032>(v);
     v += dpp_d<kQuad2301>(v);
     if constexpr (G >= 8) v += dpp_d<kRowHalfMirror>(v);
     if constexpr (G >= 16) v += dpp_d<kRowMirror>(v);
-    if constexpr (G >= 32) v += xor16_d(v);
-    if constexpr (G >= 64) v += xor32_d(v);
+    double a, b;
+    if constexpr (G >= 32) {
+        rows16_d(v, a, b);
+        v = a + b;
+    }
+    if constexpr (G >= 64) {
+        rows32_d(v, a, b);
+        v = a + b;
+    }
     return v;
 }
 
@@ -177,8 +207,15 @@ __device__ __forceinline__ double group_max_d(double v) {
     v = fmax(v, dpp_d<kQuad2301>(v));
     if constexpr (G >= 8) v = fmax(v, dpp_d<kRowHalfMirror>(v));
     if constexpr (G >= 16) v = fmax(v, dpp_d<kRowMirror>(v));
-    if constexpr (G >= 32) v = fmax(v, xor16_d(v));
-    if constexpr (G >= 64) v = fmax(v, xor32_d(v));
+    double a, b;
+    if constexpr (G >= 32) {
+        rows16_d(v, a, b);
+        v = fmax(a, b);
+    }
+    if constexpr (G >= 64) {
+        rows32_d(v, a, b);
+        v = fmax(a, b);
+    }
     return v;
 }
 
