@@ -194,6 +194,19 @@ __device__ __forceinline__ void max_message_d(const double (&h)[kLpl], const flo
 // kernel's bit for bit.
 constexpr int eq10_row_doubles(int G) { return G + 2 * G * kLpl; }
 
+// Hillis-Steele max scans over a group of G <= 16 lanes, steps K, 2K, ...:
+// pre ends as the max over lanes 0..pos, suf over lanes pos..G-1.
+template <int G, int K>
+__device__ __forceinline__ void scan_max_d(double& pre, double& suf, int pos) {
+    if constexpr (K < G) {
+        const double lo = from_lower_d<G, K>(pre, pos);
+        const double hi = from_upper_d<G, K>(suf, pos);
+        pre = fmax(pre, lo);
+        suf = fmax(suf, hi);
+        scan_max_d<G, 2 * K>(pre, suf, pos);
+    }
+}
+
 template <int G, int TW>
 __device__ __forceinline__ void max_message_eq10_d(const double (&h)[kLpl], const float* tab, float fbar, int T,
                                                    int pos, int M, int x0, bool full, double* row, float (&m)[kLpl]) {
@@ -202,13 +215,23 @@ __device__ __forceinline__ void max_message_eq10_d(const double (&h)[kLpl], cons
     double* P = row + G;  // [CAP] prefix maxima
     double* S = P + CAP;  // [CAP] suffix maxima
     wave_sync();          // the previous message is done with the row
-    lm[pos] = fmax(fmax(h[0], h[1]), fmax(h[2], h[3]));
-    wave_sync();
-    double before = 0.0, after = 0.0;
-    for (int j = 0; j < G; ++j) {
-        const double v = lm[j];
-        if (j < pos) before = fmax(before, v);
-        if (j > pos) after = fmax(after, v);
+    const double bm = fmax(fmax(h[0], h[1]), fmax(h[2], h[3]));
+    double before = 0.0, after = 0.0;  // max of the block maxima of the lanes below / above
+    if constexpr (G <= 16) {
+        // inclusive max scans up and down the group by lane shifts (0 past
+        // the group's ends), then one more shift for the exclusive ones
+        double pre = bm, suf = bm;
+        scan_max_d<G, 1>(pre, suf, pos);
+        before = from_lower_d<G, 1>(pre, pos);
+        after = from_upper_d<G, 1>(suf, pos);
+    } else {
+        lm[pos] = bm;
+        wave_sync();
+        for (int j = 0; j < G; ++j) {
+            const double v = lm[j];
+            if (j < pos) before = fmax(before, v);
+            if (j > pos) after = fmax(after, v);
+        }
     }
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) {
