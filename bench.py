@@ -461,8 +461,7 @@ def main():
         grid.reset()
         n = cfg.iters if schedule == "sync" else 2 * cfg.iters
         grid.iterate(mode, n, schedule, dense=dense)
-        grid.beliefs(beliefs)
-        grid.map_labels(labels)
+        grid.readout(beliefs, labels)
 
     log(f"bench: {cfg.name} {cfg.H}x{cfg.W} M={cfg.M} T={cfg.T} iters={cfg.iters}")
     for _ in range(args.warmup):

@@ -277,6 +277,12 @@ int bp_beliefs(bp_grid* grid, float* out_dev);
  * return, lowest label on ties, into out_dev (device, [H][W] int32). */
 int bp_map_labels(bp_grid* grid, int32_t* out_dev);
 
+/* Beliefs and MAP labels in one pass over the messages (Eq. 3 and its
+ * argmax): the same values bp_beliefs and bp_map_labels write, into either
+ * output or both (device, [H][W][M] float32 16-byte aligned and [H][W]
+ * int32; BP_EINVAL when both are null or beliefs_dev is misaligned). */
+int bp_readout(bp_grid* grid, float* beliefs_dev, int32_t* labels_dev);
+
 /* Copy the current message state out of / into the handle (device,
  * [4][H][W][M] layout above); for checkpoints and warm starts.  set_messages
  * keeps the checkerboard pass parity. */

@@ -81,6 +81,7 @@ _PROTOS = {
     "bp_iterate_dense": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_beliefs": (_c_int, [_vp, _vp]),
     "bp_map_labels": (_c_int, [_vp, _vp]),
+    "bp_readout": (_c_int, [_vp, _vp, _vp]),
     "bp_get_messages": (_c_int, [_vp, _vp]),
     "bp_set_messages": (_c_int, [_vp, _vp]),
     "bp_grad_workspace_bytes": (_c_i64, [_vp, _c_i32, _c_i32]),
@@ -302,6 +303,10 @@ def bp_beliefs(handle, out):
 
 def bp_map_labels(handle, out):
     _check(lib().bp_map_labels(handle, _ptr(out)), "bp_map_labels")
+
+
+def bp_readout(handle, beliefs, labels):
+    _check(lib().bp_readout(handle, _ptr(beliefs), _ptr(labels)), "bp_readout")
 
 
 def bp_get_messages(handle, dst):

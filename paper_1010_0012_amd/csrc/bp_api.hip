@@ -294,12 +294,13 @@ int bp_reset_messages(bp_grid* G) {
     if (st) return st;
     G->cur = 0;
     G->cb_pass = 0;
-    // both ping-pong buffers, so slots no update writes (off-grid neighbours)
-    // read 1/M whichever buffer is current
-    for (int b = 0; b < 2; ++b) {
-        hipError_t e = bpk::launch_fill(G->msg[b], G->msg_floats(), 1.0f / (float)G->M, G->stream);
-        if (e != hipSuccess) return hip_fail(e, "message reset");
-    }
+    // The current buffer in full; in the other, the slots no update writes
+    // (those of off-grid neighbours), so that they read 1/M whichever buffer
+    // is current: the first launch into it writes every other slot.
+    hipError_t e = bpk::launch_fill(G->msg[0], G->msg_floats(), 1.0f / (float)G->M, G->stream);
+    if (e != hipSuccess) return hip_fail(e, "message reset");
+    e = bpk::launch_fill_border(G->msg[1], G->H, G->W, G->M, 1.0f / (float)G->M, G->stream);
+    if (e != hipSuccess) return hip_fail(e, "message reset");
     return BP_OK;
 }
 
@@ -329,6 +330,12 @@ int bp_beliefs(bp_grid* G, float* out_dev) {
 int bp_map_labels(bp_grid* G, int32_t* out_dev) {
     if (!out_dev) return fail(BP_EINVAL, "null labels output");
     return readout(G, nullptr, out_dev);
+}
+
+int bp_readout(bp_grid* G, float* beliefs_dev, int32_t* labels_dev) {
+    if (!beliefs_dev && !labels_dev) return fail(BP_EINVAL, "null beliefs and labels outputs");
+    if (reinterpret_cast<uintptr_t>(beliefs_dev) % 16) return fail(BP_EINVAL, "beliefs output not 16-byte aligned");
+    return readout(G, beliefs_dev, labels_dev);
 }
 
 int bp_get_messages(const bp_grid* G, float* dst_dev) {

@@ -11,6 +11,27 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(float* dst, size_t n, floa
         dst[i] = value;
 }
 
+// n4 float4 stores (dst 16-byte aligned).
+__global__ __launch_bounds__(kBlock) void fill4_kernel(v4f* dst, size_t n4, float value) {
+    const v4f v = {value, value, value, value};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (size_t)gridDim.x * kBlock) dst[i] = v;
+}
+
+// One thread per (border slot, label): slots [0, H) are the left slots of
+// column 0, [H, 2H) the right slots of column W-1, [2H, 2H+W) the up slots of
+// row 0, [2H+W, 2H+2W) the down slots of row H-1.
+__global__ __launch_bounds__(kBlock) void fill_border_kernel(float* msg, int H, int W, int M, float value) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (size_t)2 * (H + W) * M) return;
+    const int s = (int)(i / M), x = (int)(i - (size_t)s * M);
+    int k, p;
+    if (s < H) { k = kLeft; p = s * W; }
+    else if (s < 2 * H) { k = kRight; p = (s - H) * W + W - 1; }
+    else if (s < 2 * H + W) { k = kUp; p = s - 2 * H; }
+    else { k = kDown; p = (H - 1) * W + (s - 2 * H - W); }
+    msg[((size_t)k * H * W + p) * M + x] = value;
+}
+
 
 template <int G, int MODE>
 hipError_t go_dense(const UpdateArgs& a, hipStream_t s) {
@@ -68,9 +89,24 @@ hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipS
 
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream) {
     if (n == 0) return hipSuccess;
+    if (n % 4 == 0 && reinterpret_cast<uintptr_t>(dst) % 16 == 0) {
+        size_t blocks = (n / 4 + kBlock - 1) / kBlock;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(fill4_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, reinterpret_cast<v4f*>(dst),
+                           n / 4, value);
+        return hipGetLastError();
+    }
     size_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, dst, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_border(float* msg, int H, int W, int M, float value, hipStream_t stream) {
+    const size_t n = (size_t)2 * (H + W) * M;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_border_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, msg,
+                       H, W, M, value);
     return hipGetLastError();
 }
 

@@ -124,6 +124,16 @@ class Grid:
         L.bp_map_labels(self.handle, out)
         return out
 
+    def readout(self, beliefs=None, labels=None):
+        """Beliefs and MAP labels in one pass over the messages."""
+        if beliefs is None:
+            beliefs = torch.empty((self.H, self.W, self.M), dtype=torch.float32, device=self.device)
+        if labels is None:
+            labels = torch.empty((self.H, self.W), dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        L.bp_readout(self.handle, beliefs, labels)
+        return beliefs, labels
+
     def get_messages(self, out=None):
         if out is None:
             out = torch.empty((4, self.H, self.W, self.M), dtype=torch.float32, device=self.device)

@@ -157,6 +157,50 @@ def test_zero_iterations_and_isolated_pixel():
     np.testing.assert_allclose(b1, g1 / g1.sum(-1, keepdims=True), atol=1e-7)
 
 
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("shape", [(7, 9, 64, 4), (5, 6, 20, 3), (1, 5, 16, 2)], ids=lambda s: "H{}W{}M{}T{}".format(*s))
+def test_readout_equals_separate_calls(shape, mode):
+    """bp_readout writes the same beliefs and labels as bp_beliefs and
+    bp_map_labels, bit for bit, into either output or both."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M, T = shape
+    say(f"readout {mode} {shape}")
+    grid = Grid(H, W)
+    grid.set_potential(M, T, 0.6)
+    grid.set_unary(torch.from_numpy(random_unary(H, W, M, 41)).cuda())
+    grid.iterate(mode, 5)
+    b0, l0 = grid.beliefs(), grid.map_labels()
+    b1, l1 = grid.readout()
+    b2 = torch.full_like(b1, -1.0)
+    l2 = torch.full_like(l1, -1)
+    from paper_1010_0012_amd import _lib as L
+    L.bp_readout(grid.handle, b2, None)
+    L.bp_readout(grid.handle, None, l2)
+    torch.cuda.synchronize()
+    for x in (b1, b2):
+        assert torch.equal(x, b0)
+    for x in (l1, l2):
+        assert torch.equal(x, l0)
+    grid.close()
+
+
+@pytest.mark.parametrize("schedule,n", [("sync", 1), ("sync", 3), ("checkerboard", 2)])
+def test_reset_off_grid_slots(schedule, n):
+    """After a reset and updates that leave the other buffer current, the
+    slots of off-grid neighbours (which no update writes) read 1/M, and the
+    state equals the oracle's."""
+    H, W, M, T = 5, 7, 16, 2
+    g32 = random_unary(H, W, M, 43)
+    say(f"reset off-grid {schedule} n={n}")
+    gpu = run_gpu(g32, M, T, 0.8, None, "sum", schedule, n)
+    msg = gpu[0]
+    u = np.float32(1.0 / M)
+    for k, sl in ((0, np.s_[:, 0]), (1, np.s_[:, W - 1]), (2, np.s_[0, :]), (3, np.s_[H - 1, :])):
+        assert np.all(msg[k][sl] == u), (k, schedule, n)
+    compare(f"reset {schedule} {n}", gpu, run_oracle(g32, M, T, 0.8, None, "sum", schedule, n))
+
+
 def test_warm_start_messages():
     """set_messages followed by iterate equals the oracle started from the
     same (float32) state."""
