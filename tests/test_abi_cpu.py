@@ -34,6 +34,8 @@ def test_host_side_argument_checks():
     assert lib.bp_iterate(None, 0, 1, 0) == L.BP_EINVAL
     assert lib.bp_workspace_bytes(None) == L.BP_EINVAL
     assert lib.bp_beliefs(None, None) == L.BP_EINVAL
+    assert lib.bp_readout(None, None, None) == L.BP_EINVAL
+    assert lib.bp_readout(None, ctypes.c_void_p(16), None) == L.BP_EINVAL
     assert lib.bp_destroy(None) == L.BP_OK
 
 

@@ -244,6 +244,13 @@ def test_api_errors():
     with pytest.raises(L.BPError) as e:
         L.bp_iterate(h, 7, 1, 0)
     assert e.value.status == L.BP_EINVAL
+    b = torch.empty(4 * 4 * 8 + 1, device="cuda")
+    with pytest.raises(L.BPError) as e:                # readout: neither output
+        L.bp_readout(h, None, None)
+    assert e.value.status == L.BP_EINVAL
+    with pytest.raises(L.BPError) as e:                # beliefs not 16-byte aligned
+        L.bp_readout(h, b.data_ptr() + 4, None)
+    assert e.value.status == L.BP_EINVAL
     L.bp_set_potential(h, 200, 2, 1.0, math.exp(-2.0))
     with pytest.raises(L.BPError) as e:                # M changed: workspace dropped
         L.bp_iterate(h, 0, 1, 0)
