@@ -113,7 +113,12 @@ int64_t bp_workspace_bytes(const bp_grid* grid);
 int bp_attach_workspace(bp_grid* grid, void* dev_ptr, int64_t bytes);
 
 /* Borrow the unary table g (device, [H][W][M], 16-byte aligned) until the
- * next bp_set_unary, a change of M, or bp_destroy. */
+ * next bp_set_unary, a change of M, or bp_destroy.  Every entry must be
+ * finite and >= 0, with a positive entry in every row (otherwise the
+ * pixel's messages are 0/0 under Eq. 5 and the normalisation).  With the
+ * environment variable BP_VALIDATE=1 this is checked on the device: the call
+ * then waits for the stream, returns BP_EINVAL on a violating table (keeping
+ * the previous one), and BP_ESTATE if no workspace is attached yet. */
 int bp_set_unary(bp_grid* grid, const float* g_dev);
 
 /* All messages := 1/M (the usual uniform start). */

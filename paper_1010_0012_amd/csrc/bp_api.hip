@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -257,7 +258,7 @@ int bp_set_potential(bp_grid* G, int32_t M, int32_t T, float alpha, float fbar) 
 int64_t bp_workspace_bytes(const bp_grid* G) {
     if (!G) return fail(BP_EINVAL, "null handle");
     if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
-    return (int64_t)(2 * align_up(G->msg_floats() * sizeof(float), 256) + window_table_bytes(G->M));
+    return (int64_t)(validate_flag_offset(G) + 256);
 }
 
 int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {
@@ -282,6 +283,23 @@ int bp_set_unary(bp_grid* G, const float* g_dev) {
     if (!G->pot_set) return fail(BP_ESTATE, "bp_set_potential has not been called");
     if (!g_dev) return fail(BP_EINVAL, "null unary");
     if (reinterpret_cast<uintptr_t>(g_dev) % 16) return fail(BP_EINVAL, "unary not 16-byte aligned");
+    const char* v = std::getenv("BP_VALIDATE");
+    if (v && v[0] == '1') {
+        // A row with a negative or non-finite entry, or with no positive
+        // entry, would make every message from that pixel 0/0 (Eq. 5 and the
+        // normalisation): check on the device and wait for the answer.
+        if (!G->ws) return fail(BP_ESTATE, "BP_VALIDATE checks need the workspace attached first");
+        int st = with_device(G);
+        if (st) return st;
+        int* flag = reinterpret_cast<int*>(static_cast<char*>(G->ws) + validate_flag_offset(G));
+        hipError_t e = bpk::launch_validate_unary(g_dev, G->N, G->M, flag, G->stream);
+        int bad = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, G->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
+        if (e != hipSuccess) return hip_fail(e, "unary validation");
+        if (bad)
+            return fail(BP_EINVAL, "unary has a negative or non-finite entry, or a row with no positive entry");
+    }
     G->g = g_dev;
     return BP_OK;
 }

@@ -69,6 +69,11 @@ bpk::UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int col
 // Device bytes of the window-potential table region at the end of the
 // workspace (Eq. 10 fallback of max-product when fbar exceeds f).
 size_t window_table_bytes(int M);
+// Byte offset in the workspace of the int flag of the unary check (after the
+// two message buffers and the window tables).
+inline size_t validate_flag_offset(const bp_grid* G) {
+    return 2 * bp_align_up(G->msg_floats() * sizeof(float), 256) + bp_align_up(window_table_bytes(G->M), 256);
+}
 // n iterations through the general kernel (caller's tables, or the window
 // potential's Eq. 10 tables); schedule sync, checkerboard or sweep.
 int iterate_general(bp_grid* G, int kmode, int n, int schedule);

@@ -54,6 +54,9 @@ hipError_t launch_batch_pair_max(int arm, bool full, const BatchLaunch& L, unsig
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);
+// flag := 1 if some row of the [N][M] unary has a negative or non-finite
+// entry or no positive entry, else 0.
+hipError_t launch_validate_unary(const float* g, int N, int M, int* flag, hipStream_t stream);
 // value into the inbox slots of off-grid neighbours of a [4][H][W][M] buffer
 // (left slots of column 0, right of column W-1, up of row 0, down of row H-1).
 hipError_t launch_fill_border(float* msg, int H, int W, int M, float value, hipStream_t stream);

@@ -11,6 +11,20 @@ __global__ __launch_bounds__(kBlock) void fill_kernel(float* dst, size_t n, floa
         dst[i] = value;
 }
 
+// One thread per unary row; a bad row sets the flag (every writer stores 1).
+__global__ __launch_bounds__(kBlock) void validate_unary_kernel(const float* g, int N, int M, int* flag) {
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    const float* row = g + (size_t)p * M;
+    bool ok = true, any = false;
+    for (int x = 0; x < M; ++x) {
+        const float v = row[x];
+        ok = ok && isfinite(v) && v >= 0.0f;
+        any = any || v > 0.0f;
+    }
+    if (!ok || !any) *flag = 1;
+}
+
 // n4 float4 stores (dst 16-byte aligned).
 __global__ __launch_bounds__(kBlock) void fill4_kernel(v4f* dst, size_t n4, float value) {
     const v4f v = {value, value, value, value};
@@ -99,6 +113,14 @@ hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream) {
     size_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, dst, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_unary(const float* g, int N, int M, int* flag, hipStream_t stream) {
+    hipError_t e = launch_fill(reinterpret_cast<float*>(flag), 1, 0.0f, stream);  // int 0
+    if (e != hipSuccess || N <= 0) return e;
+    hipLaunchKernelGGL(validate_unary_kernel, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, g,
+                       N, M, flag);
     return hipGetLastError();
 }
 

@@ -201,6 +201,40 @@ def test_reset_off_grid_slots(schedule, n):
     compare(f"reset {schedule} {n}", gpu, run_oracle(g32, M, T, 0.8, None, "sum", schedule, n))
 
 
+def test_unary_validation(monkeypatch):
+    """With BP_VALIDATE=1, bp_set_unary rejects a table with a negative or
+    non-finite entry or a row with no positive entry, keeps the previous
+    table, and accepts a valid one; without it, no check runs."""
+    import torch
+    from paper_1010_0012_amd import _lib as L
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M = 5, 6, 12
+    say("unary validation")
+    grid = Grid(H, W)
+    grid.set_potential(M, 2, 0.8)
+    good = torch.from_numpy(random_unary(H, W, M, 47)).cuda()
+    monkeypatch.setenv("BP_VALIDATE", "1")
+    grid.set_unary(good)
+    for r, c, x, v in ((2, 3, None, 0.0), (0, 5, 7, float("nan")), (4, 0, 3, -1e-3), (1, 1, 0, float("inf"))):
+        bad = good.clone()
+        if x is None:
+            bad[r, c, :] = v
+        else:
+            bad[r, c, x] = v
+        with pytest.raises(L.BPError) as e:
+            L.bp_set_unary(grid.handle, bad)
+        assert e.value.status == L.BP_EINVAL
+    grid.iterate("sum", 3)                     # still the good table
+    b = grid.beliefs()
+    monkeypatch.delenv("BP_VALIDATE")
+    zero_row = good.clone()
+    zero_row[0, 0, :] = 0.0
+    L.bp_set_unary(grid.handle, zero_row)       # no check without the variable
+    torch.cuda.synchronize()
+    assert torch.isfinite(b).all()
+    grid.close()
+
+
 def test_warm_start_messages():
     """set_messages followed by iterate equals the oracle started from the
     same (float32) state."""
