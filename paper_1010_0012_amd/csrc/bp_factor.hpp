@@ -173,8 +173,9 @@ __device__ __forceinline__ double split_outside(const FgArgs& a, int k, int i, i
 }
 
 // STAGE: the workgroup first copies its (type, slot) table rows to LDS
-// (values as double: f - fbar for sum, f for max), so the per-entry reads of
-// every message are LDS reads, shared by all of its groups.
+// (values as double: f - fbar for sum, f for max; the other slots' labels as
+// their positions in the nj rows), so the per-entry reads of every message
+// are LDS reads, shared by all of its groups, with no index arithmetic.
 template <int G, int MODE, bool EQ10, bool STAGE>
 __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     extern __shared__ double lds_d[];
@@ -203,7 +204,8 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     if constexpr (STAGE) {
         for (int e = threadIdx.x; e < row0[a.M] - e_base; e += kBlock) {
             st_w[e] = MODE == kSum ? a.ent_w[e_base + e] : (double)a.ent_f[e_base + e];
-            st_o[e] = a.ent_o[e_base + e];
+            const int2 o = a.ent_o[e_base + e];
+            st_o[e] = make_int2(row_slot<G>(o.x), row_slot<G>(o.y));  // the labels' slots in the nj rows
         }
     }
     // the other slots in slot order
@@ -238,10 +240,16 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
         double acc = split ? 0.0 : base;  // the split form replaces the fbar * prod H term
         if (x < a.M) {
             for (int e = row[x]; e < row[x + 1]; ++e) {
-                const int2 o = STAGE ? st_o[e - e_base] : a.ent_o[e];
+                int2 o;
+                if constexpr (STAGE) {
+                    o = st_o[e - e_base];
+                } else {
+                    o = a.ent_o[e];
+                    o = make_int2(row_slot<G>(o.x), row_slot<G>(o.y));
+                }
                 double p = STAGE ? st_w[e - e_base] : MODE == kSum ? a.ent_w[e] : (double)a.ent_f[e];
-                p *= nj[0][row_slot<G>(o.x)];
-                if (n_oth == 2) p *= nj[1][row_slot<G>(o.y)];
+                p *= nj[0][o.x];
+                if (n_oth == 2) p *= nj[1][o.y];
                 acc = MODE == kSum ? acc + p : fmax(acc, p);
             }
             if (split) acc = fmax(acc, split_outside<G>(a, k, i, row[x], row[x + 1], n_oth, nj[0], top_v, top_i));
