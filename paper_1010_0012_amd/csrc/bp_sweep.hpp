@@ -89,12 +89,15 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     };
     const int steps = len - 1;  // the last node of the scanline sends nothing this way
     if (steps <= 0) return;     // the same for every group
-    // inputs of the t-th sender (t clamped to the last one)
-    auto load_raw = [&](int t, float (&gv)[kLpl], float (&m0)[kLpl], float (&m1)[kLpl]) {
-        const size_t p = (size_t)sender(min(t, steps - 1));
-        load_labels<kUnaryNT>(a.g + p * a.M, x0, a.M, FULL, gv, 0.0f);
-        load_labels<kMsgNT>(in0 + p * stride0, x0, a.M, FULL, m0, 1.0f);
-        load_labels<kMsgNT>(in1 + p * stride1, x0, a.M, FULL, m1, 1.0f);
+    // Consecutive senders are a fixed number of pixels apart, so the walk
+    // advances pointers instead of recomputing offsets.
+    const long dpix = (forward ? 1L : -1L) * (horiz ? 1L : (long)a.W);
+    // inputs of the sender whose unary is at gp (and side rows at s0, s1)
+    auto load_raw = [&](const float* gp, const float* s0, const float* s1, float (&gv)[kLpl], float (&m0)[kLpl],
+                        float (&m1)[kLpl]) {
+        load_labels<kUnaryNT>(gp, x0, a.M, FULL, gv, 0.0f);
+        load_labels<kMsgNT>(s0, x0, a.M, FULL, m0, 1.0f);
+        load_labels<kMsgNT>(s1, x0, a.M, FULL, m1, 1.0f);
     };
 
     // Inputs of the next kAhead senders in flight: a ring of registers,
@@ -103,8 +106,26 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
+    // the next sender to load (t clamped to the last one) and its rows
+    const long p0 = sender(0);
+    const float* gp = a.g + p0 * a.M;
+    const float* s0p = in0 + p0 * (long)stride0;
+    const float* s1p = in1 + p0 * (long)stride1;
+    const long dg = dpix * a.M, d0 = dpix * (long)stride0, d1 = dpix * (long)stride1;
+    auto advance = [&](int t_loaded) {  // after loading sender t_loaded
+        if (t_loaded + 1 < steps) {
+            gp += dg;
+            s0p += d0;
+            s1p += d1;
+        }
+    };
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) load_raw(j, rg[j], r0[j], r1[j]);
+    for (int j = 0; j < kAhead; ++j) {
+        load_raw(gp, s0p, s1p, rg[j], r0[j], r1[j]);
+        advance(j);
+    }
+    // where the t-th sender's message goes (receiver's inbox slot)
+    float* op = a.out + opposite(dir) * plane + (p0 + step_q) * (long)a.M;
     for (int t0 = 0; t0 < steps; t0 += kAhead) {
 #pragma unroll
         for (int j = 0; j < kAhead; ++j) {
@@ -113,14 +134,13 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
             double h[kLpl];  // Eq. 5, in double as in the other updates
 #pragma unroll
             for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
-            load_raw(t + kAhead, rg[j], r0[j], r1[j]);
+            load_raw(gp, s0p, s1p, rg[j], r0[j], r1[j]);
+            advance(t + kAhead);
             float m[kLpl];
             const int s = along(t);
             msg(h, horiz ? line : s, horiz ? s : line, dir, m);
-            if (live) {
-                const int q = sender(t) + step_q;
-                store_labels<kMsgNT>(a.out + opposite(dir) * plane + (size_t)q * a.M, x0, a.M, FULL, m);
-            }
+            if (live) store_labels<kMsgNT>(op, x0, a.M, FULL, m);
+            op += dg;
 #pragma unroll
             for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
         }
