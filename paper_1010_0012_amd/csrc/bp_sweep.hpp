@@ -9,7 +9,7 @@
 // sent is exactly the inbox entry the next sender reads from the opposite
 // side, so it stays in registers (the carry) as well as being stored for the
 // later passes and the readout.  The unary and the two perpendicular inbox
-// messages of a sender do not depend on the carry and are loaded four steps
+// messages of a sender do not depend on the carry and are loaded eight steps
 // ahead.  Those loads are unconditional, so that the ring of inputs in flight
 // needs no copies and no branches: groups past the last scanline read the
 // last one, the walk's tail re-reads its last sender, and a missing
@@ -101,8 +101,10 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     };
 
     // Inputs of the next kAhead senders in flight: a ring of registers,
-    // statically indexed by unrolling the step loop by kAhead.
-    constexpr int kAhead = 4;
+    // statically indexed by unrolling the step loop by kAhead.  A step takes
+    // about 0.4 us at one wave per SIMD, so eight steps cover a load's
+    // latency; with twelve or more the ring no longer stays in registers.
+    constexpr int kAhead = 8;
     float rg[kAhead][kLpl], r0[kAhead][kLpl], r1[kAhead][kLpl], carry[kLpl];
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
