@@ -232,7 +232,9 @@ __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a, int s
     double h[4][kLpl];
     make_h_d(in, h);
     const size_t plane = (size_t)a.u.N * M;
-#pragma unroll 1
+    // unrolled: indexed by a loop counter, h[o] and px.has[o] would live in
+    // scratch memory
+#pragma unroll
     for (int o = 0; o < 4; ++o) {
         const bool live = px.ok && px.has[o];
         const int k = live ? edge_type(a, px, o) : 0;
