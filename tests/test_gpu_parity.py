@@ -442,3 +442,68 @@ def test_stereo288x384_max_sampled(schedule):
     n = cfg.iters if schedule == "sync" else 2 * cfg.iters
     say(f"stereo288x384 max {schedule} x{n}")
     _sampled_one_step(cfg, g32, "max", schedule, n)
+
+
+def test_offsets_beyond_2_31():
+    """A 4096 x 4096 grid with M = 40: each message buffer holds 2.7e9 floats
+    (more than 2^31), so every offset has to be 64-bit.  Sampled messages of
+    the second iteration, most of them in the last rows and the last inbox
+    plane, equal the oracle's single update from the GPU's first-iteration
+    state; and the two-iteration launch equals two one-iteration launches bit
+    for bit over the whole buffer."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H = W = 4096
+    M, T, alpha = 40, 3, 0.7
+    say(f"offsets beyond 2^31: {H}x{W}x{M}")
+    gen = torch.Generator(device="cuda").manual_seed(31)
+    g = torch.rand((H, W, M), generator=gen, device="cuda") * 0.9 + 0.1
+    grid = Grid(H, W)
+    grid.set_potential(M, T, alpha)
+    grid.set_unary(g)
+    grid.set_sync_fusion(False)
+    grid.iterate("sum", 1)
+    s1 = grid.get_messages()
+    grid.iterate("sum", 1)
+    s2 = grid.get_messages()
+    grid.reset()
+    grid.set_sync_fusion(True)
+    grid.iterate("sum", 2)
+    pair = grid.get_messages()
+    torch.cuda.synchronize()
+    assert 4 * H * W * M > 2 ** 31
+    assert torch.equal(pair, s2)
+    del pair
+    pot = gb.truncated_linear(M, T, float(np.float32(alpha)))
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    checked = 0
+    while checked < 96:
+        tail = checked < 64
+        r = int(rng.integers(H - 3, H)) if tail else int(rng.integers(0, H))
+        c = int(rng.integers(0, W))
+        o = gb.DOWN if tail and checked % 2 == 0 else int(rng.integers(0, 4))
+        dr, dc = gb.OFFSETS[o]
+        if not (0 <= r + dr < H and 0 <= c + dc < W):
+            continue
+        r0, r1, c0, c1 = max(0, r - 1), min(H, r + 2), max(0, c - 1), min(W, c + 2)
+        g_crop = g[r0:r1, c0:c1].double().cpu().numpy()
+        prev = s1[:, r0:r1, c0:c1].double().cpu().numpy()
+        ref = gb.single_update(g_crop, prev, pot, "sum", r - r0, c - c0, o)
+        got = s2[gb.OPPOSITE[o], r + dr, c + dc].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref))))
+        checked += 1
+    say(f"offsets beyond 2^31: one-step max|dm|={worst:.2e}")
+    assert worst <= 1e-6
+    del s1, s2
+    # checkerboard: a pass pair equals two single passes
+    grid.reset()
+    grid.set_sync_fusion(False)
+    grid.iterate("sum", 2, "checkerboard")
+    cb = grid.get_messages()
+    grid.reset()
+    grid.set_sync_fusion(True)
+    grid.iterate("sum", 2, "checkerboard")
+    torch.cuda.synchronize()
+    assert torch.equal(grid.get_messages(), cb)
+    grid.close()
