@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from bp_gpu_util import check, compare, run_gpu, run_oracle, say
+from bp_gpu_util import check, compare, library_potential, run_gpu, run_oracle, say
 from oracle import grid_bp as gb
 from synth_mrf import CONFIGS, make_config, random_unary
 
@@ -444,7 +444,8 @@ def test_stereo288x384_max_sampled(schedule):
     _sampled_one_step(cfg, g32, "max", schedule, n)
 
 
-def test_offsets_beyond_2_31():
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_offsets_beyond_2_31(mode):
     """A 4096 x 4096 grid with M = 40: each message buffer holds 2.7e9 floats
     (more than 2^31), so every offset has to be 64-bit.  Sampled messages of
     the second iteration, most of them in the last rows and the last inbox
@@ -455,26 +456,26 @@ def test_offsets_beyond_2_31():
     from paper_1010_0012_amd.grid import Grid
     H = W = 4096
     M, T, alpha = 40, 3, 0.7
-    say(f"offsets beyond 2^31: {H}x{W}x{M}")
+    say(f"offsets beyond 2^31: {H}x{W}x{M} {mode}")
     gen = torch.Generator(device="cuda").manual_seed(31)
     g = torch.rand((H, W, M), generator=gen, device="cuda") * 0.9 + 0.1
     grid = Grid(H, W)
     grid.set_potential(M, T, alpha)
     grid.set_unary(g)
     grid.set_sync_fusion(False)
-    grid.iterate("sum", 1)
+    grid.iterate(mode, 1)
     s1 = grid.get_messages()
-    grid.iterate("sum", 1)
+    grid.iterate(mode, 1)
     s2 = grid.get_messages()
     grid.reset()
     grid.set_sync_fusion(True)
-    grid.iterate("sum", 2)
+    grid.iterate(mode, 2)
     pair = grid.get_messages()
     torch.cuda.synchronize()
     assert 4 * H * W * M > 2 ** 31
     assert torch.equal(pair, s2)
     del pair
-    pot = gb.truncated_linear(M, T, float(np.float32(alpha)))
+    pot = library_potential(M, T, alpha, None, mode)
     rng = np.random.default_rng(5)
     worst = 0.0
     checked = 0
@@ -489,21 +490,21 @@ def test_offsets_beyond_2_31():
         r0, r1, c0, c1 = max(0, r - 1), min(H, r + 2), max(0, c - 1), min(W, c + 2)
         g_crop = g[r0:r1, c0:c1].double().cpu().numpy()
         prev = s1[:, r0:r1, c0:c1].double().cpu().numpy()
-        ref = gb.single_update(g_crop, prev, pot, "sum", r - r0, c - c0, o)
+        ref = gb.single_update(g_crop, prev, pot, mode, r - r0, c - c0, o)
         got = s2[gb.OPPOSITE[o], r + dr, c + dc].cpu().numpy()
         worst = max(worst, float(np.max(np.abs(got - ref))))
         checked += 1
-    say(f"offsets beyond 2^31: one-step max|dm|={worst:.2e}")
+    say(f"offsets beyond 2^31 {mode}: one-step max|dm|={worst:.2e}")
     assert worst <= 1e-6
     del s1, s2
     # checkerboard: a pass pair equals two single passes
     grid.reset()
     grid.set_sync_fusion(False)
-    grid.iterate("sum", 2, "checkerboard")
+    grid.iterate(mode, 2, "checkerboard")
     cb = grid.get_messages()
     grid.reset()
     grid.set_sync_fusion(True)
-    grid.iterate("sum", 2, "checkerboard")
+    grid.iterate(mode, 2, "checkerboard")
     torch.cuda.synchronize()
     assert torch.equal(grid.get_messages(), cb)
     grid.close()
