@@ -10,7 +10,7 @@ sender (the horizontal planes they read are not written afterwards).
 import numpy as np
 import pytest
 
-from bp_gpu_util import BELIEF_TOL, MAP_MARGIN, check, compare, run_gpu, run_oracle, say
+from bp_gpu_util import BELIEF_TOL, MAP_MARGIN, check, compare, library_potential, run_gpu, run_oracle, say
 from oracle import brute
 from oracle import grid_bp as gb
 from synth_mrf import CONFIGS, make_config, random_unary
@@ -149,3 +149,47 @@ def test_stereo480x640_sweep_sampled(mode):
     has = gb.has_neighbor(H, W)
     assert msgs[has].min() >= pot.fbar / cfg.M * (1 - 1e-5)
     np.testing.assert_array_equal(lab, np.argmax(b, axis=-1))
+
+
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_sweep_offsets_beyond_2_31(mode):
+    """One sweep of a 4096 x 4096 grid with M = 40 (message buffers beyond
+    2^31 floats).  The vertical passes run last, and a message sent up or
+    down uses the sender's left and right inbox rows (final after the
+    horizontal passes) and the row the same pass has just delivered, so every
+    vertical message equals the oracle's single update from the final state;
+    sampled ones, many in the last rows and columns, are checked."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H = W = 4096
+    M, T, alpha = 40, 3, 0.7
+    say(f"sweep offsets beyond 2^31: {H}x{W}x{M} {mode}")
+    gen = torch.Generator(device="cuda").manual_seed(37)
+    g = torch.rand((H, W, M), generator=gen, device="cuda") * 0.9 + 0.1
+    grid = Grid(H, W)
+    grid.set_potential(M, T, alpha)
+    grid.set_unary(g)
+    grid.iterate(mode, 1, "sweep")
+    post = grid.get_messages()
+    torch.cuda.synchronize()
+    pot = library_potential(M, T, alpha, None, mode)
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    checked = 0
+    while checked < 96:
+        edge = checked < 48
+        r = int(rng.integers(H - 3, H)) if edge and checked % 2 == 0 else int(rng.integers(0, H))
+        c = int(rng.integers(W - 3, W)) if edge and checked % 2 == 1 else int(rng.integers(0, W))
+        o = gb.UP if rng.integers(0, 2) else gb.DOWN
+        dr, dc = gb.OFFSETS[o]
+        if not (0 <= r + dr < H and 0 <= c + dc < W):
+            continue
+        r0, r1, c0, c1 = max(0, r - 1), min(H, r + 2), max(0, c - 1), min(W, c + 2)
+        ref = gb.single_update(g[r0:r1, c0:c1].double().cpu().numpy(), post[:, r0:r1, c0:c1].double().cpu().numpy(),
+                               pot, mode, r - r0, c - c0, o)
+        got = post[gb.OPPOSITE[o], r + dr, c + dc].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref))))
+        checked += 1
+    say(f"sweep offsets beyond 2^31 {mode}: max|dm|={worst:.2e}")
+    assert worst <= 1e-6
+    grid.close()
