@@ -214,3 +214,30 @@ def test_general_full_size_sampled():
     say(f"general full size: sampled max|dm| = {worst:.2e}, |sum - 1| <= {np.max(np.abs(sums - 1)):.2e}")
     assert worst <= 1e-6
     assert np.max(np.abs(sums - 1.0)) <= 1e-5
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+def test_general_offsets_beyond_2_31(schedule):
+    """A 4096 x 4096 grid with M = 40 (message buffers beyond 2^31 floats):
+    the general kernel on the truncated-linear potential as a CSR type equals
+    the window kernel bit for bit (max-product), over the whole buffer."""
+    import torch
+    from paper_1010_0012_amd.grid import Grid
+    H = W = 4096
+    M, T, alpha = 40, 3, 0.7
+    say(f"general offsets beyond 2^31: {H}x{W}x{M} {schedule}")
+    gen = torch.Generator(device="cuda").manual_seed(41)
+    g = torch.rand((H, W, M), generator=gen, device="cuda") * 0.9 + 0.1
+    fbar = float(np.float32(np.exp(-float(np.float32(alpha)) * T)))
+    grid = Grid(H, W)
+    grid.set_potential(M, T, alpha, fbar)
+    grid.set_unary(g)
+    grid.iterate("max", 2, schedule)
+    window = grid.get_messages()
+    grid.set_sparse_potentials([window_csr(M, T, alpha, fbar)])
+    grid.reset()
+    grid.iterate("max", 2, schedule)
+    torch.cuda.synchronize()
+    assert 4 * H * W * M > 2 ** 31
+    assert torch.equal(grid.get_messages(), window)
+    grid.close()
