@@ -500,6 +500,11 @@ def main():
     extra["sparse_sum_sync_single_launch_GBs"] = bytes_launch / (ms_single * 1e-3) / 1e9
     extra["sparse_sum_sync_single_launch_frac"] = bytes_launch / (ms_single * 1e-3) / 1e9 / HBM_PEAK_GBS
     extra["pair_over_single_per_iteration"] = ms_single / (ms_launch / 2)
+    # one iteration's algorithmic bytes over the pair launch's time per
+    # iteration: above the HBM peak means the pair beats the one-iteration
+    # roofline (its first iteration's messages never reach HBM)
+    extra["sparse_sum_sync_pair_per_iteration_equiv_GBs"] = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9
+    extra["sparse_sum_sync_pair_per_iteration_equiv_frac"] = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9 / HBM_PEAK_GBS
     log(f"bench: sparse sum single launch {ms_single * 1e3:.1f} us "
         f"({bytes_launch / (ms_single * 1e-3) / 1e9:.0f} GB/s); pair launch per iteration {ms_launch * 500:.1f} us")
     if not args.no_legs:
