@@ -4,7 +4,7 @@ float32-storage model, same rule as bp_gpu_util.check_against."""
 import numpy as np
 import pytest
 
-from bp_gpu_util import BELIEF_TOL, MAP_MARGIN, MSG_TOL, STORAGE_TOL, say
+from bp_gpu_util import BELIEF_TOL, MAP_MARGIN, MSG_TOL, STORAGE_LIMITED, STORAGE_LIMITED_SEEN, STORAGE_TOL, say
 from oracle import factor_bp as fb
 from oracle import grid_bp as gb
 
@@ -77,9 +77,21 @@ def compare_fg(tag, gpu, fg, g32, mode, n, impl=fb.SPARSE):
     say(f"{tag}: vs f32-storage model max|db|={e32_b:.2e} max|dm|={e32_m:.2e}; vs FP64 max|db|={e64_b:.2e} "
         f"max|dm|={e64_m:.2e} (storage-only deviation {dev_b:.1e})")
     assert e32_b <= STORAGE_TOL and e32_m <= STORAGE_TOL
-    assert e64_b <= max(BELIEF_TOL, dev_b + STORAGE_TOL) and e64_m <= max(MSG_TOL, dev_m + STORAGE_TOL)
-    sure = gb.top2_margin(b64) > max(MAP_MARGIN, 2 * dev_b + STORAGE_TOL)
-    assert np.array_equal(lab[sure], np.argmax(b64, axis=-1)[sure])
+    sure32 = gb.top2_margin(b32) > MAP_MARGIN
+    assert np.array_equal(lab[sure32], np.argmax(b32, axis=-1)[sure32])
+    sure = gb.top2_margin(b64) > MAP_MARGIN
+    flips = int(np.sum((np.argmax(b32, axis=-1) != np.argmax(b64, axis=-1)) & sure))
+    missed = dev_b > BELIEF_TOL or dev_m > MSG_TOL or flips > 0
+    if tag in STORAGE_LIMITED:
+        assert missed, f"{tag} is named storage-limited, but the float32-storage model meets the FP64 bar"
+        bad = int(np.sum((lab != np.argmax(b64, axis=-1)) & sure))
+        say(f"{tag} [FP64, storage-limited: {STORAGE_LIMITED[tag]}]: FP64 bar NOT met by float32 storage: "
+            f"GPU max|db|={e64_b:.2e}, MAP mismatches={bad}; storage model alone max|db|={dev_b:.2e}")
+        STORAGE_LIMITED_SEEN.append((tag, e64_b, bad, dev_b))
+        assert e64_b <= dev_b + STORAGE_TOL
+    else:
+        assert e64_b <= BELIEF_TOL and e64_m <= MSG_TOL, (tag, e64_b, e64_m, dev_b, dev_m)
+        assert np.array_equal(lab[sure], np.argmax(b64, axis=-1)[sure]), tag
     np.testing.assert_array_equal(lab, np.argmax(b_gpu, axis=-1))
 
 

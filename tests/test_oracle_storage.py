@@ -4,7 +4,8 @@ message rounded once to float32).
 - every stored entry is a float32 value, under every schedule;
 - a flat potential (alpha = 0, fbar = 1) sends uniform messages, so after one
   iteration every live entry is float32(1/M) exactly;
-- a step from a float32-valued state is the FP64 step rounded once;
+- after a step every stored entry is its exact message (recomputed one
+  message at a time) rounded to the nearest float32;
 - sum-product stays within rounding of the FP64 result (it contracts
   perturbations): a chain after one sweep is the exact marginal to ~1e-7,
   and a stereo grid after 10 iterations is within 1e-6 of FP64.
@@ -40,12 +41,32 @@ def test_flat_potential_gives_rounded_uniform(schedule):
 
 
 @pytest.mark.parametrize("mode", [gb.SUM, gb.MAX])
-def test_step_is_rounded_fp64_step(mode):
-    g = random_unary(4, 5, 8, 3).astype(np.float64)
-    pot = gb.truncated_linear(8, 2, 0.9)
+def test_step_rounds_each_exact_message_once(mode):
+    """Every entry the storage model stores after a step is the exact message
+    of Eq. 7 / Eq. 11 (recomputed one message at a time by single_update, a
+    separate code path from the vectorised step), rounded to the nearest
+    float32: within half an ulp of it, and float32-representable.  Rounding
+    before the normalisation, rounding h or the window sums, or a narrower
+    format all break the half-ulp bound."""
+    H, W, M = 4, 5, 8
+    g = random_unary(H, W, M, 3).astype(np.float64)
+    pot = gb.truncated_linear(M, 2, 0.9)
     s0 = gb.run(g, pot, mode, 2, storage=F32)
-    want = gb.sync_step(g, s0, pot, mode).astype(F32).astype(np.float64)
-    np.testing.assert_array_equal(gb.sync_step(g, s0, pot, mode, storage=F32), want)
+    s1 = gb.sync_step(g, s0, pot, mode, storage=F32)
+    rounded = 0
+    for r in range(H):
+        for c in range(W):
+            for o in gb.DIRS:
+                dr, dc = gb.OFFSETS[o]
+                if not (0 <= r + dr < H and 0 <= c + dc < W):
+                    continue
+                exact = gb.single_update(g, s0, pot, mode, r, c, o)
+                got = s1[gb.OPPOSITE[o], r + dr, c + dc]
+                assert np.all(got.astype(F32).astype(np.float64) == got)
+                half_ulp = np.spacing(np.abs(exact).astype(F32)).astype(np.float64) / 2
+                assert np.all(np.abs(got - exact) <= half_ulp)
+                rounded += int(np.sum(got != exact))
+    assert rounded > 0   # the model did round
 
 
 def test_chain_sweep_close_to_exact():
