@@ -79,7 +79,10 @@ enum bp_schedule {
 #define BP_MAX_LABELS 256     /* largest M this library accepts */
 #define BP_FBAR_TIED (-1.0f)  /* bp_set_potential: fbar := f(T) = exp(-alpha T) */
 
-/* Create a handle for an H x W grid (H, W >= 1, H*W < 2^31 / 4).
+/* Create a handle for an H x W grid (H, W >= 1, H*W < 2^31 / 4): the pairwise
+ * MRF of Eq. 1 on the 4-connected pixel lattice of the stereo model (Sec. 6),
+ * one node per pixel and one pairwise factor per pair of horizontal or
+ * vertical neighbours.
  * hip_stream: a hipStream_t, or NULL for the default stream.  The GPU that is
  * current on the calling thread becomes the handle's device.
  * Errors: BP_EINVAL (sizes, null out), BP_EHIP (no usable device). */
@@ -102,8 +105,10 @@ int bp_set_stream(bp_grid* grid, void* hip_stream);
  * the messages. */
 int bp_set_potential(bp_grid* grid, int32_t M, int32_t T, float alpha, float fbar);
 
-/* Bytes of device workspace needed after bp_set_potential (two message
- * buffers for the synchronous ping-pong, plus the tables of the Eq. 10
+/* Bytes of device workspace needed after bp_set_potential: the message
+ * state of BP on the Eq. 1 grid (one M-label message per directed edge,
+ * Sec. 3, stored as four inbox planes) in two buffers for the synchronous
+ * ping-pong, plus the tables of the Eq. 10
  * max-product update sized for any T < M), or a negative status. */
 int64_t bp_workspace_bytes(const bp_grid* grid);
 
@@ -112,7 +117,9 @@ int64_t bp_workspace_bytes(const bp_grid* grid);
  * set_potential, BP_ENOMEM if too small, BP_EINVAL on misalignment. */
 int bp_attach_workspace(bp_grid* grid, void* dev_ptr, int64_t bytes);
 
-/* Borrow the unary table g (device, [H][W][M], 16-byte aligned) until the
+/* Borrow the unary table g (the per-node factor of Eq. 1; in the stereo
+ * model of Sec. 6 the data term of each disparity) (device, [H][W][M],
+ * 16-byte aligned) until the
  * next bp_set_unary, a change of M, or bp_destroy.  Every entry must be
  * finite and >= 0, with a positive entry in every row (otherwise the
  * pixel's messages are 0/0 under Eq. 5 and the normalisation).  With the
@@ -121,7 +128,9 @@ int bp_attach_workspace(bp_grid* grid, void* dev_ptr, int64_t bytes);
  * the previous one), and BP_ESTATE if no workspace is attached yet. */
 int bp_set_unary(bp_grid* grid, const float* g_dev);
 
-/* All messages := 1/M (the usual uniform start). */
+/* All messages := 1/M: the uniform start of the iteration of Eq. 2 / Eq. 9
+ * (Sec. 3 leaves the start open; uniform is the usual choice).  Returns
+ * BP_ESTATE before a workspace is attached. */
 int bp_reset_messages(bp_grid* grid);
 
 /* Run n_iters >= 0 iterations of the O(mM) update (Eq. 7 for sum-product,
@@ -278,8 +287,9 @@ int bp_fg_destroy(bp_fgraph* fg);
  * max-marginals. */
 int bp_beliefs(bp_grid* grid, float* out_dev);
 
-/* MAP labels: argmax over labels of the float32 beliefs bp_beliefs would
- * return, lowest label on ties, into out_dev (device, [H][W] int32). */
+/* MAP labels, the disparity map of Sec. 6: argmax over labels of the
+ * float32 beliefs bp_beliefs would return (Eq. 3), lowest label on ties,
+ * into out_dev (device, [H][W] int32). */
 int bp_map_labels(bp_grid* grid, int32_t* out_dev);
 
 /* Beliefs and MAP labels in one pass over the messages (Eq. 3 and its
@@ -306,7 +316,10 @@ int bp_set_messages(bp_grid* grid, const float* src_dev);
  * that changes the state in between (iterate, reset, set_*, attach) makes
  * bp_backward return BP_ESTATE.
  * Supported: T <= 16 (T <= 12 when M <= 16), the compiled register-window
- * variants; otherwise BP_EUNSUPPORTED.
+ * variants, and fbar > 0; otherwise BP_EUNSUPPORTED.  The reverse pass works
+ * with adjoints of log messages and divides by each unnormalised message
+ * u(y); fbar > 0 keeps u(y) >= fbar * sum(h) > 0, while fbar = 0 (Eq. 8)
+ * lets u(y) vanish where h is zero across the window.
  * ---------------------------------------------------------------------- */
 
 /* Device bytes bp_forward_ckpt / bp_backward need for n_iters >= 0

@@ -45,6 +45,11 @@ int grad_checks(const bp_grid* G, int n, int k) {
     if (n < 0) return fail(BP_EINVAL, "n_iters < 0");
     if (k < 1) return fail(BP_EINVAL, "ckpt_every must be >= 1");
     if (G->general) return fail(BP_EUNSUPPORTED, "the adjoint takes the truncated-linear potential only");
+    // The reverse pass works with log-message adjoints and divides by u(y);
+    // fbar > 0 keeps every u(y) >= fbar * sum(h) > 0.  With fbar = 0, u(y) is
+    // 0 wherever h vanishes across the window, and the log adjoint carries
+    // no information there.
+    if (!(G->fbar_d > 0.0)) return fail(BP_EUNSUPPORTED, "the adjoint needs fbar > 0 (messages stay positive)");
     if (!bpk::adjoint_supported(G->M, G->T))
         return fail(BP_EUNSUPPORTED, "adjoint supports T <= 16 (12 for M <= 16) (M=%d, T=%d)", G->M, G->T);
     return BP_OK;

@@ -116,6 +116,70 @@ def test_autograd_function():
     grid.close()
 
 
+def test_autograd_two_forwards_then_two_backwards():
+    """Two forwards on one grid with different theta (and alpha), then both
+    backwards, the first forward's last: each gradient is its own forward's,
+    against the FP64 reference (the handle keeps only the latest forward's
+    checkpoints, so the first backward has to replay its forward)."""
+    import torch
+    from paper_1010_0012_amd.autograd import bp_beliefs
+    from paper_1010_0012_amd.grid import Grid
+    H, W, M, T, n = 9, 11, 16, 2, 5
+    grid = Grid(H, W)
+    runs = []
+    for seed, a in ((21, 0.8), (22, 1.1)):
+        g32, y, _, _ = make_stereo(H, W, M, 0.05, 4.0, "rectangles", seed)
+        theta = torch.log(torch.from_numpy(g32).cuda()).requires_grad_(True)
+        alpha = torch.tensor(a, device="cuda", requires_grad=True)
+        b = bp_beliefs(theta, alpha, grid, T, n, ckpt_every=2)
+        yt = torch.from_numpy(y).cuda().long()
+        loss = -torch.log(torch.gather(b, -1, yt[..., None])).mean()
+        runs.append((g32, y, a, theta, alpha, loss))
+    for g32, y, a, theta, alpha, loss in reversed(runs):
+        loss.backward()
+    for k, (g32, y, a, theta, alpha, loss) in enumerate(runs):
+        ref = grad_ref.grad(g32.astype(np.float64), y, M, T, float(np.float32(a)), n)
+        check(f"autograd forward {k}", (float(loss.detach()), theta.grad.cpu().numpy(), float(alpha.grad), None), ref)
+    # a state change between forward and backward (not by a forward) also replays
+    g32, y, _, _ = make_stereo(H, W, M, 0.05, 4.0, "rectangles", 23)
+    theta = torch.log(torch.from_numpy(g32).cuda()).requires_grad_(True)
+    alpha = torch.tensor(0.9, device="cuda", requires_grad=True)
+    b = bp_beliefs(theta, alpha, grid, T, n, ckpt_every=2)
+    yt = torch.from_numpy(y).cuda().long()
+    loss = -torch.log(torch.gather(b, -1, yt[..., None])).mean()
+    grid.iterate("sum", 3)
+    loss.backward()
+    ref = grad_ref.grad(g32.astype(np.float64), y, M, T, float(np.float32(0.9)), n)
+    check("autograd after iterate", (float(loss.detach()), theta.grad.cpu().numpy(), float(alpha.grad), None), ref)
+    torch.cuda.synchronize()
+    grid.close()
+
+
+def test_adjoint_refuses_fbar_zero():
+    """fbar = 0 lets an unnormalised message vanish (h zero across the
+    window, e.g. a unary with zero entries), where the log-message adjoint
+    is undefined: the gradient calls refuse it instead of returning NaN."""
+    import torch
+    from paper_1010_0012_amd import _lib as L
+    from paper_1010_0012_amd.grid import Grid
+    g32 = random_unary(4, 5, 8, 1)
+    g32[:, :, 3:] = 0.0
+    grid = Grid(4, 5)
+    grid.set_potential(8, 1, 1.0, 0.0)
+    grid.set_unary(torch.from_numpy(g32).cuda())
+    nbytes = L.bp_grad_workspace_bytes(grid.handle, 3, 2)
+    gws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.BPError) as e:
+        L.bp_forward_ckpt(grid.handle, 3, 2, gws, nbytes)
+    assert e.value.status == L.BP_EUNSUPPORTED
+    buf = torch.zeros(4, 5, 8, device="cuda")
+    with pytest.raises(L.BPError) as e:
+        L.bp_backward(grid.handle, buf, buf.clone(), torch.zeros(1, device="cuda"))
+    assert e.value.status == L.BP_ESTATE
+    torch.cuda.synchronize()
+    grid.close()
+
+
 def test_backward_state_errors():
     import torch
     from paper_1010_0012_amd import _lib as L
