@@ -81,6 +81,35 @@ def measured_traffic():
     return rec["traffic_bytes"] if rec.get("source_sha256") == h.hexdigest() else None
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_accuracy(case, b, lab):
+    """Error of a whole solve against the FP64 oracle's solve of the same
+    workload, stored by tests/golden/make_e2e_ref.py (run on the CPU, oracle
+    only): max |b - b_FP64| over the 4096 sampled pixels, MAP mismatches where
+    the FP64 top-two margin exceeds 1e-6 (every pixel), and, where the file
+    has it, the same for the oracle's float32-storage model alone."""
+    import numpy as np
+    try:
+        z = np.load(os.path.join(GOLDEN, f"e2e_{case}.npz"))
+    except OSError:
+        return {}
+    meta = json.loads(str(z["meta"]))
+    H, W, M = meta["H"], meta["W"], meta["M"]
+    bs = np.asarray(b).reshape(H * W, M)[z["sample_idx"]]
+    lab = np.asarray(lab).reshape(-1)
+    margin = dict(zip(z["low_idx"].tolist(), z["low_margin"].tolist()))
+    diff = np.nonzero(lab != z["labels"].reshape(-1).astype(lab.dtype))[0]
+    bad = sum(1 for i in diff if margin.get(int(i), math.inf) > 1e-6)
+    out = {"case": case, "max_abs_db_vs_fp64": float(np.max(np.abs(bs - z["sample_b"]))),
+           "map_mismatches_vs_fp64": int(bad), "pixels": H * W, "sampled_pixels": int(len(z["sample_idx"]))}
+    if "store_max_db" in meta:
+        out["f32_storage_model_max_abs_db_vs_fp64"] = meta["store_max_db"]
+        out["max_abs_db_vs_f32_storage_model"] = float(np.max(np.abs(bs - z["store_sample_b"])))
+    return out
+
+
 def time_launches(grid, mode, n, schedule, dense, reps, iters_per_launch=1):
     """Average duration of one update launch (covering iters_per_launch
     iterations), from HIP events on the stream the library launches on
@@ -162,10 +191,24 @@ def grad_leg(reps=3):
     dt = (time.perf_counter() - t0) / reps
     grid.close()
     log(f"bench: fwd+bwd {cfg.name}: {dt * 1e3:.2f} ms per {cfg.iters}-iteration forward+backward")
-    return {"fwd_bwd_workload": f"{cfg.name}: {cfg.H}x{cfg.W}, M={cfg.M}, T={cfg.T}, "
-                                f"{cfg.iters} iterations, checkpoints every {cfg.ckpt_every}",
-            "fwd_bwd_ms": dt * 1e3, "fwd_bwd_it_per_s": cfg.iters / dt,
-            "fwd_bwd_solves_per_s": 1.0 / dt}
+    out = {"fwd_bwd_workload": f"{cfg.name}: {cfg.H}x{cfg.W}, M={cfg.M}, T={cfg.T}, "
+                               f"{cfg.iters} iterations, checkpoints every {cfg.ckpt_every}",
+           "fwd_bwd_ms": dt * 1e3, "fwd_bwd_it_per_s": cfg.iters / dt,
+           "fwd_bwd_solves_per_s": 1.0 / dt}
+    # accuracy against the FP64 reference gradient (tests/golden, oracle only)
+    import numpy as np
+    try:
+        z = np.load(os.path.join(GOLDEN, "grad_stereo256grad.npz"))
+        meta = json.loads(str(z["meta"]))
+        th = dtheta.cpu().numpy().reshape(-1, cfg.M)[z["sample_idx"]]
+        out["fwd_bwd_accuracy"] = {
+            "dtheta_max_abs_err_over_max_abs": float(np.max(np.abs(th - z["sample_dtheta"])) / meta["max_abs_dtheta"]),
+            "dalpha_rel_err": abs(float(dalpha.cpu()[0]) - meta["dalpha"]) / abs(meta["dalpha"]),
+            "sampled_pixels": int(len(z["sample_idx"])), "reference": "FP64 hand adjoint (oracle), 4096 sampled pixels"}
+        log(f"bench: fwd+bwd accuracy {out['fwd_bwd_accuracy']}")
+    except OSError:
+        pass
+    return out
 
 
 def sweep_leg(grid, cfg, reps=2):
@@ -400,6 +443,14 @@ def batch_leg(n_iters=30, reps=3):
         e1.record(s)
         e1.synchronize()
         ms = min(ms, e0.elapsed_time(e1))
+    acc = {}
+    j = min(range(len(insts)), key=lambda i: insts[i].H * insts[i].W * insts[i].M)
+    b_j, l_j = batch.beliefs()[j].cpu().numpy(), batch.map_labels()[j].cpu().numpy()
+    acc[f"batch32_{j}_sum_sync"] = golden_accuracy(f"batch32_{j}_sum_sync", b_j, l_j)
+    j = max((i for i in range(len(insts)) if insts[i].M == 128), key=lambda i: insts[i].H * insts[i].W)
+    b_j, l_j = batch.beliefs()[j].cpu().numpy(), batch.map_labels()[j].cpu().numpy()
+    acc[f"batch32_{j}_sum_sync"] = golden_accuracy(f"batch32_{j}_sum_sync", b_j, l_j)
+    log(f"bench: batch accuracy {acc}")
     batch.close()
     # one grid at a time
     t_single = 0.0
@@ -422,7 +473,7 @@ def batch_leg(n_iters=30, reps=3):
             "batch_ms": ms, "batch_updates_per_s": updates / (ms * 1e-3),
             "batch_alg_GBs": alg_bytes / (ms * 1e-3) / 1e9,
             "batch_plan": {"passes": plan[0], "grid_blocks": plan[1], "streams": streams, "autotune_best_us": best_us},
-            "batch_one_grid_at_a_time_ms": t_single}
+            "batch_one_grid_at_a_time_ms": t_single, "batch_accuracy": acc}
 
 
 def main():
@@ -475,6 +526,8 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = updates_per_iter * cfg.iters * args.steps / dt
     log(f"bench: sum sync {ms_per_step:.3f} ms/step, {value:.4e} updates/s")
+    accuracy = golden_accuracy(f"{cfg.name}_sum_sync", beliefs.cpu().numpy(), labels.cpu().numpy())
+    log(f"bench: accuracy of the last step vs the FP64 oracle's solve: {accuracy}")
 
     # Dominant kernel: the sparse sum-product launch that runs two synchronous
     # iterations; per launch it reads the unary and the inbox once and writes
@@ -483,15 +536,21 @@ def main():
     ms_launch = time_launches(grid, "sum", cfg.iters, "sync", False, reps, iters_per_launch=2)
     bytes_launch = alg_bytes_per_sync_iter(cfg)
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
+    per_iter_equiv = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                 "kernel": sparse_kernel_name(cfg.M, cfg.T, 0, pair=True),
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3,
-                "iterations_per_launch": 2}
+                "iterations_per_launch": 2,
+                # one iteration's algorithmic bytes (the per-iteration model:
+                # every message read and written once, the unary read once)
+                # over the launch time per iteration; above 1 because the
+                # first iteration's messages never reach HBM
+                "frac_per_iteration_equiv": per_iter_equiv / HBM_PEAK_GBS}
     log(f"bench: sparse sum pair launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
-    extra = {"sparse_sum_sync_pair_launch_us": ms_launch * 1e3}
+    extra = {"sparse_sum_sync_pair_launch_us": ms_launch * 1e3, "accuracy": accuracy}
     # one iteration per launch, for comparison
     grid.set_sync_fusion(False)
     ms_single = time_launches(grid, "sum", cfg.iters, "sync", False, reps)
@@ -520,6 +579,10 @@ def main():
             per_iter = step * (1 if sched == "sync" else 2)          # every message updated once
             unit = "iteration" if sched == "sync" else "pass"
             key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
+            # the state is that of a whole solve from the uniform start
+            grid.readout(beliefs, labels)
+            extra[key + "_accuracy"] = golden_accuracy(f"{cfg.name}_{mode}_{sched}", beliefs.cpu().numpy(),
+                                                       labels.cpu().numpy())
             extra[key + "_updates_per_s"] = updates_per_iter / (per_iter * 1e-3)
             extra[key + "_launch_us"] = ms * 1e3
             extra[key + f"_us_per_{unit}"] = step * 1e3

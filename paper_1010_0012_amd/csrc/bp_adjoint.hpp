@@ -68,19 +68,11 @@ __global__ __launch_bounds__(kBlock) void adjoint_seed_kernel(SeedArgs a) {
     PixelInputs in;
     load_pixel_at(a.g, a.m, a.N, a.M, px, x0, full, in);
     float b[kLpl], gb[kLpl];
-    make_belief(in, b);  // same product order and normalisation as the readout
-    float z = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i) z += b[i];
-    z = group_sum<G>(z);
-    const float inv = 1.0f / z;
+    belief_d<G>(in, a.M, x0, full, b);  // the beliefs the readout returns, bit for bit
     load_labels<false>(a.dL_db + (size_t)px.p * a.M, x0, a.M, full, gb, 0.0f);
     float dot = 0.0f;
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) {
-        b[i] *= inv;
-        dot = fmaf(b[i], gb[i], dot);
-    }
+    for (int i = 0; i < kLpl; ++i) dot = fmaf(b[i], gb[i], dot);
     dot = group_sum<G>(dot);
     float abar[kLpl];
 #pragma unroll

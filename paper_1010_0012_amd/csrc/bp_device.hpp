@@ -513,13 +513,6 @@ __device__ __forceinline__ void make_h_d(const PixelInputs& in, double (&h)[4][k
     }
 }
 
-// Eq. 3 before normalisation, in the order every readout uses.
-__device__ __forceinline__ void make_belief(const PixelInputs& in, float (&b)[kLpl]) {
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i)
-        b[i] = (((in.g[i] * in.m[kLeft][i]) * in.m[kRight][i]) * in.m[kUp][i]) * in.m[kDown][i];
-}
-
 // Store a finished message into the receiver's inbox slot.
 __device__ __forceinline__ void store_message(float* out, size_t plane, int M, int W, const Pixel& px,
                                               int dir, int x0, bool full, const float (&m)[kLpl]) {
@@ -552,6 +545,21 @@ __device__ __forceinline__ void normalise_d(double (&u)[kLpl], int M, int x0, bo
     const double inv = recip_d(z);
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) m[i] = (float)(u[i] * inv);
+}
+
+// Eq. 3 for this lane's labels: the product of the unary and the four
+// incoming messages formed in double (five float32 factors: no underflow,
+// whose smallest product is about 1e-224, and at most three roundings), then
+// normalised in double and rounded once to float32, as every message is.
+// Only a row whose product is exactly zero for every label (a unary row with
+// no positive entry, which bp_set_unary's contract excludes) gives 0/0.
+template <int G>
+__device__ __forceinline__ void belief_d(const PixelInputs& in, int M, int x0, bool full, float (&b)[kLpl]) {
+    double p[kLpl];
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i)
+        p[i] = ((((double)in.g[i] * in.m[kLeft][i]) * in.m[kRight][i]) * in.m[kUp][i]) * in.m[kDown][i];
+    normalise_d<G>(p, M, x0, full, b);
 }
 
 }  // namespace bpk

@@ -356,21 +356,70 @@ __device__ __forceinline__ void message_d(const double (&h)[kLpl], const double*
 // branch.  Loads are unconditional: a missing neighbour (or a missing row of
 // a neighbour's inbox) reads a valid row and is replaced by the factor 1,
 // which keeps every load of the pixel in one basic block.
+// The arithmetic of both iterations for one receiver p: rows[k] are the
+// unary and the three inbox rows of the neighbour in direction k that its
+// message to p uses ({g, the two partial-product rows, the far-side row}),
+// gp is p's unary, has[k] whether that neighbour exists.  put_mid(k, m)
+// takes each first-iteration message into p (the factor 1 where there is no
+// neighbour), put_out(o, u) each second-iteration message p sends.
+template <int G, int TW, int MODE, bool FULL, class PutMid, class PutOut>
+__device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], const float (&gp)[kLpl],
+                                             const bool (&has)[4], int pos, int M, const double* dtab,
+                                             double fbar_d, const float* tab, float fbar, PutMid put_mid,
+                                             PutOut put_out) {
+    const int x0 = pos * kLpl;
+    PixelInputs mid;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double h[kLpl];
+        sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
+        message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) mid.m[k][i] = has[k] ? mid.m[k][i] : 1.0f;
+        put_mid(k, mid.m[k]);
+    }
+    // Second iteration, sender side, from the messages just computed.
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
+    double h[4][kLpl];
+    make_h_d(mid, h);
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        float u[kLpl];
+        message_d<G, TW, MODE>(h[o], dtab, fbar_d, tab, fbar, pos, M, x0, FULL, u);
+        put_out(o, u);
+    }
+}
+
+// Inbox rows of the neighbour q in direction k that q's message to p uses:
+// q sees p in direction opposite(k) and leaves out its own row from p; the
+// partial product pairs the two rows across that axis.
+__device__ __forceinline__ void pair_sources(int k, int (&src)[3]) {
+    const int o = opposite(k);  // direction of p seen from q
+    const int ka = (o == kLeft || o == kRight) ? kUp : kLeft;
+    src[0] = ka;
+    src[1] = ka + 1;
+    src[2] = opposite(o);
+}
+
+// Both iterations for one pixel px of an H x W grid (in -> out); with
+// mid_out, the first iteration's messages into px are stored there too
+// (px's own inbox slots, coalesced).  FULL:
+// M == 4G, known at compile time so that no load or normalisation carries a
+// branch.  Loads are unconditional: a missing neighbour (or a missing row of
+// a neighbour's inbox) reads a valid row and is replaced by the factor 1,
+// which keeps every load of the pixel in one basic block.
 template <int G, int TW, int MODE, bool FULL>
 __device__ __forceinline__ void pair_pixel(const float* g, const float* in, float* out, float* mid_out, int H, int W,
                                            int M, const Pixel& px, int pos, const double* dtab, double fbar_d,
                                            const float* tab, float fbar) {
     const int x0 = pos * kLpl;
     const size_t plane = (size_t)H * W * M;
-    // First iteration, receiver side: the message from the neighbour in
-    // direction k (inbox slot k of p).  The sender q sees p in direction
-    // opposite(k) and leaves out its own inbox row from p.
     float rows[4][4][kLpl];  // [k][g, the two partial-product rows, the opposite row]
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int o = opposite(k);  // direction of p seen from q
-        const int ka = (o == kLeft || o == kRight) ? kUp : kLeft;
-        const int src[3] = {ka, ka + 1, opposite(o)};
+        int src[3];
+        pair_sources(k, src);
         const int qr = px.has[k] ? px.r + (k == kUp ? -1 : k == kDown ? 1 : 0) : px.r;
         const int qc = px.has[k] ? px.c + (k == kLeft ? -1 : k == kRight ? 1 : 0) : px.c;
         const bool qhas[4] = {qc > 0, qc + 1 < W, qr > 0, qr + 1 < H};
@@ -384,27 +433,81 @@ __device__ __forceinline__ void pair_pixel(const float* g, const float* in, floa
     }
     float gp[kLpl];
     load_labels<false>(g + (size_t)px.p * M, x0, M, FULL, gp, 0.0f);
-    PixelInputs mid;
+    pair_compute<G, TW, MODE, FULL>(
+        rows, gp, px.has, pos, M, dtab, fbar_d, tab, fbar,
+        [&](int k, const float (&m)[kLpl]) {
+            if (mid_out && px.has[k]) store_labels<kMsgNT>(mid_out + k * plane + (size_t)px.p * M, x0, M, FULL, m);
+        },
+        [&](int o, const float (&u)[kLpl]) { store_message(out, plane, M, W, px, o, x0, FULL, u); });
+}
+
+// Global-memory byte pointers.  A float4 at a 32-bit byte offset from a
+// uniform base: the access takes its base from scalar registers and its
+// offset from one VGPR, with no 64-bit address arithmetic per row.
+typedef const char __attribute__((address_space(1)))* gcptr;
+typedef char __attribute__((address_space(1)))* gptr;
+
+// A uniform pointer, held in scalar registers as such: without this the
+// compiler may fold a uniform plane offset into the per-lane address and
+// form 64-bit addresses in VGPRs again.
+template <typename P>
+__device__ __forceinline__ P uniform_ptr(P p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ v4f ld_off(gcptr base, uint32_t off) {
+    return *(const v4f __attribute__((address_space(1)))*)(base + off);
+}
+__device__ __forceinline__ void st_off_nt(gptr base, uint32_t off, const float (&v)[kLpl]) {
+    __builtin_nontemporal_store(v4f{v[0], v[1], v[2], v[3]}, (v4f __attribute__((address_space(1)))*)(base + off));
+}
+__device__ __forceinline__ void unpack(v4f t, float (&v)[kLpl]) {
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+}
+
+// pair_pixel for M = 4G and a pixel at least two rows and two columns away
+// from every grid border: every one of the seventeen rows exists and all
+// four outgoing messages are stored, so no row is replaced and no store is
+// conditional.  voff is the byte offset of p's label row plus this lane's
+// 16 bytes; plane_b (bytes of one inbox plane) and row_b (bytes of one grid
+// row of label rows) are below 2^32, so every offset is 32-bit.  The same
+// pair_compute as pair_pixel: the same bits.
+template <int G, int TW, int MODE>
+__device__ __forceinline__ void pair_pixel_inner(gcptr gb, gcptr ib, gptr ob, gptr mb, uint32_t plane_b,
+                                                 uint32_t row_b, uint32_t voff, int pos, const double* dtab,
+                                                 double fbar_d, const float* tab, float fbar) {
+    constexpr uint32_t lab_b = 16u * G;  // bytes of one label row
+    const uint32_t q_off[4] = {voff - lab_b, voff + lab_b, voff - row_b, voff + row_b};
+    gcptr ib_plane[4];
+    gptr ob_plane[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double h[kLpl];
-        sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
-        message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
-#pragma unroll
-        for (int i = 0; i < kLpl; ++i) mid.m[k][i] = px.has[k] ? mid.m[k][i] : 1.0f;
-        if (mid_out && px.has[k]) store_labels<kMsgNT>(mid_out + k * plane + (size_t)px.p * M, x0, M, FULL, mid.m[k]);
+        ib_plane[k] = uniform_ptr(ib + (size_t)k * plane_b);
+        ob_plane[k] = uniform_ptr(ob + (size_t)k * plane_b);
     }
-    // Second iteration, sender side, from the messages just computed.
+    float rows[4][4][kLpl];
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
-    double h[4][kLpl];
-    make_h_d(mid, h);
+    for (int k = 0; k < 4; ++k) {
+        int src[3];
+        pair_sources(k, src);
+        unpack(ld_off(gb, q_off[k]), rows[k][0]);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        float u[kLpl];
-        message_d<G, TW, MODE>(h[o], dtab, fbar_d, tab, fbar, pos, M, x0, FULL, u);
-        store_message(out, plane, M, W, px, o, x0, FULL, u);
+        for (int j = 0; j < 3; ++j) unpack(ld_off(ib_plane[src[j]], q_off[k]), rows[k][j + 1]);
     }
+    float gp[kLpl];
+    unpack(ld_off(gb, voff), gp);
+    const bool all[4] = {true, true, true, true};
+    pair_compute<G, TW, MODE, true>(
+        rows, gp, all, pos, 4 * G, dtab, fbar_d, tab, fbar,
+        [&](int k, const float (&m)[kLpl]) {
+            if (mb) st_off_nt(uniform_ptr(mb + (size_t)k * plane_b), voff, m);
+        },
+        [&](int o, const float (&u)[kLpl]) { st_off_nt(ob_plane[opposite(o)], q_off[o], u); });
 }
 
 // Synchronous (a.colour < 0): every pixel, two iterations a.in -> a.out,
@@ -423,6 +526,44 @@ __global__ __launch_bounds__(kBlock) void sparse_update2_kernel(UpdateArgs a, in
     const Pixel px = map_slot(slot, a);
     if (!px.ok) return;  // whole groups only
     pair_pixel<G, TW, MODE, FULL>(a.g, a.in, a.out, a.mid, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
+}
+
+// The same launch for M = 4G when an inbox plane is below 2^32 bytes, with
+// workgroups that each cover kBlock/G consecutive pixels (or colour slots) of
+// one grid row: the row and column come from the workgroup index in scalar
+// registers (no per-lane division), and a wave whose pixels all lie two or
+// more pixels inside the grid runs pair_pixel_inner.  gx = workgroups per
+// row; the XCD band remap is that of sparse_update2_kernel.
+template <int G, int TW, int MODE>
+__global__ __launch_bounds__(kBlock) void sparse_update2_rows_kernel(UpdateArgs a, int per, int gx) {
+    constexpr int PPB = kBlock / G;
+    const int b = xcd_band_block(blockIdx.x, per);
+    const int r = b / gx;
+    const int j = (b - r * gx) * PPB + (int)(threadIdx.x / G);
+    const int pos = threadIdx.x & (G - 1);
+    const int c = a.colour < 0 ? j : 2 * j + ((a.colour + r) & 1);
+    if (r >= a.H || c >= a.W) return;  // whole groups only
+    const int p = r * a.W + c;
+    const bool inner = r >= 2 && r + 2 < a.H && c >= 2 && c + 2 < a.W;
+    if (__builtin_amdgcn_ballot_w64(!inner) == 0) {
+        const uint32_t plane_b = (uint32_t)a.N * (16u * G);
+        const uint32_t row_b = (uint32_t)a.W * (16u * G);
+        const uint32_t voff = (uint32_t)p * (16u * G) + (uint32_t)pos * 16u;
+        pair_pixel_inner<G, TW, MODE>((gcptr)a.g, (gcptr)a.in, (gptr)a.out, (gptr)a.mid, plane_b, row_b, voff, pos,
+                                      a.dtab, a.fbar_d, a.tab, a.fbar);
+    } else {
+        Pixel px;
+        px.r = r;
+        px.c = c;
+        px.p = p;
+        px.ok = true;
+        px.has[kLeft] = c > 0;
+        px.has[kRight] = c + 1 < a.W;
+        px.has[kUp] = r > 0;
+        px.has[kDown] = r + 1 < a.H;
+        pair_pixel<G, TW, MODE, true>(a.g, a.in, a.out, a.mid, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab,
+                                      a.fbar);
+    }
 }
 
 // ------------------------------------- sparse update, runtime window ----
@@ -593,25 +734,18 @@ __global__ __launch_bounds__(dense_block(G)) void dense_update_kernel(UpdateArgs
 }
 
 // ------------------------------------------------------------ readout ----
-// Eq. 3: b = g * product of all incoming messages, normalised; MAP label =
-// argmax of the normalised float32 beliefs, lowest label on ties.
+// Eq. 3: b = g * product of all incoming messages, normalised (belief_d);
+// MAP label = argmax of the normalised float32 beliefs, lowest label on ties.
 template <int G>
 __device__ __forceinline__ void readout_pixel(const PixelInputs& in, int M, int x0, bool full,
                                               float* beliefs_row, int* label) {
     float b[kLpl];
-    make_belief(in, b);
-    float z = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kLpl; ++i) z += b[i];
-    z = group_sum<G>(z);
-    const float inv = 1.0f / z;
+    belief_d<G>(in, M, x0, full, b);
     float best = -1.0f;
     int arg = 0x7fffffff;
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) {
-        b[i] *= inv;
+    for (int i = 0; i < kLpl; ++i)
         if (x0 + i < M && b[i] > best) { best = b[i]; arg = x0 + i; }
-    }
     if (beliefs_row) store_labels<false>(beliefs_row, x0, M, full, b);
     if (label) {
         group_argmax<G>(best, arg);

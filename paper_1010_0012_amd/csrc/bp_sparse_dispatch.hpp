@@ -64,6 +64,16 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
 // selects the branch-free full-row instance.
 template <int G, int TW, int MODE>
 hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
+    if (a.M == G * kLpl && (uint64_t)a.N * a.M * sizeof(float) < (uint64_t(1) << 32)) {
+        // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
+        const int slots = a.colour < 0 ? a.W : a.half_w;
+        const int gx = (slots + kBlock / G - 1) / (kBlock / G);
+        const int64_t total = (int64_t)gx * a.H;
+        const int per = (int)((total + kXcds - 1) / kXcds);
+        hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)(per * kXcds)), dim3(kBlock), 0,
+                           s, a, per, gx);
+        return hipGetLastError();
+    }
     const int nblk = (int)groups_blocks<G>(a.n_slots);
     const int per = (nblk + kXcds - 1) / kXcds;
     if (a.M == G * kLpl)

@@ -140,6 +140,33 @@ def test_pairs_equal_single_launches(shape, mode, schedule):
             np.testing.assert_array_equal(x, y)
 
 
+# Grids with waves whose pixels all lie two or more pixels inside the grid
+# (the row-block pair launch's path without border handling) next to border
+# waves, for every lane count with M = 4G, odd widths and a ragged last
+# workgroup of each row.
+INNER_SHAPES = [(23, 41, 64, 4, 0.5, None), (19, 150, 16, 2, 1.0, None), (17, 75, 32, 3, 0.7, None),
+                (9, 133, 8, 1, 0.9, None), (13, 29, 128, 8, 0.3, None), (11, 21, 256, 6, 0.2, None),
+                (21, 37, 64, 3, 0.4, 0.0)]
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+@pytest.mark.parametrize("shape", INNER_SHAPES, ids=_id)
+def test_pair_launch_inner_waves(shape, mode, schedule):
+    """The pair launch on grids with interior waves: equal to single
+    launches bit for bit, and to the oracle by the parity rule."""
+    H, W, M, T, alpha, fbar = shape
+    g32 = random_unary(H, W, M, 500 + INNER_SHAPES.index(shape))
+    n = 6
+    tag = f"pair inner {mode} {schedule} {_id(shape)}"
+    say(tag)
+    a = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, fuse=True)
+    b = run_gpu(g32, M, T, alpha, fbar, mode, schedule, n, fuse=False)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    check(tag, a, g32, M, T, alpha, fbar, mode, schedule, n, gb.SPARSE)
+
+
 def test_deterministic():
     g32 = random_unary(31, 29, 64, 9)
     a = run_gpu(g32, 64, 4, 0.5, None, "sum", "sync", 7)
@@ -183,6 +210,40 @@ def test_readout_equals_separate_calls(shape, mode):
     for x in (l1, l2):
         assert torch.equal(x, l0)
     grid.close()
+
+
+def tiny_product_unary():
+    """3 x 3, M = 16: the centre's unary is 1e-30 on every label and its four
+    neighbours peak at labels 0, 5, 10 and 15 (1e-30 elsewhere).  With
+    fbar = 0 each message into the centre is about 1e-30 away from its
+    sender's peak, so every label's Eq. 3 product there is about 1e-120: it
+    underflows to zero in float32 arithmetic, while the stored float32
+    messages (all above 1e-38) still carry the beliefs."""
+    M = 16
+    g = np.ones((3, 3, M), np.float32)
+    g[1, 1, :] = np.float32(1e-30)
+    for (r, c), peak in (((1, 0), 0), ((1, 2), 5), ((0, 1), 10), ((2, 1), 15)):
+        g[r, c, :] = np.float32(1e-30)
+        g[r, c, peak] = 1.0
+    return g
+
+
+@pytest.mark.parametrize("schedule,n", [("sync", 3), ("checkerboard", 4)])
+@pytest.mark.parametrize("mode", ["sum", "max"])
+def test_readout_tiny_products_fbar_zero(mode, schedule, n):
+    """Eq. 3 is formed in double: beliefs whose float32 product would
+    underflow on every label (0/0) match the oracle."""
+    g32 = tiny_product_unary()
+    tag = f"tiny Eq. 3 products fbar=0 {mode} {schedule}"
+    say(tag)
+    gpu = run_gpu(g32, 16, 2, 1.0, 0.0, mode, schedule, n)
+    m = gpu[0]
+    prod = g32[1, 1].copy()
+    for k in gb.DIRS:
+        prod = prod * m[k, 1, 1]
+    assert np.all(prod == 0.0)                 # float32 arithmetic would give 0/0 here
+    assert np.all(np.isfinite(gpu[1])) and abs(float(gpu[1][1, 1].sum()) - 1.0) <= 1e-6
+    check(tag, gpu, g32, 16, 2, 1.0, 0.0, mode, schedule, n)
 
 
 @pytest.mark.parametrize("schedule,n", [("sync", 1), ("sync", 3), ("checkerboard", 2)])
