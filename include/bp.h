@@ -425,6 +425,40 @@ int bp_batch_map_labels(bp_batch* batch, int32_t* out_dev);
 /* Free the handle and its captured graphs and private streams. */
 int bp_batch_destroy(bp_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): one whole solve,
+ * messages held in a fixed device array inside the library instead of a
+ * caller-attached workspace, and no handle.
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of the library's fixed device workspace for bp_solve_noalloc: two
+ * message buffers (4*H*W*M floats each, 256-byte aligned) plus the window
+ * tables and flag slot of bp_workspace_bytes must fit, i.e. about
+ * H*W*M <= 2^21 (for example 256 x 256 x 32 or 288 x 384 x 16). */
+#define BP_NOALLOC_WORKSPACE_BYTES (72u * 1024u * 1024u)
+
+/* Uniform start, n_iters iterations (or checkerboard passes, or sweeps) of
+ * the O(mM) update of the window potential (arguments as bp_set_potential
+ * and bp_iterate), then Eq. 3 beliefs and MAP labels into beliefs_dev
+ * ([H][W][M] float32, 16-byte aligned) and/or labels_dev ([H][W] int32),
+ * both device, either may be NULL but not both.  g_dev: device unary
+ * [H][W][M] as for bp_set_unary.  Enqueued on hip_stream (NULL: default);
+ * results equal those of the handle calls bp_init_grid .. bp_readout bit for
+ * bit.  Calls no hipMalloc/hipFree: the messages live in a device array of
+ * BP_NOALLOC_WORKSPACE_BYTES that each GPU the library runs on keeps until
+ * the process ends (looked up on the first call on that device).  All calls
+ * on one GPU share that array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and give undefined results; calls on one
+ * stream in order are safe (each starts from a full reset).
+ * Errors: BP_EINVAL (arguments as bp_set_potential / bp_iterate; a problem
+ * whose workspace exceeds BP_NOALLOC_WORKSPACE_BYTES), BP_EUNSUPPORTED
+ * (max-product with fbar above f(T) and T beyond the register windows, which
+ * needs tables staged through host memory), BP_EHIP. */
+int bp_solve_noalloc(const float* g_dev, int32_t H, int32_t W, int32_t M, int32_t T, float alpha, float fbar,
+                     int32_t mode, int32_t n_iters, int32_t schedule, float* beliefs_dev, int32_t* labels_dev,
+                     void* hip_stream);
+
 const char* bp_status_string(int status);
 const char* bp_last_error(void);
 

@@ -78,6 +78,8 @@ _PROTOS = {
     "bp_reset_messages": (_c_int, [_vp]),
     "bp_set_sync_fusion": (_c_int, [_vp, _c_i32]),
     "bp_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
+    "bp_solve_noalloc": (_c_int, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_f, _c_f, _c_i32, _c_i32, _c_i32, _vp, _vp,
+                                  _vp]),
     "bp_iterate_dense": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_beliefs": (_c_int, [_vp, _vp]),
     "bp_map_labels": (_c_int, [_vp, _vp]),
@@ -291,6 +293,15 @@ def bp_set_sync_fusion(handle, enable):
 
 def bp_iterate(handle, mode, n_iters, schedule):
     _check(lib().bp_iterate(handle, mode, n_iters, schedule), "bp_iterate")
+
+
+def bp_solve_noalloc(g, H, W, M, T, alpha, fbar, mode, n_iters, schedule, beliefs, labels, stream=None):
+    """stream: a torch stream, a raw hipStream_t address (int) or None for
+    torch's current stream on g's device."""
+    dev = g.device if hasattr(g, "device") else None
+    _check(lib().bp_solve_noalloc(_ptr(g), H, W, M, T, alpha, BP_FBAR_TIED if fbar is None else fbar, mode,
+                                  n_iters, schedule, _ptr(beliefs), _ptr(labels), _stream(stream, dev)),
+           "bp_solve_noalloc")
 
 
 def bp_iterate_dense(handle, mode, n_iters, schedule):
