@@ -733,6 +733,102 @@ __global__ __launch_bounds__(dense_block(G)) void dense_update_kernel(UpdateArgs
     }
 }
 
+// ------------------------------- dense O(M^2) sum-product, matrix cores ----
+// Eq. 2 for M = 32 or 64 (full label rows) as the matrix product it is: the
+// u rows of a wave's messages (four per pixel: 16 for M = 64, 32 for M = 32)
+// are H F, H the wave's h rows [message][x] and F the M x M table.  The
+// products run on v_mfma_f64_16x16x4 (FP64 operands, FP64 accumulation;
+// no algebraic shortcut, every F[x][y] h(x) product is formed), 16 messages
+// by 16 labels by 4 sender labels per instruction: F stays in LDS and each
+// lane reads one double of H and one of F per instruction, a quarter of the
+// operand traffic of the one-FMA-per-lane form above.  h, the
+// normalisation and the store are those of the other kernels.
+// Operand layout of the instruction (measured on gfx950): A[i][k] in lane
+// i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i mod 4),
+// element i / 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int G>
+constexpr size_t dense_mfma_lds_bytes() {
+    constexpr int M = 4 * G;
+    return ((size_t)M * M + kMaxTab + (size_t)(kBlock / 64) * (4 * (64 / G)) * (M + 1)) * sizeof(double);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void dense_mfma_kernel(UpdateArgs a) {
+    constexpr int M = 4 * G;           // full rows only
+    constexpr int MPW = 4 * (64 / G);  // messages per wave
+    constexpr int LD = M + 1;          // row stride in doubles (spreads a column over the banks)
+    constexpr int KS = M / 4;          // sender-label steps
+    constexpr int CT = M / 16;         // 16-label column tiles
+    constexpr int RPB = kBlock / G;    // pixels per workgroup tile
+    static_assert(MPW % 16 == 0, "whole 16-message batches");
+    extern __shared__ double lds_d[];
+    double* F = lds_d;                                        // [M][M]: F[x][y]
+    double* fd = F + M * M;                                   // f(d) = exp(-alpha d), d <= T
+    double* rows = fd + kMaxTab + (threadIdx.x / 64) * MPW * LD;  // this wave's [MPW][LD]
+    for (int d = threadIdx.x; d < kMaxTab; d += kBlock) fd[d] = d <= a.T ? exp(-a.alpha_d * d) : 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < M * M; i += kBlock) {
+        const int x = i / M, y = i - x * M;
+        const int d = x > y ? x - y : y - x;
+        F[i] = d <= a.T ? fd[d] : a.fbar_d;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int pos = threadIdx.x & (G - 1);
+    const int gw = lane / G;      // pixel group within the wave
+    const int x0 = pos * kLpl;
+    const int li = lane & 15, lk = lane >> 4;
+    const int n_tiles = (a.n_slots + RPB - 1) / RPB;
+    const size_t plane = (size_t)a.N * M;
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const Pixel px = map_slot(tile * RPB + (int)(threadIdx.x / G), a);
+        PixelInputs in;
+        if (px.ok) load_pixel(a, px, x0, true, in); else dummy_pixel(in);
+        double h[4][kLpl];
+        make_h_d(in, h);
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) rows[(gw * 4 + o) * LD + x0 + i] = h[o][i];
+        wave_sync();
+#pragma unroll
+        for (int nb = 0; nb < MPW / 16; ++nb) {
+            v4d acc[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+            const double* arow = rows + (nb * 16 + li) * LD + lk;
+#pragma unroll 4
+            for (int t = 0; t < KS; ++t) {
+                const double av = arow[4 * t];
+                const double* brow = F + (4 * t + lk) * M + li;
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * c], acc[c], 0, 0, 0);
+            }
+            wave_sync();  // every read of this batch's h rows is done
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) rows[(nb * 16 + 4 * r + lk) * LD + 16 * c + li] = acc[c][r];
+        }
+        wave_sync();
+        double u[4][kLpl];
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int i = 0; i < kLpl; ++i) u[o][i] = rows[(gw * 4 + o) * LD + x0 + i];
+        wave_sync();  // the rows are free for the next tile
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float m[kLpl];
+            normalise_d<G>(u[o], M, x0, true, m);
+            store_message(a.out, plane, M, a.W, px, o, x0, true, m);
+        }
+    }
+}
+
 // ------------------------------------------------------------ readout ----
 // Eq. 3: b = g * product of all incoming messages, normalised (belief_d);
 // MAP label = argmax of the normalised float32 beliefs, lowest label on ties.

@@ -49,6 +49,20 @@ __global__ __launch_bounds__(kBlock) void fill_border_kernel(float* msg, int H, 
 
 template <int G, int MODE>
 hipError_t go_dense(const UpdateArgs& a, hipStream_t s) {
+    if constexpr (MODE == kSum && (G == 8 || G == 16)) {
+        if (a.M == 4 * G) {  // Eq. 2 on the matrix cores
+            constexpr size_t lds = dense_mfma_lds_bytes<G>();
+            if (lds > 64 * 1024) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_mfma_kernel<G>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            const int n_tiles = (a.n_slots + (kBlock / G) - 1) / (kBlock / G);
+            const int grid = n_tiles < 4096 ? n_tiles : 4096;
+            hipLaunchKernelGGL((dense_mfma_kernel<G>), dim3(grid), dim3(kBlock), lds, s, a);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = dense_lds_bytes(G, a.M, MODE);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dense_update_kernel<G, MODE>),
@@ -82,7 +96,11 @@ hipError_t go_readout(const UpdateArgs& a, float* b, int* lab, hipStream_t s) {
 
 }  // namespace
 
-size_t dense_lds_need(int M, int mode) { return dense_lds_bytes(lanes_for(M), M, mode); }
+size_t dense_lds_need(int M, int mode) {
+    if (mode == kSum && M == 32) return dense_mfma_lds_bytes<8>();
+    if (mode == kSum && M == 64) return dense_mfma_lds_bytes<16>();
+    return dense_lds_bytes(lanes_for(M), M, mode);
+}
 
 hipError_t launch_dense(const UpdateArgs& a, int mode, hipStream_t stream) {
     if (a.n_slots <= 0) return hipSuccess;

@@ -85,6 +85,8 @@ STORAGE_LIMITED = {
     "stereo288x384_max_sync": "max-product, oscillating synchronous iterations",
     # f32-storage model alone: beliefs 1.7e-5 from FP64 after 100 passes
     "stereo288x384_max_checkerboard": "max-product does not contract rounding",
+    # f32-storage model alone: beliefs 4.9e-5 from FP64 after 100 iterations
+    "stereo480x640_max_sync": "max-product does not contract rounding",
     # f32-storage model alone: beliefs 1.9e-5 from FP64 after 30 iterations
     # (403 x 493, M = 128, T = 3; the smallest top-two margin is 6.8e-6)
     "batch32_5_sum_sync": "sum-product, M = 128, a weakly damped instance",
