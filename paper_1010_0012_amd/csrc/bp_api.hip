@@ -272,6 +272,8 @@ int bp_attach_workspace(bp_grid* G, void* dev_ptr, int64_t bytes) {
     G->ws = dev_ptr;
     G->ws_bytes = bytes;
     const size_t buf = align_up(G->msg_floats() * sizeof(float), 256);
+    BP_ASSERT(2 * buf <= validate_flag_offset(G));
+    BP_ASSERT(validate_flag_offset(G) + 256 <= (size_t)bytes);
     G->msg[0] = static_cast<float*>(dev_ptr);
     G->msg[1] = reinterpret_cast<float*>(static_cast<char*>(dev_ptr) + buf);
     return bp_reset_messages(G);

@@ -231,9 +231,6 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
     if (!out) return fail(BP_EINVAL, "null output handle pointer");
     *out = nullptr;
     if (n < 1 || !descs) return fail(BP_EINVAL, "need n >= 1 descriptors");
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::vector<int> arms(n);
     std::vector<float> fbars(n);
     for (int j = 0; j < n; ++j) {
@@ -253,6 +250,9 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
         if (arms[j] < 0) return fail(BP_EUNSUPPORTED, "instance %d: no compiled window for M=%d T=%d", j, d.M, d.T);
         fbars[j] = fb;
     }
+    int dev = -1;  // after the host-side checks: argument errors are reported as such without a device
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     bp_batch* B = new (std::nothrow) bp_batch();
     if (!B) return fail(BP_ENOMEM, "host allocation failed");
     B->dev = dev;
@@ -268,6 +268,7 @@ int bp_batch_init(bp_batch** out, int32_t n, const bp_grid_desc* descs, void* hi
         off += 2 * bp_align_up(B->msg_floats(j) * sizeof(float), 256);
     }
     B->total = off;
+    BP_ASSERT(B->msg_bytes_off.size() == (size_t)n && (n == 0 || B->msg_bytes_off.back() < off));
     *out = B;
     return BP_OK;
 }
@@ -289,21 +290,20 @@ int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
     if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(BP_EINVAL, "workspace not 256-byte aligned");
     if (bytes < (int64_t)B->total)
         return fail(BP_ENOMEM, "workspace %lld bytes < %zu needed", (long long)bytes, B->total);
-    int st = set_device(B);
-    if (st) return st;
-    drop_graphs(B);
-    B->ws = static_cast<char*>(dev_ptr);
-    B->ws_bytes = bytes;
-    B->hdesc.assign(B->n, bpk::InstDesc{});
+    // the instance descriptors (host), then the device
+    char* ws = static_cast<char*>(dev_ptr);
+    std::vector<bpk::InstDesc> hdesc(B->n, bpk::InstDesc{});
     long long boff = 0, loff = 0;
     for (int j = 0; j < B->n; ++j) {
         const bp_grid_desc& d = B->desc[j];
-        bpk::InstDesc& h = B->hdesc[j];
+        bpk::InstDesc& h = hdesc[j];
         memset(&h, 0, sizeof h);
         h.g = d.unary;
         const size_t buf = bp_align_up(B->msg_floats(j) * sizeof(float), 256);
-        h.msg[0] = reinterpret_cast<float*>(B->ws + B->msg_bytes_off[j]);
-        h.msg[1] = reinterpret_cast<float*>(B->ws + B->msg_bytes_off[j] + buf);
+        BP_ASSERT(B->msg_bytes_off[j] + 2 * buf <= (size_t)bytes);
+        BP_ASSERT(j + 1 == B->n || B->msg_bytes_off[j] + 2 * buf == B->msg_bytes_off[j + 1]);
+        h.msg[0] = reinterpret_cast<float*>(ws + B->msg_bytes_off[j]);
+        h.msg[1] = reinterpret_cast<float*>(ws + B->msg_bytes_off[j] + buf);
         h.belief_off = boff;
         h.label_off = loff;
         h.H = d.H; h.W = d.W; h.M = d.M; h.N = d.H * d.W; h.T = d.T;
@@ -319,6 +319,12 @@ int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
         boff += (long long)h.N * d.M;
         loff += h.N;
     }
+    int st = set_device(B);
+    if (st) return st;
+    drop_graphs(B);
+    B->ws = ws;
+    B->ws_bytes = bytes;
+    B->hdesc.swap(hdesc);
     build_launches(B);
     return bp_batch_reset_messages(B);
 }

@@ -115,6 +115,7 @@ void build_tables(bp_fgraph* F, const std::vector<std::vector<int>>& tup, const 
 size_t place(size_t& off, size_t bytes) {
     const size_t at = off;
     off += bp_align_up(std::max<size_t>(bytes, 1), 256);
+    BP_ASSERT(at % 256 == 0 && off >= at + bytes);
     return at;
 }
 
@@ -189,12 +190,8 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
     if (n_types < 1 || n_types > bpk::kFgMaxTypes || !types)
         return fail(BP_EINVAL, "n_types must be in [1, %d]", bpk::kFgMaxTypes);
     if ((int64_t)n_factors * 3 * M >= (int64_t(1) << 31)) return fail(BP_EINVAL, "too many factor messages");
-    int dev = -1;
-    hipError_t he = hipGetDevice(&dev);
-    if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
     bp_fgraph* F = new (std::nothrow) bp_fgraph();
     if (!F) return fail(BP_ENOMEM, "host allocation failed");
-    F->dev = dev;
     F->stream = static_cast<hipStream_t>(hip_stream);
     F->n_vars = n_vars;
     F->M = M;
@@ -313,6 +310,15 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
     memcpy(F->image.data() + F->off_items, F->items.data(), F->items.size() * sizeof(int));
     copy_tables(F->sparse, F->image.data());
     if (F->has_dense) copy_tables(F->dense, F->image.data());
+    BP_ASSERT(F->off_items + F->items.size() * sizeof(int) <= tables_end && tables_end <= F->off_m);
+    BP_ASSERT(F->off_n + (size_t)n_factors * 3 * M * sizeof(float) <= F->total);
+    int dev = -1;  // after the host-side build: argument errors are reported as such without a device
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) {
+        delete F;
+        return hip_fail(he, "hipGetDevice");
+    }
+    F->dev = dev;
     *out = F;
     return BP_OK;
 }

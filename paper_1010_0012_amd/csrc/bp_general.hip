@@ -34,6 +34,7 @@ TabLayout layout(int n_types, int M, size_t entries_per_orientation) {
         o += bp_align_up(std::max<size_t>(sz[i], 1), 256);
     }
     L.total = o;
+    for (int i = 0; i < 5; ++i) BP_ASSERT(L.off[i] % 256 == 0 && L.off[i] + sz[i] <= L.total);
     return L;
 }
 

@@ -32,6 +32,8 @@ struct GradLayout {
         lam_off = seg_off + (size_t)(n > 0 ? (k < n ? k : n) : 0) * buf;
         part_off = lam_off + 2 * buf;
         total = part_off + bp_align_up(blocks * sizeof(float), 256);
+        BP_ASSERT(ckpt_off <= seg_off && seg_off <= lam_off && lam_off + 2 * buf == part_off && part_off < total);
+        BP_ASSERT(seg_off == (size_t)nckpt * buf && nckpt <= nseg);
     }
     float* ckpt(char* ws, int i) const { return reinterpret_cast<float*>(ws + ckpt_off + i * buf); }
     float* seg(char* ws, int i) const { return reinterpret_cast<float*>(ws + seg_off + i * buf); }

@@ -51,6 +51,23 @@ struct bp_grid {
     size_t msg_floats() const { return (size_t)4 * N * M; }
 };
 
+// BP_DEBUG builds check the host side's workspace carving and index
+// arithmetic as they go and abort on the first violation (host code only;
+// the sanitizer build of the host runtime compiles with it).
+#ifdef BP_DEBUG
+#include <cstdio>
+#include <cstdlib>
+#define BP_ASSERT(cond)                                                                     \
+    do {                                                                                    \
+        if (!(cond)) {                                                                      \
+            std::fprintf(stderr, "BP_ASSERT failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
+            std::abort();                                                                   \
+        }                                                                                   \
+    } while (0)
+#else
+#define BP_ASSERT(cond) ((void)0)
+#endif
+
 // Workspace carving shared by the host files.
 size_t bp_align_up(size_t v, size_t a);
 

@@ -136,6 +136,11 @@ std::vector<Level> plan_levels(const bp_grid* G, int levels, size_t* total) {
         }
     }
     *total = off;
+    for (int l = 1; l <= levels; ++l) {
+        BP_ASSERT(L[l].unary_off % 256 == 0 && L[l].msg_off[0] % 256 == 0 && L[l].msg_off[1] % 256 == 0);
+        BP_ASSERT(L[l].unary_off < L[l].msg_off[0] && L[l].msg_off[0] < L[l].msg_off[1] && L[l].msg_off[1] < off);
+        BP_ASSERT(L[l].H >= 1 && L[l].W >= 1 && 2 * L[l].H >= L[l - 1].H && 2 * L[l].W >= L[l - 1].W);
+    }
     return L;
 }
 
