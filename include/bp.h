@@ -146,6 +146,23 @@ int bp_reset_messages(bp_grid* grid);
  * schedule (bp_iterate_dense returns BP_EUNSUPPORTED). */
 int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
 
+/* Arithmetic of the update.  BP_ARITH_F64 (the default): h, the window sums,
+ * the normaliser and the normalisation in double, every stored message its
+ * exact value rounded once to float32.  BP_ARITH_F32: the same Eq. 7
+ * sum-product update entirely in float32 (a few roundings per message,
+ * contracted by sum-product; results agree with BP_ARITH_F64 to rounding,
+ * not bit for bit), where it is compiled: sum-product of the window
+ * potential with fbar > 0 (with fbar = 0 messages reach zero and the
+ * denormal range, where float32 products lose their precision), the
+ * synchronous or checkerboard schedule, T within the
+ * register windows (T <= 16, 12 for M <= 16), M = 4 * ceil-pow2(M / 4) (16,
+ * 32, 64, 128, 256) and 4*H*W*M bytes below 2^32.  Everything else (max-
+ * product, sweeps, dense, general potentials, batches, multi-scale, the
+ * gradient) computes in double whatever this says.  BP_EINVAL for another
+ * value. */
+enum bp_arith { BP_ARITH_F64 = 0, BP_ARITH_F32 = 1 };
+int bp_set_arithmetic(bp_grid* grid, int32_t arith);
+
 /* Synchronous iterations and checkerboard passes of the window potential
  * run two per launch by default (where a register window is compiled: T <=
  * 16, 12 for M <= 16; not for Eq. 10): each pixel computes the four

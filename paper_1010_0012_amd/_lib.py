@@ -21,6 +21,7 @@ BP_SUM_PRODUCT, BP_MAX_PRODUCT = 0, 1
 BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD, BP_SCHED_SWEEP = 0, 1, 2
 BP_MAX_LABELS = 256
 BP_FBAR_TIED = -1.0
+BP_ARITH_F64, BP_ARITH_F32 = 0, 1
 
 _c_int, _c_i32, _c_i64, _c_f, _vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
 
@@ -77,6 +78,7 @@ _PROTOS = {
     "bp_set_unary": (_c_int, [_vp, _vp]),
     "bp_reset_messages": (_c_int, [_vp]),
     "bp_set_sync_fusion": (_c_int, [_vp, _c_i32]),
+    "bp_set_arithmetic": (_c_int, [_vp, _c_i32]),
     "bp_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_solve_noalloc": (_c_int, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_f, _c_f, _c_i32, _c_i32, _c_i32, _vp, _vp,
                                   _vp]),
@@ -289,6 +291,10 @@ def bp_reset_messages(handle):
 
 def bp_set_sync_fusion(handle, enable):
     _check(lib().bp_set_sync_fusion(handle, 1 if enable else 0), "bp_set_sync_fusion")
+
+
+def bp_set_arithmetic(handle, arith):
+    _check(lib().bp_set_arithmetic(handle, arith), "bp_set_arithmetic")
 
 
 def bp_iterate(handle, mode, n_iters, schedule):

@@ -128,6 +128,14 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     if ((st = with_device(G))) return st;
     // sparse sum uses w(d) = f(d) - fbar; sparse max and dense use f(d)
     const float* tab = (!dense && kmode == bpk::kSum) ? G->tab_w : G->tab_f;
+    // float32 arithmetic (BP_ARITH_F32) where it is compiled: sum-product of
+    // the window potential with fbar > 0 (every message entry then stays at
+    // or above fbar/M, so h cannot underflow), synchronous or checkerboard, a
+    // register window, full label rows (M = 4G), inbox planes below 2^32 bytes
+    const bool f32 = G->arith_f32 && kmode == bpk::kSum && !dense && schedule != BP_SCHED_SWEEP && G->fbar > 0.0f &&
+                     bpk::sparse_variant_tw(G->M, G->T) >= 0 && G->M == 4 * bpk::lanes_for(G->M) &&
+                     (uint64_t)G->N * G->M * sizeof(float) < (uint64_t(1) << 32);
+    const int kupd = f32 ? bpk::kSumF32 : kmode;
     if (schedule == BP_SCHED_SWEEP) {
         // One sweep = passes with messages travelling left, right, up, down.
         // The left and right passes are independent (each reads the up and
@@ -161,7 +169,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
                 a.mid = G->msg[G->cur ^ 1];
             }
             memcpy(a.tab, tab, sizeof a.tab);
-            hipError_t e = bpk::launch_sparse2(a, kmode, G->stream);
+            hipError_t e = bpk::launch_sparse2(a, kupd, G->stream);
             if (e != hipSuccess) return hip_fail(e, "fused sparse update launch");
             G->cur ^= 1;
             if (schedule == BP_SCHED_CHECKERBOARD) G->cb_pass += 2;
@@ -177,7 +185,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
         memcpy(a.tab, tab, sizeof a.tab);
         a.eq10 = eq10;
         hipError_t e = dense ? bpk::launch_dense(a, kmode, G->stream)
-                             : bpk::launch_sparse(a, kmode, G->stream);
+                             : bpk::launch_sparse(a, kupd, G->stream);
         if (e != hipSuccess) return hip_fail(e, dense ? "dense update launch" : "sparse update launch");
         if (schedule == BP_SCHED_SYNC) G->cur ^= 1;
         else G->cb_pass++;
@@ -196,6 +204,13 @@ extern "C" {
 int bp_set_sync_fusion(bp_grid* G, int32_t enable) {
     if (!G) return fail(BP_EINVAL, "null handle");
     G->fuse_sync = enable != 0;
+    return BP_OK;
+}
+
+int bp_set_arithmetic(bp_grid* G, int32_t arith) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (arith != BP_ARITH_F64 && arith != BP_ARITH_F32) return fail(BP_EINVAL, "bad arithmetic %d", arith);
+    G->arith_f32 = arith == BP_ARITH_F32;
     return BP_OK;
 }
 

@@ -29,7 +29,9 @@ constexpr int kBlock = BP_BLOCK;    // threads per workgroup
 constexpr int kMaxTab = 256;        // potential table entries (|d| < BP_MAX_LABELS)
 constexpr int kDTab = 32;           // double window weights carried in the arguments (|d| <= 31)
 
-enum Mode { kSum = 0, kMax = 1 };
+// kSumF32: sum-product with float32 arithmetic (BP_ARITH_F32), used by the
+// synchronous and checkerboard window kernels only.
+enum Mode { kSum = 0, kMax = 1, kSumF32 = 2 };
 
 #ifndef BP_MSG_NT
 #define BP_MSG_NT 1

@@ -28,6 +28,7 @@ struct bp_grid {
     int cur = 0;                          // buffer holding the current state
     int64_t cb_pass = 0;                  // checkerboard passes since reset
     bool fuse_sync = true;                // sync iterations run two per launch where compiled
+    bool arith_f32 = false;               // BP_ARITH_F32: float32 arithmetic where compiled
     const float* g = nullptr;
     // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10
     // tables of the window potential built into the workspace's table region

@@ -270,6 +270,51 @@ __device__ __forceinline__ float group_total(const float (&v)[kLpl]) {
     return group_reduce<MODE, G>(s);
 }
 
+// ------------------------------------- FP32 arithmetic (sum-product) ----
+// The Eq. 7 message with h, S, the window, Z and the normalisation all in
+// float32 (the BP_ARITH_F32 setting of a grid): one FP32 FMA per tap, one DPP
+// move per shifted value and no conversions, against the double path's two
+// moves per value and the conversions in and out.  Every step rounds to
+// float32, so a message carries a few roundings instead of one; sum-product
+// contracts them (the synchronous and checkerboard kernels use it; the
+// results agree with the double path to rounding, not bit for bit).
+__device__ __forceinline__ void sender_h_f(const float (&g)[kLpl], const float (&ma)[kLpl], const float (&mb)[kLpl],
+                                           const float (&mc)[kLpl], float (&h)[kLpl]) {
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) h[i] = ((g[i] * ma[i]) * mb[i]) * mc[i];
+}
+
+// 1/z from the hardware reciprocal and one Newton step (about one ulp).
+__device__ __forceinline__ float recip_f(float z) {
+    const float r = __builtin_amdgcn_rcpf(z);
+    return fmaf(r, fmaf(-z, r, 1.0f), r);
+}
+
+template <int G>
+__device__ __forceinline__ void normalise_f(float (&u)[kLpl], int M, int x0, bool full, float (&m)[kLpl]) {
+    float z = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) {
+        if (!full && x0 + i >= M) u[i] = 0.0f;
+        z += u[i];
+    }
+    z = group_sum<G>(z);
+    const float inv = recip_f(z);
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) m[i] = u[i] * inv;
+}
+
+// wtab: f(d) - fbar in float32 for d <= T (0 beyond), fbar in float32.
+template <int G, int TW>
+__device__ __forceinline__ void sum_message_f(const float (&h)[kLpl], const float* wtab, float fbar, int pos, int M,
+                                              int x0, bool full, float (&m)[kLpl]) {
+    float s = (h[0] + h[1]) + (h[2] + h[3]);
+    s = group_sum<G>(s);
+    float u[kLpl];
+    window_apply<G, TW, kSum>(h, wtab, fbar * s, pos, u);
+    normalise_f<G>(u, M, x0, full, m);
+}
+
 // Grid-wide update, register window.  One group of G lanes per sending
 // pixel; a wave's load and store instructions cover 64/G consecutive pixels.
 // EQ10: max-product with Eq. 10 (max_message_eq10_d, one LDS row per group).
@@ -285,17 +330,28 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
     PixelInputs in;
     load_pixel(a, px, x0, full, in);
     const size_t plane = (size_t)a.N * a.M;
-    double h[4][kLpl];
-    make_h_d(in, h);
+    if constexpr (MODE == kSumF32) {
+        float h[4][kLpl];
+        make_h(in, h);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        float u[kLpl];
-        if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], a.dtab, a.fbar_d, pos, a.M, x0, full, u);
-        else if constexpr (EQ10)
-            max_message_eq10_d<G, TW>(h[o], a.tab, a.fbar, a.T, pos, a.M, x0, full,
-                                      lds_d + (threadIdx.x / G) * eq10_row_doubles(G), u);
-        else max_message_d<G, TW>(h[o], a.tab, a.fbar, pos, a.M, x0, full, u);
-        store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
+        for (int o = 0; o < 4; ++o) {
+            float u[kLpl];
+            sum_message_f<G, TW>(h[o], a.tab, a.fbar, pos, a.M, x0, full, u);
+            store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
+        }
+    } else {
+        double h[4][kLpl];
+        make_h_d(in, h);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float u[kLpl];
+            if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], a.dtab, a.fbar_d, pos, a.M, x0, full, u);
+            else if constexpr (EQ10)
+                max_message_eq10_d<G, TW>(h[o], a.tab, a.fbar, a.T, pos, a.M, x0, full,
+                                          lds_d + (threadIdx.x / G) * eq10_row_doubles(G), u);
+            else max_message_d<G, TW>(h[o], a.tab, a.fbar, pos, a.M, x0, full, u);
+            store_message(a.out, plane, a.M, a.W, px, o, x0, full, u);
+        }
     }
 }
 
@@ -349,13 +405,6 @@ __device__ __forceinline__ void message_d(const double (&h)[kLpl], const double*
     else max_message_d<G, TW>(h, tab, fbar, pos, M, x0, full, m);
 }
 
-// Both iterations for one pixel px of an H x W grid (in -> out); with
-// mid_out, the first iteration's messages into px are stored there too
-// (px's own inbox slots, coalesced).  FULL:
-// M == 4G, known at compile time so that no load or normalisation carries a
-// branch.  Loads are unconditional: a missing neighbour (or a missing row of
-// a neighbour's inbox) reads a valid row and is replaced by the factor 1,
-// which keeps every load of the pixel in one basic block.
 // The arithmetic of both iterations for one receiver p: rows[k] are the
 // unary and the three inbox rows of the neighbour in direction k that its
 // message to p uses ({g, the two partial-product rows, the far-side row}),
@@ -371,9 +420,15 @@ __device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], co
     PixelInputs mid;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double h[kLpl];
-        sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
-        message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
+        if constexpr (MODE == kSumF32) {
+            float h[kLpl];
+            sender_h_f(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
+            sum_message_f<G, TW>(h, tab, fbar, pos, M, x0, FULL, mid.m[k]);
+        } else {
+            double h[kLpl];
+            sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
+            message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
+        }
 #pragma unroll
         for (int i = 0; i < kLpl; ++i) mid.m[k][i] = has[k] ? mid.m[k][i] : 1.0f;
         put_mid(k, mid.m[k]);
@@ -381,13 +436,24 @@ __device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], co
     // Second iteration, sender side, from the messages just computed.
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
-    double h[4][kLpl];
-    make_h_d(mid, h);
+    if constexpr (MODE == kSumF32) {
+        float h[4][kLpl];
+        make_h(mid, h);
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        float u[kLpl];
-        message_d<G, TW, MODE>(h[o], dtab, fbar_d, tab, fbar, pos, M, x0, FULL, u);
-        put_out(o, u);
+        for (int o = 0; o < 4; ++o) {
+            float u[kLpl];
+            sum_message_f<G, TW>(h[o], tab, fbar, pos, M, x0, FULL, u);
+            put_out(o, u);
+        }
+    } else {
+        double h[4][kLpl];
+        make_h_d(mid, h);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            float u[kLpl];
+            message_d<G, TW, MODE>(h[o], dtab, fbar_d, tab, fbar, pos, M, x0, FULL, u);
+            put_out(o, u);
+        }
     }
 }
 
@@ -782,12 +848,17 @@ __global__ __launch_bounds__(kBlock) void dense_mfma_kernel(UpdateArgs a) {
     const int li = lane & 15, lk = lane >> 4;
     const int n_tiles = (a.n_slots + RPB - 1) / RPB;
     const size_t plane = (size_t)a.N * M;
+    // the next tile's inputs are loaded before this tile's products run
+    Pixel px_next = map_slot(blockIdx.x * RPB + (int)(threadIdx.x / G), a);
+    PixelInputs in_next;
+    if (blockIdx.x < n_tiles && px_next.ok) load_pixel(a, px_next, x0, true, in_next); else dummy_pixel(in_next);
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const Pixel px = map_slot(tile * RPB + (int)(threadIdx.x / G), a);
-        PixelInputs in;
-        if (px.ok) load_pixel(a, px, x0, true, in); else dummy_pixel(in);
+        const Pixel px = px_next;
         double h[4][kLpl];
-        make_h_d(in, h);
+        make_h_d(in_next, h);
+        const int nt = tile + gridDim.x;
+        px_next = map_slot(nt * RPB + (int)(threadIdx.x / G), a);
+        if (nt < n_tiles && px_next.ok) load_pixel(a, px_next, x0, true, in_next); else dummy_pixel(in_next);
 #pragma unroll
         for (int o = 0; o < 4; ++o)
 #pragma unroll

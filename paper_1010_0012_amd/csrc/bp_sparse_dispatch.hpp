@@ -64,7 +64,11 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
 // selects the branch-free full-row instance.
 template <int G, int TW, int MODE>
 hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
-    if (a.M == G * kLpl && (uint64_t)a.N * a.M * sizeof(float) < (uint64_t(1) << 32)) {
+    const bool rows = a.M == G * kLpl && (uint64_t)a.N * a.M * sizeof(float) < (uint64_t(1) << 32);
+    if constexpr (MODE == kSumF32) {
+        if (!rows) return hipErrorInvalidValue;  // float32 arithmetic: row-block launches only
+    }
+    if (rows) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
         const int slots = a.colour < 0 ? a.W : a.half_w;
         const int gx = (slots + kBlock / G - 1) / (kBlock / G);
@@ -76,6 +80,7 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
     }
     const int nblk = (int)groups_blocks<G>(a.n_slots);
     const int per = (nblk + kXcds - 1) / kXcds;
+    if constexpr (MODE == kSumF32) return hipErrorInvalidValue;
     if (a.M == G * kLpl)
         hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, true>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
                            0, s, a, per);
@@ -117,6 +122,8 @@ hipError_t dispatch_tw(const UpdateArgs& a, int tw, hipStream_t s) {
         constexpr int TW = TwList<G>::v[I];
         if (tw == TW) return go_sparse<G, TW, MODE>(a, s);
         return dispatch_tw<G, MODE, I + 1>(a, tw, s);
+    } else if constexpr (MODE == kSumF32) {
+        return hipErrorInvalidValue;  // float32 arithmetic: register windows only
     } else {
         return go_sparse_wide<G, MODE>(a, s);
     }

@@ -94,6 +94,11 @@ class Grid:
         """Two synchronous iterations per launch (default on; same results)."""
         L.bp_set_sync_fusion(self.handle, enable)
 
+    def set_arithmetic(self, arith):
+        """"f64" (default) or "f32": the arithmetic of the sum-product window
+        update where a float32 kernel is compiled (bp_set_arithmetic)."""
+        L.bp_set_arithmetic(self.handle, {"f64": L.BP_ARITH_F64, "f32": L.BP_ARITH_F32}[arith])
+
     def iterate(self, mode="sum", n_iters=1, schedule="sync", dense=False):
         self._sync_stream()
         fn = L.bp_iterate_dense if dense else L.bp_iterate

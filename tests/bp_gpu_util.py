@@ -19,13 +19,14 @@ def say(*a):
 
 
 def run_gpu(g32, M, T, alpha, fbar=None, mode="sum", schedule="sync", n_iters=5, dense=False,
-            init=None, want_messages=True, fuse=True):
+            init=None, want_messages=True, fuse=True, arith="f64"):
     import torch
     from paper_1010_0012_amd.grid import Grid
     H, W, _ = g32.shape
     grid = Grid(H, W)
     grid.set_potential(M, T, alpha, fbar)
     grid.set_sync_fusion(fuse)
+    grid.set_arithmetic(arith)
     g = torch.from_numpy(np.ascontiguousarray(g32)).cuda()
     grid.set_unary(g)
     if init is not None:

@@ -39,7 +39,7 @@ def load(name):
     return {k: z[k] for k in z.files if k != "meta"}, json.loads(str(z["meta"]))
 
 
-def gpu_solve(meta):
+def gpu_solve(meta, arith="f64"):
     import torch
     src, mode, sched, n = meta["source"], meta["mode"], meta["schedule"], meta["n"]
     if src.startswith("batch:"):
@@ -60,6 +60,7 @@ def gpu_solve(meta):
     g32, _ = make_config(cfg)
     grid = Grid(cfg.H, cfg.W)
     grid.set_potential(cfg.M, cfg.T, cfg.alpha)
+    grid.set_arithmetic(arith)
     grid.set_unary(torch.from_numpy(g32).cuda())
     grid.iterate(mode, n, sched)
     b = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device="cuda")
@@ -112,3 +113,20 @@ def test_end_to_end(name):
     STORAGE_LIMITED_SEEN.append((name, err, len(bad), meta["store_max_db"]))
     assert err32 <= STORAGE_TOL, (name, err32)
     assert not bad32, (name, bad32[:5])
+
+
+@pytest.mark.parametrize("name", ["stereo480x640_sum_sync", "stereo480x640_sum_checkerboard"])
+def test_end_to_end_f32_arithmetic(name):
+    """The 480x640 sum-product solves with float32 arithmetic against the
+    FP64 oracle's solve: the bar itself (beliefs within 1e-5, MAP equal where
+    the FP64 margin exceeds 1e-6)."""
+    ref, meta = load(name)
+    H, W, M = meta["H"], meta["W"], meta["M"]
+    say(f"end-to-end {name}, float32 arithmetic")
+    g32, b, lab = gpu_solve(meta, arith="f32")
+    np.testing.assert_array_equal(lab, np.argmax(b, axis=-1))
+    err = float(np.max(np.abs(b.reshape(H * W, M)[ref["sample_idx"]] - ref["sample_b"])))
+    bad = label_mismatches(lab, ref["labels"], ref["low_idx"], ref["low_margin"])
+    say(f"{name} [float32 arithmetic]: FP64 max|db| = {err:.2e}, MAP mismatches (margin > 1e-6) = {len(bad)}")
+    assert err <= BELIEF_TOL
+    assert not bad, bad[:5]

@@ -167,6 +167,43 @@ def test_pair_launch_inner_waves(shape, mode, schedule):
     check(tag, a, g32, M, T, alpha, fbar, mode, schedule, n, gb.SPARSE)
 
 
+# Shapes where the float32-arithmetic sum-product kernels run (M = 4G, a
+# register window): every lane class, several window widths, ragged grids
+# with interior waves, fbar = 0 and fbar above f(T).
+F32_SHAPES = [(5, 7, 16, 2, 1.0, None), (23, 41, 64, 4, 0.5, None), (19, 150, 16, 2, 1.0, None),
+              (17, 75, 32, 3, 0.7, None), (13, 29, 128, 8, 0.3, None), (11, 21, 256, 6, 0.2, None),
+              (9, 33, 64, 16, 0.1, None), (6, 5, 16, 0, 1.0, 0.2), (21, 37, 64, 3, 0.4, 0.0),
+              (12, 14, 32, 5, 0.6, 0.5), (1, 40, 16, 2, 1.0, None), (40, 1, 32, 3, 0.8, None)]
+
+
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("shape", F32_SHAPES, ids=_id)
+def test_f32_arithmetic(shape, schedule):
+    """Sum-product with float32 arithmetic: pair launches equal single
+    launches bit for bit, the parity rule against the oracle holds, and the
+    result is within 1e-6 of the double-arithmetic kernels."""
+    H, W, M, T, alpha, fbar = shape
+    g32 = random_unary(H, W, M, 700 + F32_SHAPES.index(shape))
+    tag = f"f32 arithmetic sum {schedule} {_id(shape)}"
+    say(tag)
+    for n in (5, 6):
+        a = run_gpu(g32, M, T, alpha, fbar, "sum", schedule, n, arith="f32")
+        b = run_gpu(g32, M, T, alpha, fbar, "sum", schedule, n, arith="f32", fuse=False)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    d = run_gpu(g32, M, T, alpha, fbar, "sum", schedule, 6)
+    if fbar == 0.0:
+        # fbar = 0 lets messages reach zero, where float32 products lose their
+        # precision: the library keeps double arithmetic there
+        for x, y in zip(a, d):
+            np.testing.assert_array_equal(x, y)
+    else:
+        assert np.max(np.abs(a[0] - d[0])) <= 1e-6 and np.max(np.abs(a[1] - d[1])) <= 1e-6
+        if H * W * M >= 10000:
+            assert not np.array_equal(a[0], d[0])   # the float32 kernels ran (they round differently)
+    check(tag, a, g32, M, T, alpha, fbar, "sum", schedule, 6, gb.SPARSE)
+
+
 def test_deterministic():
     g32 = random_unary(31, 29, 64, 9)
     a = run_gpu(g32, 64, 4, 0.5, None, "sum", "sync", 7)
