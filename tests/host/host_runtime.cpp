@@ -47,6 +47,7 @@ static void null_handles() {
     EXPECT(bp_iterate(nullptr, BP_SUM_PRODUCT, 1, BP_SCHED_SYNC) == BP_EINVAL);
     EXPECT(bp_iterate_dense(nullptr, BP_SUM_PRODUCT, 1, BP_SCHED_SYNC) == BP_EINVAL);
     EXPECT(bp_set_sync_fusion(nullptr, 1) == BP_EINVAL);
+    EXPECT(bp_set_arithmetic(nullptr, BP_ARITH_F32) == BP_EINVAL);
     EXPECT(bp_beliefs(nullptr, &f) == BP_EINVAL);
     EXPECT(bp_map_labels(nullptr, &i) == BP_EINVAL);
     EXPECT(bp_readout(nullptr, nullptr, nullptr) == BP_EINVAL);
@@ -112,6 +113,9 @@ static void potentials_and_layouts() {
                 EXPECT(bp_attach_workspace(&G, w, ws - 1) == BP_ENOMEM);
                 EXPECT(bp_attach_workspace(&G, static_cast<char*>(w) + 16, ws) == BP_EINVAL);
                 EXPECT(bp_attach_workspace(&G, w, ws) == BP_EHIP);
+                EXPECT(bp_set_arithmetic(&G, BP_ARITH_F32) == BP_OK && G.arith_f32);
+                EXPECT(bp_set_arithmetic(&G, 7) == BP_EINVAL && G.arith_f32);
+                EXPECT(bp_set_arithmetic(&G, BP_ARITH_F64) == BP_OK && !G.arith_f32);
                 // other potentials on the same handle
                 EXPECT(bp_set_potential(&G, M, T, 1.5f, 0.0f) == BP_OK);
                 EXPECT(bp_set_potential(&G, M, T, -0.3f, 0.5f) == BP_OK);

@@ -30,8 +30,9 @@ from synth_mrf import CONFIGS, make_batch_configs, make_batch_instance, make_con
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = ["stereo480x640_sum_sync", "stereo480x640_sum_checkerboard", "stereo480x640_max_sync", "stereo288x384_max_sync",
-         "stereo288x384_max_checkerboard", "batch32_5_sum_sync", "batch32_3_sum_sync"]
+CASES = ["stereo480x640_sum_sync", "stereo480x640_sum_checkerboard", "stereo480x640_max_sync",
+         "stereo480x640_max_checkerboard", "stereo288x384_max_sync", "stereo288x384_max_checkerboard",
+         "batch32_5_sum_sync", "batch32_3_sum_sync"]
 
 
 def load(name):
