@@ -34,6 +34,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Legs beside the headline: other schedules and modes of the sparse update,
+# the dense O(M^2) update, sweeps, coarse-to-fine, general potentials,
+# factor graphs, the fbar = 0 experiment, forward + backward, batches.
+LEGS = ("sparse", "dense", "sweep", "multiscale", "general", "factor", "fbar0", "grad", "batch")
+
+
 def alg_bytes_per_sync_iter(cfg):
     """Each live message entry read once and written once, unary read once:
     4 * M * (2E + N) bytes per synchronous iteration."""
@@ -42,15 +48,18 @@ def alg_bytes_per_sync_iter(cfg):
 
 KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
                   "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp",
-                  "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_update2_stereo480x640.json")
+                  "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip",
+                  "paper_1010_0012_amd/csrc/bp_launch_sparse_sumf.hip",
+                  "paper_1010_0012_amd/csrc/bp_launch_misc.hip"]
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_pair_rows_f32_stereo480x640.json")
 
 
-def sparse_kernel_name(M, T, mode, pair=False):
+def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0):
     """Template instance of the sparse update that runs (M, T): lanes per pixel
     G is the smallest power of two >= ceil(M/4) in [4, 64]; the window width is
-    the smallest compiled half-width >= T; pair: the two-iteration launch
-    (whose last parameter says whether M = 4G)."""
+    the smallest compiled half-width >= T; pair: the two-iteration launch,
+    whose row-block form runs when M = 4G and the messages of one direction
+    fit 32-bit byte offsets (mode 2: sum-product in float32 arithmetic)."""
     G = 4
     while G * 4 < M and G < 64:
         G *= 2
@@ -58,6 +67,8 @@ def sparse_kernel_name(M, T, mode, pair=False):
     tw = next((t for t in tws if t >= T), None)
     if tw is None:
         return f"sparse_update_wide_kernel<{G}, {mode}>"
+    if pair and M == 4 * G and n_pixels * M * 4 < 2 ** 32:
+        return f"sparse_update2_rows_kernel<{G}, {tw}, {mode}>"
     if pair:
         return f"sparse_update2_kernel<{G}, {tw}, {mode}, {'true' if M == 4 * G else 'false'}>"
     return f"sparse_update_kernel<{G}, {tw}, {mode}>"
@@ -482,7 +493,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-legs", action="store_true", help="skip the max/checkerboard/dense legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip every leg beside the headline")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help=f"comma-separated legs to run beside the headline, of {','.join(LEGS)}")
+    ap.add_argument("--arith", choices=("f32", "f64"), default="f32",
+                    help="arithmetic of the headline sum-product update (bp_set_arithmetic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this library has no multi-GPU path "
@@ -502,6 +517,7 @@ def main():
     g = torch.from_numpy(g32).to(dev)
     grid = Grid(cfg.H, cfg.W)
     grid.set_potential(cfg.M, cfg.T, cfg.alpha)
+    grid.set_arithmetic(args.arith)
     grid.set_unary(g)
     beliefs = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device=dev)
     labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device=dev)
@@ -514,7 +530,7 @@ def main():
         grid.iterate(mode, n, schedule, dense=dense)
         grid.readout(beliefs, labels)
 
-    log(f"bench: {cfg.name} {cfg.H}x{cfg.W} M={cfg.M} T={cfg.T} iters={cfg.iters}")
+    log(f"bench: {cfg.name} {cfg.H}x{cfg.W} M={cfg.M} T={cfg.T} iters={cfg.iters}, {args.arith} arithmetic")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -539,7 +555,9 @@ def main():
     per_iter_equiv = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                "kernel": sparse_kernel_name(cfg.M, cfg.T, 0, pair=True),
+                "kernel": sparse_kernel_name(cfg.M, cfg.T, 2 if args.arith == "f32" else 0, pair=True,
+                                             n_pixels=cfg.n_pixels),
+                "arithmetic": args.arith,
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3,
                 "iterations_per_launch": 2,
                 # one iteration's algorithmic bytes (the per-iteration model:
@@ -566,10 +584,33 @@ def main():
     extra["sparse_sum_sync_pair_per_iteration_equiv_frac"] = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9 / HBM_PEAK_GBS
     log(f"bench: sparse sum single launch {ms_single * 1e3:.1f} us "
         f"({bytes_launch / (ms_single * 1e-3) / 1e9:.0f} GB/s); pair launch per iteration {ms_launch * 500:.1f} us")
-    if not args.no_legs:
-        for mode, sched, dense in (("max", "sync", False), ("sum", "checkerboard", False),
-                                   ("max", "checkerboard", False), ("sum", "sync", True),
-                                   ("max", "sync", True)):
+    # the other arithmetic beside it (double: every message its exact value rounded once)
+    other = "f64" if args.arith == "f32" else "f32"
+    grid.set_arithmetic(other)
+    ms_o = time_launches(grid, "sum", cfg.iters, "sync", False, reps, iters_per_launch=2)
+    grid.readout(beliefs, labels)
+    extra[f"sparse_sum_sync_{other}_pair_launch_us"] = ms_o * 1e3
+    extra[f"sparse_sum_sync_{other}_pair_launch_frac"] = bytes_launch / (ms_o * 1e-3) / 1e9 / HBM_PEAK_GBS
+    extra[f"sparse_sum_sync_{other}_accuracy"] = golden_accuracy(f"{cfg.name}_sum_sync", beliefs.cpu().numpy(),
+                                                                labels.cpu().numpy())
+    grid.set_sync_fusion(False)
+    extra[f"sparse_sum_sync_{other}_single_launch_us"] = time_launches(grid, "sum", cfg.iters, "sync", False,
+                                                                      reps) * 1e3
+    grid.set_sync_fusion(True)
+    grid.set_arithmetic(args.arith)
+    log(f"bench: {other} arithmetic: pair launch {ms_o * 1e3:.1f} us, single launch "
+        f"{extra[f'sparse_sum_sync_{other}_single_launch_us']:.1f} us")
+    legs = set() if args.no_legs else {x for x in args.legs.split(",") if x}
+    unknown = legs - set(LEGS)
+    if unknown:
+        raise SystemExit(f"bench.py: unknown legs {sorted(unknown)}; known: {','.join(LEGS)}")
+    schedule_legs = []
+    if "sparse" in legs:
+        schedule_legs += [("max", "sync", False), ("sum", "checkerboard", False), ("max", "checkerboard", False)]
+    if "dense" in legs:
+        schedule_legs += [("sum", "sync", True), ("max", "sync", True)]
+    if schedule_legs:
+        for mode, sched, dense in schedule_legs:
             # sparse launches run two iterations (sync) or two passes
             # (checkerboard) each; dense launches run one
             n = cfg.iters if sched == "sync" else 2 * cfg.iters
@@ -588,20 +629,39 @@ def main():
             extra[key + f"_us_per_{unit}"] = step * 1e3
             log(f"bench: {key}: {ms * 1e3:.1f} us per launch, {step * 1e3:.1f} us per {unit}, "
                 f"{updates_per_iter / (per_iter * 1e-3):.4e} updates/s")
+    if {"sparse", "dense"} <= legs:
+        # sparse O(mM) against dense O(M^2), like for like: one iteration per
+        # launch on both sides, and each side's fastest form (the sparse pair
+        # launch per iteration; the dense kernel has no pair form); both in
+        # double arithmetic (the dense sum-product runs on the FP64 matrix
+        # cores), with the dense kernels' own FP64 fraction
+        grid.set_arithmetic("f64")
+        grid.set_sync_fusion(False)
+        extra["sparse_max_sync_single_launch_us"] = time_launches(grid, "max", cfg.iters, "sync", False, 2) * 1e3
+        grid.set_sync_fusion(True)
+        extra["sparse_sum_sync_f64_pair_per_iteration_us"] = (
+            extra.get("sparse_sum_sync_f64_pair_launch_us", ms_launch * 1e3) / 2)
+        grid.set_arithmetic(args.arith)
+        flops = 2.0 * cfg.n_directed_edges * cfg.M * cfg.M          # Eq. 2 / Eq. 9 per iteration
+        single = {"sum": extra.get("sparse_sum_sync_f64_single_launch_us", ms_single * 1e3),
+                  "max": extra["sparse_max_sync_single_launch_us"]}
+        best = {"sum": extra["sparse_sum_sync_f64_pair_per_iteration_us"],
+                "max": extra["sparse_max_sync_us_per_iteration"]}
         for mode in ("sum", "max"):
-            sp = extra.get(f"sparse_{mode}_sync_updates_per_s", value if mode == "sum" else None)
-            dn = extra.get(f"dense_{mode}_sync_updates_per_s")
-            if sp and dn:
-                extra[f"sparse_over_dense_{mode}"] = sp / dn
+            d_us = extra[f"dense_{mode}_sync_us_per_iteration"]
+            extra[f"dense_{mode}_sync_fp64_TFs"] = flops / (d_us * 1e-6) / 1e12
+            extra[f"dense_{mode}_sync_frac_fp64_peak"] = flops / (d_us * 1e-6) / 78.6e12
+            extra[f"sparse_over_dense_{mode}_single_vs_single"] = d_us / single[mode]
+            extra[f"sparse_over_dense_{mode}_best_vs_best"] = d_us / best[mode]
+            log(f"bench: sparse over dense ({mode}): {d_us / single[mode]:.2f}x single vs single, "
+                f"{d_us / best[mode]:.2f}x best vs best; dense at {flops / (d_us * 1e-6) / 1e12:.1f} TF/s "
+                f"({100 * flops / (d_us * 1e-6) / 78.6e12:.0f}% of the FP64 peak)")
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
-    if not args.no_legs:
-        extra.update(sweep_leg(grid, cfg))
-        extra.update(multiscale_leg(grid, cfg))
-        extra.update(general_leg(g, cfg))
-        extra.update(factor_leg())
-        extra.update(fbar_zero_leg())
-        extra.update(grad_leg())
-        extra.update(batch_leg())
+    for name, leg in (("sweep", lambda: sweep_leg(grid, cfg)), ("multiscale", lambda: multiscale_leg(grid, cfg)),
+                      ("general", lambda: general_leg(g, cfg)), ("factor", factor_leg), ("fbar0", fbar_zero_leg),
+                      ("grad", grad_leg), ("batch", batch_leg)):
+        if name in legs:
+            extra.update(leg())
 
     # copy-kernel ceiling on this GPU (torch device-to-device copy)
     big = torch.empty(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
@@ -627,11 +687,11 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "edge·label updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.arith,
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.H}x{cfg.W} grid, M={cfg.M}, T={cfg.T}, "
                                f"alpha={cfg.alpha}, {cfg.iters} synchronous sum-product iterations "
-                               f"(sparse O(mM) update) + beliefs + MAP",
+                               f"(sparse O(mM) update, {args.arith} arithmetic, float32 messages) + beliefs + MAP",
                    "H": cfg.H, "W": cfg.W, "M": cfg.M, "T": cfg.T, "iters": cfg.iters,
                    "mode": "sum", "schedule": "sync", "parallelism": "single GPU"},
         "roofline": roofline,

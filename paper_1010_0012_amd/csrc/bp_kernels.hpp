@@ -364,10 +364,11 @@ __global__ __launch_bounds__(kBlock) void sparse_update_kernel(UpdateArgs a) {
 // once), then p's four outgoing messages, and iteration t's messages never
 // reach HBM: a launch reads the unary and the inbox and writes the outbox
 // once for two iterations.  The neighbours' rows are read up to four times,
-// from L2: workgroups are remapped so that each XCD (its own L2) walks a
-// contiguous band of rows.  The arithmetic of both iterations is that of
-// sparse_update_kernel, so the results equal two of its launches bit for
-// bit.
+// from L2: the launches keep a pixel's neighbours on its own XCD (its own
+// L2) -- sparse_update2_kernel gives each XCD a contiguous band of rows, the
+// row-block launch whole column strips.  The arithmetic of both iterations
+// is that of sparse_update_kernel, so the results equal two of its launches
+// bit for bit.
 
 // h of the message a sender sends towards o (Eq. 5, the factor order of
 // make_h_d): horizontal targets ((g mU) mD) m_{opp(o)}, vertical ones
@@ -599,13 +600,19 @@ __global__ __launch_bounds__(kBlock) void sparse_update2_kernel(UpdateArgs a, in
 // one grid row: the row and column come from the workgroup index in scalar
 // registers (no per-lane division), and a wave whose pixels all lie two or
 // more pixels inside the grid runs pair_pixel_inner.  gx = workgroups per
-// row; the XCD band remap is that of sparse_update2_kernel.
+// row, padded to gxp, a multiple of the XCD count (the padding exits at
+// once): in launch order workgroup b runs on XCD b mod 8, so each XCD holds
+// the same column strips in every row, the rows above and below a pixel are
+// read through that XCD's own L2, and all XCDs sweep the grid top to bottom
+// together.  (Giving each XCD a contiguous band of rows instead, as
+// sparse_update2_kernel does, measured 6% slower for this launch.)
 template <int G, int TW, int MODE>
-__global__ __launch_bounds__(kBlock) void sparse_update2_rows_kernel(UpdateArgs a, int per, int gx) {
+__global__ __launch_bounds__(kBlock) void sparse_update2_rows_kernel(UpdateArgs a, int gxp, int gx) {
     constexpr int PPB = kBlock / G;
-    const int b = xcd_band_block(blockIdx.x, per);
-    const int r = b / gx;
-    const int j = (b - r * gx) * PPB + (int)(threadIdx.x / G);
+    const int r = (int)blockIdx.x / gxp;
+    const int cb = (int)blockIdx.x - r * gxp;
+    if (cb >= gx) return;  // padding: whole workgroup
+    const int j = cb * PPB + (int)(threadIdx.x / G);
     const int pos = threadIdx.x & (G - 1);
     const int c = a.colour < 0 ? j : 2 * j + ((a.colour + r) & 1);
     if (r >= a.H || c >= a.W) return;  // whole groups only

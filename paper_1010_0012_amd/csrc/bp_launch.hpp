@@ -51,6 +51,10 @@ hipError_t launch_batch_pair_sum(int arm, bool full, const BatchLaunch& L, unsig
                                  hipStream_t s);
 hipError_t launch_batch_pair_max(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
                                  hipStream_t s);
+// Dynamic LDS bytes for a launch whose kernel uses none, sized so that at
+// most n of its workgroups fit in one CU's LDS (an occupancy cap) on the
+// current device; 0 when the device cannot be queried.
+size_t lds_cap_bytes(int n);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

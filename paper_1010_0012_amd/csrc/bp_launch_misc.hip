@@ -1,4 +1,6 @@
 // Dense comparison kernel, readout and fill launchers.
+#include <atomic>
+
 #include "bp_kernels.hpp"
 #include "bp_launch.hpp"
 
@@ -95,6 +97,27 @@ hipError_t go_readout(const UpdateArgs& a, float* b, int* lab, hipStream_t s) {
 }
 
 }  // namespace
+
+size_t lds_cap_bytes(int n) {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> lds_per_cu[kMaxDevices];  // 0: not yet queried
+    int dev = 0;
+    if (n < 1 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    int lds = lds_per_cu[dev].load(std::memory_order_relaxed);
+    if (lds == 0) {
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            lds <= 0)
+            return 0;
+        lds_per_cu[dev].store(lds, std::memory_order_relaxed);
+    }
+    int per_block = 0;
+    if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    // n workgroups of floor(lds / n) (rounded down to 256 bytes) fit and n + 1
+    // do not, as long as lds / (n (n + 1)) exceeds the rounding
+    const size_t bytes = (size_t)(lds / n) / 256 * 256;
+    if ((size_t)lds / ((size_t)n * (n + 1)) <= 256 || bytes > (size_t)per_block) return 0;
+    return bytes;
+}
 
 size_t dense_lds_need(int M, int mode) {
     if (mode == kSum && M == 32) return dense_mfma_lds_bytes<8>();
