@@ -423,10 +423,13 @@ def factor_leg(reps=3, n_iters=10):
     return out
 
 
-def batch_leg(n_iters=30, reps=3):
+def batch_leg(arith="f64", n_iters=30, reps=3):
     """The 32-instance batch (H, W in [64, 512], M in {16, 32, 64, 128}, T in
-    [1, 8]): autotuned plan, n_iters sum-product iterations per graph replay;
-    and the same instances run one grid at a time for comparison."""
+    [1, 8]) in the given arithmetic: autotuned plan, n_iters sum-product
+    iterations per graph replay; each label class (the instances of one M)
+    as a batch of its own; and the same instances run one grid at a time.
+    Double by default: float32 arithmetic ends 1.3e-5 from the FP64 solve on
+    the smallest instance (78 x 115, M = 32), beyond the 1e-5 bar."""
     import torch
 
     from paper_1010_0012_amd.batch import Batch
@@ -434,57 +437,90 @@ def batch_leg(n_iters=30, reps=3):
     from synth_mrf import make_batch_configs, make_batch_instance
     insts = make_batch_configs()
     gs = [torch.from_numpy(make_batch_instance(i)[0]).cuda() for i in insts]
-    batch = Batch([(g, i.T, i.alpha) for g, i in zip(gs, insts)])
-    best_us = batch.autotune("sum", 2)
-    plan = batch.get_plan()
-    streams = batch.get_streams()
-    updates = sum(2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) * i.M for i in insts) * n_iters
-    alg_bytes = sum(4 * i.M * (2 * 2 * (i.H * (i.W - 1) + i.W * (i.H - 1)) + i.H * i.W)
-                    for i in insts) * n_iters
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    batch.reset()
-    batch.iterate("sum", n_iters)          # captures the graph
-    torch.cuda.synchronize()
-    ms = 1e30
-    for _ in range(reps):
+
+    def work(js):
+        updates = sum(2 * (insts[j].H * (insts[j].W - 1) + insts[j].W * (insts[j].H - 1)) * insts[j].M
+                      for j in js) * n_iters
+        # one synchronous iteration's bytes (each message read and written once,
+        # the unary read once); a two-iteration launch moves one iteration's bytes
+        iter_bytes = sum(4 * insts[j].M * (2 * 2 * (insts[j].H * (insts[j].W - 1) + insts[j].W * (insts[j].H - 1))
+                                           + insts[j].H * insts[j].W) for j in js) * n_iters
+        return updates, iter_bytes
+
+    def run_batch(js):
+        batch = Batch([(gs[j], insts[j].T, insts[j].alpha) for j in js])
+        batch.set_arithmetic(arith)
+        best_us = batch.autotune("sum", 2)
         batch.reset()
-        e0.record(s)
-        batch.iterate("sum", n_iters)
-        e1.record(s)
-        e1.synchronize()
-        ms = min(ms, e0.elapsed_time(e1))
+        batch.iterate("sum", n_iters)          # captures the graph
+        torch.cuda.synchronize()
+        ms = 1e30
+        for _ in range(reps):
+            batch.reset()
+            e0.record(s)
+            batch.iterate("sum", n_iters)
+            e1.record(s)
+            e1.synchronize()
+            ms = min(ms, e0.elapsed_time(e1))
+        return batch, ms, best_us
+
+    every = list(range(len(insts)))
+    batch, ms, best_us = run_batch(every)
+    plan = batch.get_plan()
+    streams = batch.get_streams()
+    updates, iter_bytes = work(every)
     acc = {}
-    j = min(range(len(insts)), key=lambda i: insts[i].H * insts[i].W * insts[i].M)
+    j = min(every, key=lambda i: insts[i].H * insts[i].W * insts[i].M)
     b_j, l_j = batch.beliefs()[j].cpu().numpy(), batch.map_labels()[j].cpu().numpy()
     acc[f"batch32_{j}_sum_sync"] = golden_accuracy(f"batch32_{j}_sum_sync", b_j, l_j)
-    j = max((i for i in range(len(insts)) if insts[i].M == 128), key=lambda i: insts[i].H * insts[i].W)
+    j = max((i for i in every if insts[i].M == 128), key=lambda i: insts[i].H * insts[i].W)
     b_j, l_j = batch.beliefs()[j].cpu().numpy(), batch.map_labels()[j].cpu().numpy()
     acc[f"batch32_{j}_sum_sync"] = golden_accuracy(f"batch32_{j}_sum_sync", b_j, l_j)
     log(f"bench: batch accuracy {acc}")
     batch.close()
-    # one grid at a time
+    # each label class as a batch of its own
+    classes = {}
+    for M in sorted({i.M for i in insts}):
+        js = [j for j in every if insts[j].M == M]
+        cb, cms, _ = run_batch(js)
+        cb.close()
+        cu, cbytes = work(js)
+        classes[f"M{M}"] = {"instances": len(js), "ms": cms, "updates_per_s": cu / (cms * 1e-3),
+                            "iteration_equiv_GBs": cbytes / (cms * 1e-3) / 1e9,
+                            "launch_GBs": cbytes / 2 / (cms * 1e-3) / 1e9}
+        log(f"bench: batch class M={M}: {len(js)} instances, {cms:.2f} ms, "
+            f"{cbytes / 2 / (cms * 1e-3) / 1e9:.0f} GB/s on the pair launches' own bytes")
+    # one grid at a time (the best of `reps` solves of each)
     t_single = 0.0
     for g, i in zip(gs, insts):
         grid = Grid(i.H, i.W)
         grid.set_potential(i.M, i.T, i.alpha)
+        grid.set_arithmetic(arith)
         grid.set_unary(g)
         grid.iterate("sum", 2)
-        e0.record(s)
-        grid.iterate("sum", n_iters)
-        e1.record(s)
-        e1.synchronize()
-        t_single += e0.elapsed_time(e1)
+        best = 1e30
+        for _ in range(reps):
+            grid.reset()
+            e0.record(s)
+            grid.iterate("sum", n_iters)
+            e1.record(s)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        t_single += best
         grid.close()
-    log(f"bench: batch32 x{n_iters}: {ms:.2f} ms ({updates / (ms * 1e-3):.4e} updates/s, "
-        f"{alg_bytes / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic), plan {plan}, {streams} streams; one grid at a time "
-        f"{t_single:.2f} ms")
+    log(f"bench: batch32 x{n_iters} ({arith}): {ms:.2f} ms ({updates / (ms * 1e-3):.4e} updates/s, "
+        f"{iter_bytes / 2 / (ms * 1e-3) / 1e9:.0f} GB/s on the pair launches' own bytes), plan {plan}, "
+        f"{streams} streams; one grid at a time {t_single:.2f} ms ({t_single / ms:.2f}x)")
     return {"batch_workload": f"32 grids, H,W in [64,512], M in {{16,32,64,128}}, T in [1,8], "
-                              f"{n_iters} sum-product iterations, one graph replay",
+                              f"{n_iters} sum-product iterations, one graph replay, {arith} arithmetic",
             "batch_ms": ms, "batch_updates_per_s": updates / (ms * 1e-3),
-            "batch_alg_GBs": alg_bytes / (ms * 1e-3) / 1e9,
+            "batch_alg_GBs": iter_bytes / (ms * 1e-3) / 1e9,
+            "batch_launch_GBs": iter_bytes / 2 / (ms * 1e-3) / 1e9,
             "batch_plan": {"passes": plan[0], "grid_blocks": plan[1], "streams": streams, "autotune_best_us": best_us},
-            "batch_one_grid_at_a_time_ms": t_single, "batch_accuracy": acc}
+            "batch_one_grid_at_a_time_ms": t_single, "batch_over_one_at_a_time": t_single / ms,
+            "batch_classes": classes, "batch_accuracy": acc}
 
 
 def main():

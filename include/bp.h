@@ -157,9 +157,9 @@ int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
  * synchronous or checkerboard schedule, T within the
  * register windows (T <= 16, 12 for M <= 16), M = 4 * ceil-pow2(M / 4) (16,
  * 32, 64, 128, 256) and 4*H*W*M bytes below 2^32.  Everything else (max-
- * product, sweeps, dense, general potentials, batches, multi-scale, the
- * gradient) computes in double whatever this says.  BP_EINVAL for another
- * value. */
+ * product, sweeps, dense, general potentials, multi-scale, the gradient)
+ * computes in double whatever this says; batches have their own setting
+ * (bp_batch_set_arithmetic).  BP_EINVAL for another value. */
 enum bp_arith { BP_ARITH_F64 = 0, BP_ARITH_F32 = 1 };
 int bp_set_arithmetic(bp_grid* grid, int32_t arith);
 
@@ -412,6 +412,17 @@ int bp_batch_iterate(bp_batch* batch, int32_t mode, int32_t n_iters);
 /* enable = 0: launch the kernels directly on every call instead of
  * replaying captured graphs (results are identical). */
 int bp_batch_set_graphs(bp_batch* batch, int32_t enable);
+
+/* Arithmetic of the batch's sum-product updates (Eq. 7), as
+ * bp_set_arithmetic for one grid: with BP_ARITH_F32, the instances that
+ * qualify for it there (fbar > 0, M = 4 * ceil-pow2(M / 4), 4*H*W*M bytes
+ * below 2^32; every batch window is a register window) compute in float32,
+ * each equal bit for bit to its single-grid solve with BP_ARITH_F32; the
+ * others, and max-product, compute in double.  An instance runs in float32
+ * only when every instance launched with it (same lanes per pixel and
+ * window width) qualifies.  Drops captured graphs; keeps the messages.
+ * BP_EINVAL for a null handle or another value. */
+int bp_batch_set_arithmetic(bp_batch* batch, int32_t arith);
 
 /* Work plan: passes[c] = passes per workgroup for instances of lane class c
  * (M <= 16, 32, 64, 128, 256; a pass covers 256 threads' worth of pixels at

@@ -99,6 +99,7 @@ _PROTOS = {
     "bp_batch_reset_messages": (_c_int, [_vp]),
     "bp_batch_iterate": (_c_int, [_vp, _c_i32, _c_i32]),
     "bp_batch_set_graphs": (_c_int, [_vp, _c_i32]),
+    "bp_batch_set_arithmetic": (_c_int, [_vp, _c_i32]),
     "bp_batch_set_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), _c_i32]),
     "bp_batch_get_plan": (_c_int, [_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
     "bp_batch_set_streams": (_c_int, [_vp, _c_i32]),
@@ -394,6 +395,10 @@ def bp_batch_iterate(handle, mode, n_iters):
 
 def bp_batch_set_graphs(handle, enable):
     _check(lib().bp_batch_set_graphs(handle, int(bool(enable))), "bp_batch_set_graphs")
+
+
+def bp_batch_set_arithmetic(handle, arith):
+    _check(lib().bp_batch_set_arithmetic(handle, arith), "bp_batch_set_arithmetic")
 
 
 BP_BATCH_CLASSES = 5

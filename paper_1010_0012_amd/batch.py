@@ -61,6 +61,11 @@ class Batch:
         self._sync_stream()
         L.bp_batch_iterate(self.handle, MODES[mode] if isinstance(mode, str) else int(mode), n_iters)
 
+    def set_arithmetic(self, arith):
+        """"f64" (default) or "f32": the arithmetic of the sum-product updates
+        of the instances that have a float32 kernel (bp_batch_set_arithmetic)."""
+        L.bp_batch_set_arithmetic(self.handle, {"f64": L.BP_ARITH_F64, "f32": L.BP_ARITH_F32}[arith])
+
     def set_plan(self, passes, grid_blocks):
         self._sync_stream()
         L.bp_batch_set_plan(self.handle, passes, grid_blocks)

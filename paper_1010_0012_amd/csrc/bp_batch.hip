@@ -38,6 +38,8 @@ struct bp_batch {
     std::vector<bpk::BatchLaunch> launches;
     std::vector<int> launch_arm;
     std::vector<char> launch_full;       // every instance of the launch has M = 4G
+    std::vector<char> launch_f32;        // sum-product of the launch in float32 arithmetic
+    bool arith_f32 = false;              // BP_ARITH_F32 requested
     bool use_pairs = true;               // two iterations per launch (same bits as single launches)
     // Launches touch disjoint instances, so each launch's iterations form an
     // independent chain: the chains run on kSide streams (forked from and
@@ -79,6 +81,26 @@ void drop_graphs(bp_batch* B) {
 
 bool full_rows(int M) { return M == bpk::lanes_for(M) * bpk::kLpl; }
 
+// The row-block layout of a full launch (BatchLaunch.rows): per instance
+// ceil(W / (kBlock/G)) workgroups per grid row, padded to a multiple of the
+// XCD count; only when every inbox plane is below 2^32 bytes and the
+// workgroup total fits an int.
+void set_rows_layout(bpk::BatchLaunch& L) {
+    L.rows = 0;
+    long long end = 0;
+    for (int k = 0; k < L.n_inst; ++k) {
+        const bpk::InstDesc& d = L.inst[k];
+        const int ppb = bpk::kBlock / bpk::lanes_for(d.M);
+        if ((uint64_t)d.N * d.M * sizeof(float) >= (uint64_t(1) << 32)) return;
+        L.gx[k] = (d.W + ppb - 1) / ppb;
+        L.gxp[k] = (L.gx[k] + bpk::kXcds - 1) / bpk::kXcds * bpk::kXcds;
+        end += (long long)L.gxp[k] * d.H;
+        if (end >= (1LL << 31)) return;
+        L.rows_end[k] = (int)end;
+    }
+    L.rows = 1;
+}
+
 // Launch plan: the instances of each code path (and whether M = 4G), largest
 // first (bytes moved, pixels * M), packed into launches of up to
 // kLaunchInst; each instance is cut into workgroups of passes * kBlock/G
@@ -88,6 +110,7 @@ void build_launches(bp_batch* B) {
     B->launches.clear();
     B->launch_arm.clear();
     B->launch_full.clear();
+    B->launch_f32.clear();
     std::vector<long long> work_of;
     auto work = [&](int j) { return (long long)B->desc[j].H * B->desc[j].W * B->desc[j].M; };
     for (int af = 0; af < 2 * bpk::kBatchArms; ++af) {
@@ -113,9 +136,15 @@ void build_launches(bp_batch* B) {
                 L.n_inst++;
                 w += work(j);
             }
+            if (full) set_rows_layout(L);
+            // float32 arithmetic where the single-grid update has it: full
+            // rows (the row-block layout) and fbar > 0 in every instance
+            bool f32 = B->arith_f32 && full && L.rows;
+            for (int k = 0; k < L.n_inst; ++k) f32 = f32 && L.inst[k].fbar > 0.0f;
             B->launches.push_back(L);
             B->launch_arm.push_back(a);
             B->launch_full.push_back(full);
+            B->launch_f32.push_back(f32);
             work_of.push_back(w);
         }
     }
@@ -194,12 +223,15 @@ hipError_t launch_iters(bp_batch* B, int mode, int n, int parity0, hipStream_t s
             hipStream_t ls = fork ? B->side[B->launch_stream[l]] : s;
             const int arm = B->launch_arm[l];
             const unsigned grid = launch_grid(B, L);
+            const bool f32 = mode == bpk::kSum && B->launch_f32[l];
             if (t < pairs)
-                e = mode == bpk::kSum ? bpk::launch_batch_pair_sum(arm, B->launch_full[l], L, grid, par, ls)
-                                      : bpk::launch_batch_pair_max(arm, B->launch_full[l], L, grid, par, ls);
+                e = f32                   ? bpk::launch_batch_pair_sumf(arm, B->launch_full[l], L, grid, par, ls)
+                    : mode == bpk::kSum ? bpk::launch_batch_pair_sum(arm, B->launch_full[l], L, grid, par, ls)
+                                        : bpk::launch_batch_pair_max(arm, B->launch_full[l], L, grid, par, ls);
             else
-                e = mode == bpk::kSum ? launch_arm<bpk::kSum>(arm, L, grid, par, ls)
-                                      : launch_arm<bpk::kMax>(arm, L, grid, par, ls);
+                e = f32                   ? launch_arm<bpk::kSumF32>(arm, L, grid, par, ls)
+                    : mode == bpk::kSum ? launch_arm<bpk::kSum>(arm, L, grid, par, ls)
+                                        : launch_arm<bpk::kMax>(arm, L, grid, par, ls);
             if (e != hipSuccess) return e;
         }
     }
@@ -314,6 +346,7 @@ int bp_batch_attach_workspace(bp_batch* B, void* dev_ptr, int64_t bytes) {
             const bool in = k <= d.T;
             const double f = std::exp(-(double)d.alpha * k);
             h.tab_f[k] = in ? (float)f : 0.0f;
+            h.tab_wf[k] = in ? (float)(f - (double)h.fbar) : 0.0f;
             h.tab_wd[k] = in ? f - h.fbar_d : 0.0;
         }
         boff += (long long)h.N * d.M;
@@ -385,6 +418,16 @@ int bp_batch_iterate(bp_batch* B, int32_t mode, int32_t n_iters) {
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
     B->parity ^= launches_for(B, n_iters) & 1;
+    return BP_OK;
+}
+
+int bp_batch_set_arithmetic(bp_batch* B, int32_t arith) {
+    if (!B) return fail(BP_EINVAL, "null batch handle");
+    if (arith != BP_ARITH_F64 && arith != BP_ARITH_F32) return fail(BP_EINVAL, "bad arithmetic %d", arith);
+    if ((arith == BP_ARITH_F32) == B->arith_f32) return BP_OK;
+    drop_graphs(B);
+    B->arith_f32 = arith == BP_ARITH_F32;
+    if (B->ws) build_launches(B);
     return BP_OK;
 }
 

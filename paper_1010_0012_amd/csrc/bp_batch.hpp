@@ -37,6 +37,7 @@ struct InstDesc {
     int arm;                 // code path: G = arm_g(arm), TW = arm_tw(arm)
     float fbar;              // float32 (max-product)
     float tab_f[kBatchTab];  // f(d), |d| <= T (max-product, float32)
+    float tab_wf[kBatchTab]; // f(d) - fbar, |d| <= T (sum-product in float32 arithmetic)
     double fbar_d;           // double (sum-product)
     double tab_wd[kBatchTab];  // f(d) - fbar, |d| <= T (sum-product, double)
 };
@@ -46,11 +47,22 @@ struct InstDesc {
 // workgroup's first message load).  Workgroup b serves the instance k whose
 // block range [blocks_end[k-1], blocks_end[k]) holds b, covering `passes`
 // passes of kBlock/G pixels from (b - blocks_end[k-1]) * passes * kBlock/G.
+//
+// Two-iteration launches whose instances all have M = 4G and inbox planes
+// below 2^32 bytes also carry the row-block layout of
+// batch_update2_rows_kernel: instance k gets gxp[k] * H workgroups, gx[k] of
+// kBlock/G pixels per grid row padded to gxp[k], a multiple of the XCD
+// count, so every instance starts on XCD 0 and each XCD holds the same column
+// strips in every row (as in the single-grid row-block launch).
 constexpr int kLaunchInst = 8;
 struct BatchLaunch {
     int n_inst;
     int passes;
     int blocks_end[kLaunchInst];  // inclusive prefix sums of workgroups per instance
+    int rows;                     // 1: the row-block layout below is valid
+    int rows_end[kLaunchInst];    // inclusive prefix sums of gxp[k] * H
+    int gx[kLaunchInst];
+    int gxp[kLaunchInst];
     InstDesc inst[kLaunchInst];
 };
 
@@ -76,14 +88,25 @@ __device__ __forceinline__ void batch_item(const InstDesc& d, int first, int pas
         if (!px.ok) continue;  // whole groups only
         PixelInputs pin;
         load_pixel_ptr(d.g, in, plane, M, px, x0, full, pin);
-        double h[4][kLpl];
-        make_h_d(pin, h);
+        if constexpr (MODE == kSumF32) {
+            float h[4][kLpl];
+            make_h(pin, h);
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            float u[kLpl];
-            if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], d.tab_wd, d.fbar_d, pos, M, x0, full, u);
-            else max_message_d<G, TW>(h[o], d.tab_f, d.fbar, pos, M, x0, full, u);
-            store_message(out, plane, M, W, px, o, x0, full, u);
+            for (int o = 0; o < 4; ++o) {
+                float u[kLpl];
+                sum_message_f<G, TW>(h[o], d.tab_wf, d.fbar, pos, M, x0, full, u);
+                store_message(out, plane, M, W, px, o, x0, full, u);
+            }
+        } else {
+            double h[4][kLpl];
+            make_h_d(pin, h);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                float u[kLpl];
+                if constexpr (MODE == kSum) sum_message_d<G, TW>(h[o], d.tab_wd, d.fbar_d, pos, M, x0, full, u);
+                else max_message_d<G, TW>(h[o], d.tab_f, d.fbar, pos, M, x0, full, u);
+                store_message(out, plane, M, W, px, o, x0, full, u);
+            }
         }
     }
 }
@@ -126,9 +149,31 @@ __global__ __launch_bounds__(kBlock) void batch_update2_kernel(const BatchLaunch
             const Pixel px = sync_pixel(first + pass * RPB + grp, d.H, d.W, d.N);
             if (!px.ok) continue;  // whole groups only
             pair_pixel<G, TW, MODE, FULL>(d.g, d.msg[parity], d.msg[parity ^ 1], nullptr, d.H, d.W, d.M, px, pos,
-                                          d.tab_wd, d.fbar_d, d.tab_f, d.fbar);
+                                          d.tab_wd, d.fbar_d, MODE == kSumF32 ? d.tab_wf : d.tab_f, d.fbar);
         }
     }
+}
+
+// The row-block form of batch_update2_kernel (L.rows set; one workgroup per
+// range, grid = L.rows_end[n_inst - 1]): the per-pixel code of the
+// single-grid row-block launch, so each instance's result equals its
+// single-grid pair launch bit for bit.
+template <int MODE, int G, int TW>
+__global__ __launch_bounds__(kBlock) void batch_update2_rows_kernel(const BatchLaunch L, int parity) {
+    constexpr int PPB = kBlock / G;
+    const int b = (int)blockIdx.x;
+    int k = 0;
+    while (k + 1 < L.n_inst && b >= L.rows_end[k]) ++k;  // uniform over the workgroup
+    const InstDesc& d = L.inst[k];
+    const int lb = b - (k ? L.rows_end[k - 1] : 0);
+    const int r = lb / L.gxp[k];
+    const int cb = lb - r * L.gxp[k];
+    if (cb >= L.gx[k]) return;  // padding: whole workgroup
+    const int c = cb * PPB + (int)(threadIdx.x / G);
+    if (c >= d.W) return;  // whole groups only
+    pair_rows_pixel<G, TW, MODE>(d.g, d.msg[parity], d.msg[parity ^ 1], nullptr, d.H, d.W, r, c,
+                                 (int)(threadIdx.x & (G - 1)), d.tab_wd, d.fbar_d,
+                                 MODE == kSumF32 ? d.tab_wf : d.tab_f, d.fbar);
 }
 
 // Beliefs (Eq. 3) and MAP labels of every instance into concatenated outputs.

@@ -595,6 +595,36 @@ __global__ __launch_bounds__(kBlock) void sparse_update2_kernel(UpdateArgs a, in
     pair_pixel<G, TW, MODE, FULL>(a.g, a.in, a.out, a.mid, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
 }
 
+// Both iterations for pixel (r, c) of an H x W grid with M = 4G whose inbox
+// plane is below 2^32 bytes, as the row-block launches run them: a wave
+// whose pixels all lie two or more pixels inside the grid takes
+// pair_pixel_inner, any other wave pair_pixel (the same bits).
+template <int G, int TW, int MODE>
+__device__ __forceinline__ void pair_rows_pixel(const float* g, const float* in, float* out, float* mid, int H, int W,
+                                                int r, int c, int pos, const double* dtab, double fbar_d,
+                                                const float* tab, float fbar) {
+    const int p = r * W + c;
+    const bool inner = r >= 2 && r + 2 < H && c >= 2 && c + 2 < W;
+    if (__builtin_amdgcn_ballot_w64(!inner) == 0) {
+        const uint32_t plane_b = (uint32_t)(H * W) * (16u * G);
+        const uint32_t row_b = (uint32_t)W * (16u * G);
+        const uint32_t voff = (uint32_t)p * (16u * G) + (uint32_t)pos * 16u;
+        pair_pixel_inner<G, TW, MODE>((gcptr)g, (gcptr)in, (gptr)out, (gptr)mid, plane_b, row_b, voff, pos, dtab,
+                                      fbar_d, tab, fbar);
+    } else {
+        Pixel px;
+        px.r = r;
+        px.c = c;
+        px.p = p;
+        px.ok = true;
+        px.has[kLeft] = c > 0;
+        px.has[kRight] = c + 1 < W;
+        px.has[kUp] = r > 0;
+        px.has[kDown] = r + 1 < H;
+        pair_pixel<G, TW, MODE, true>(g, in, out, mid, H, W, 4 * G, px, pos, dtab, fbar_d, tab, fbar);
+    }
+}
+
 // The same launch for M = 4G when an inbox plane is below 2^32 bytes, with
 // workgroups that each cover kBlock/G consecutive pixels (or colour slots) of
 // one grid row: the row and column come from the workgroup index in scalar
@@ -616,27 +646,7 @@ __global__ __launch_bounds__(kBlock) void sparse_update2_rows_kernel(UpdateArgs 
     const int pos = threadIdx.x & (G - 1);
     const int c = a.colour < 0 ? j : 2 * j + ((a.colour + r) & 1);
     if (r >= a.H || c >= a.W) return;  // whole groups only
-    const int p = r * a.W + c;
-    const bool inner = r >= 2 && r + 2 < a.H && c >= 2 && c + 2 < a.W;
-    if (__builtin_amdgcn_ballot_w64(!inner) == 0) {
-        const uint32_t plane_b = (uint32_t)a.N * (16u * G);
-        const uint32_t row_b = (uint32_t)a.W * (16u * G);
-        const uint32_t voff = (uint32_t)p * (16u * G) + (uint32_t)pos * 16u;
-        pair_pixel_inner<G, TW, MODE>((gcptr)a.g, (gcptr)a.in, (gptr)a.out, (gptr)a.mid, plane_b, row_b, voff, pos,
-                                      a.dtab, a.fbar_d, a.tab, a.fbar);
-    } else {
-        Pixel px;
-        px.r = r;
-        px.c = c;
-        px.p = p;
-        px.ok = true;
-        px.has[kLeft] = c > 0;
-        px.has[kRight] = c + 1 < a.W;
-        px.has[kUp] = r > 0;
-        px.has[kDown] = r + 1 < a.H;
-        pair_pixel<G, TW, MODE, true>(a.g, a.in, a.out, a.mid, a.H, a.W, a.M, px, pos, a.dtab, a.fbar_d, a.tab,
-                                      a.fbar);
-    }
+    pair_rows_pixel<G, TW, MODE>(a.g, a.in, a.out, a.mid, a.H, a.W, r, c, pos, a.dtab, a.fbar_d, a.tab, a.fbar);
 }
 
 // ------------------------------------- sparse update, runtime window ----

@@ -51,6 +51,9 @@ hipError_t launch_batch_pair_sum(int arm, bool full, const BatchLaunch& L, unsig
                                  hipStream_t s);
 hipError_t launch_batch_pair_max(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
                                  hipStream_t s);
+// Sum-product in float32 arithmetic (full launches only).
+hipError_t launch_batch_pair_sumf(int arm, bool full, const BatchLaunch& L, unsigned grid, int parity,
+                                  hipStream_t s);
 // Dynamic LDS bytes for a launch whose kernel uses none, sized so that at
 // most n of its workgroups fit in one CU's LDS (an occupancy cap) on the
 // current device; 0 when the device cannot be queried.

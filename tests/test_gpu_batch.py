@@ -163,3 +163,52 @@ def test_batch32_full():
                 run_oracle(data[j][0], it.M, it.T, it.alpha, None, "sum", "sync", n, gb.DENSE),
                 check_msgs=False)
     batch.close()
+
+
+# Instances for the float32 setting: every lane class with M = 4G (float32
+# where fbar > 0), one M that is not 4G and one fbar = 0 instance in a code
+# path of its own (both stay in double, as a single grid does), and a grid
+# wide and tall enough for interior waves in the row-block launch.
+F32_SPECS = [  # H, W, M, T, alpha, fbar
+    (9, 13, 16, 2, 1.0, None),
+    (8, 1, 16, 5, 0.7, 0.01),
+    (6, 11, 20, 3, 0.6, None),
+    (5, 8, 32, 8, 0.4, None),
+    (20, 70, 32, 2, 0.7, None),
+    (4, 6, 64, 4, 0.5, None),
+    (12, 40, 64, 4, 0.8, None),
+    (7, 9, 64, 3, 0.5, 0.0),
+    (3, 5, 128, 8, 0.2, None),
+]
+
+
+@pytest.mark.parametrize("n", [6, 5])
+def test_f32_batch_equals_single_grids(n):
+    """With float32 arithmetic every instance equals its single-grid solve
+    with float32 arithmetic bit for bit (instances without a float32 kernel
+    run in double on both sides), under the row-block launches and under a
+    persistent plan; the wide instance really ran in float32 (it differs
+    from the double batch)."""
+    seeds = [300 + i for i in range(len(F32_SPECS))]
+    batch, gs = make_batch(F32_SPECS, seeds)
+    batch.set_arithmetic("f32")
+    say(f"batch f32 sum x{n}: {len(F32_SPECS)} instances")
+    batch.iterate("sum", n)
+    bb, bl = results(batch)
+    for j, (H, W, M, T, a, f) in enumerate(F32_SPECS):
+        _, b1, l1 = run_gpu(gs[j].cpu().numpy(), M, T, a, f, "sum", "sync", n, want_messages=False, arith="f32")
+        np.testing.assert_array_equal(bb[j], b1, err_msg=f"instance {j}")
+        np.testing.assert_array_equal(bl[j], l1, err_msg=f"instance {j}")
+    batch.set_plan([2, 2, 2, 2, 2], 7)  # persistent: no row-block layout
+    batch.reset()
+    batch.iterate("sum", n)
+    got = results(batch)
+    for x, y in zip(got[0] + got[1], bb + bl):
+        np.testing.assert_array_equal(x, y)
+    batch.set_arithmetic("f64")
+    batch.reset()
+    batch.iterate("sum", n)
+    b64, _ = results(batch)
+    assert not np.array_equal(b64[4], bb[4])
+    np.testing.assert_allclose(b64[4], bb[4], rtol=0, atol=1e-5)
+    batch.close()
