@@ -243,8 +243,9 @@ int bp_fg_init(bp_fgraph** out, int32_t n_vars, int32_t M, int32_t n_factors, co
         }
     }
     // Factor messages grouped by (type, slot), factor order inside a group,
-    // each run padded with -1 to whole workgroups of the factor kernel.
-    const int rpb = bpk::kBlock / bpk::lanes_for(M);
+    // each run padded with -1 to a multiple of kFgLane items: whole
+    // workgroups of either factor kernel (kFgLane items, or kBlock/G).
+    const int rpb = bpk::kFgLane;
     for (int k = 0; k < n_types; ++k)
         for (int i = 0; i < F->arity[k]; ++i) {
             size_t n = 0;
@@ -446,6 +447,13 @@ hipError_t go_iteration(const FgArgs& a, int most_entries, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     if (a.n_items > 0) {
+        if constexpr (!kTops && G <= 8) {
+            // M <= 32 outside the split form: one message per lane
+            const dim3 grid((unsigned)(a.n_items / kFgLane));
+            if (a.M <= 16) hipLaunchKernelGGL((fg_factor_lane_kernel<16, MODE>), grid, dim3(kFgLane), 0, s, a);
+            else hipLaunchKernelGGL((fg_factor_lane_kernel<32, MODE>), grid, dim3(kFgLane), 0, s, a);
+            return hipGetLastError();
+        }
         const unsigned blocks = (unsigned)(a.n_items / RPB);
         if ((size_t)most_entries <= fg_stage_entries(G, kTops))
             hipLaunchKernelGGL((fg_factor_kernel<G, MODE, SPLIT, true>), dim3(blocks), dim3(kBlock),

@@ -48,7 +48,7 @@ struct FgArgs {
     float* m_fv;             // [n_factors * 3][M] factor -> variable
     float* n_vf;             // [n_factors * 3][M] variable -> factor
     const int* items;        // factor messages a * 3 + i grouped by (type, slot), each run padded with -1
-                             // to whole workgroups, so a workgroup's messages share one table
+                             // to a multiple of kFgLane items, so a workgroup's messages share one table
     int n_items;
     int n_vars, n_factors, M;
     int arity[kFgMaxTypes];
@@ -195,8 +195,10 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     double* top_v = lds_d + (size_t)RPB * 2 * CAP + (size_t)grp * 2 * kFgTop;  // [2][kFgTop]
     int* top_i = reinterpret_cast<int*>(lds_d + (size_t)RPB * 2 * CAP + (size_t)RPB * 2 * kFgTop) + grp * 2 * kFgTop;
     const bool split = kTops && a.eq10[k];
-    // the workgroup's table: every run of items starts a workgroup with a real item
+    // the workgroup's table: every run of items starts a workgroup with a real
+    // item, and a workgroup of padding only (runs are padded to 64 items) exits
     const int first = a.items[blockIdx.x * RPB];
+    if (first < 0) return;  // whole workgroup, before the barrier
     const int* row0 = a.tptr + ((size_t)a.fac_type[first / 3] * 3 + first % 3) * (a.M + 1);
     const int e_base = row0[0];
     double* st_w = lds_d + fg_lds_bytes(G, kTops) / sizeof(double);
@@ -259,6 +261,131 @@ __global__ __launch_bounds__(kBlock) void fg_factor_kernel(FgArgs a) {
     float m[kLpl];
     normalise_d<G>(u, a.M, x0, full, m);
     store_labels<false>(a.m_fv + (size_t)item * a.M, x0, a.M, full, m);
+}
+
+// factor -> variable with one message per lane, for M <= MM (16 or 32) and
+// the sum and plain max forms: a workgroup is one wave of kFgLane items of
+// one (type, slot) (runs are padded to whole workgroups), so the table entry
+// of every step is the same for all lanes: uniform (scalar) reads of its
+// labels and value, from the scalar cache or L2.  (Staging the table in LDS
+// for workgroups of four waves sharing it measured no faster, 273 against
+// 269 us per iteration at 256 x 256, M = 32; one packed 16-byte read per
+// entry was slower, 290 us.)  Each lane gathers from its own copy of the
+// other slots' messages, held in registers and indexed by the wave-uniform
+// label.  The arithmetic is fg_factor_kernel's in the same order: S_j (H_j)
+// as the group's tree over 4-label partials, the listed tuples of each label
+// in row order with left-to-right products, and the normaliser as the same
+// tree over the lanes of a G-lane group (G = lanes_for(M)), so the messages
+// are the same bits.
+constexpr int kFgLane = 64;  // items per workgroup of fg_factor_lane_kernel
+
+// The tree sum (or max) of a group's per-lane values t[0..G) that the
+// DPP butterflies of group_sum_d / group_max_d form (neighbours first).
+// N = MM/4 entries; G <= N (uniform), a power of two.  Statically indexed.
+template <int MODE, int N>
+__device__ __forceinline__ double lane_tree(double (&t)[N], int G) {
+#pragma unroll
+    for (int w = 1; w < N; w *= 2) {
+        if (w >= G) break;
+#pragma unroll
+        for (int p = 0; p + w < N; p += 2 * w) t[p] = MODE == kSum ? t[p] + t[p + w] : fmax(t[p], t[p + w]);
+    }
+    return t[0];
+}
+
+template <int MM, int MODE>
+__global__ __launch_bounds__(kFgLane) void fg_factor_lane_kernel(FgArgs a) {
+    const int lane = (int)threadIdx.x;
+    const int item = a.items[blockIdx.x * kFgLane + lane];  // a * 3 + i, or -1
+    // every run of items starts a workgroup with a real item
+    const int first = __builtin_amdgcn_readfirstlane(a.items[blockIdx.x * kFgLane]);
+    const int k = __builtin_amdgcn_readfirstlane(a.fac_type[first / 3]);
+    const int i = first - 3 * (first / 3);
+    const int M = a.M;
+    const int G = lanes_for(M);
+    const int n_oth = a.arity[k] - 1;
+    const int j0 = i == 0 ? 1 : 0;
+    const int j1 = i == 2 ? 1 : 2;
+    const bool live = item >= 0;
+    const int fa = live ? item / 3 : 0;
+    const bool vec = (M & 3) == 0;  // rows of whole float4s
+    const int* row = a.tptr + ((size_t)k * 3 + i) * (M + 1);
+    // this lane's copies of the other slots' messages; the gathers below
+    // index them with a wave-uniform label (relative register moves; two
+    // arrays, each small enough to stay in registers)
+    float n0[MM], n1[MM];
+    double agg[2] = {1.0, 1.0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const float* src = a.n_vf + ((size_t)fa * 3 + (q ? j1 : j0)) * M;
+        const bool use = live && q < n_oth;
+        double t[MM / kLpl];
+#pragma unroll
+        for (int c = 0; c < MM / kLpl; ++c) {
+            float v[kLpl] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (use && c * kLpl < M) {
+                if (vec) {
+                    const v4f x = *reinterpret_cast<const v4f*>(src + c * kLpl);
+                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                } else {
+#pragma unroll
+                    for (int l = 0; l < kLpl; ++l)
+                        if (c * kLpl + l < M) v[l] = src[c * kLpl + l];
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < kLpl; ++l) (q ? n1 : n0)[c * kLpl + l] = v[l];
+            t[c] = MODE == kSum ? ((double)v[0] + (double)v[1]) + ((double)v[2] + (double)v[3])
+                                : fmax(fmax((double)v[0], (double)v[1]), fmax((double)v[2], (double)v[3]));
+        }
+        if (q < n_oth) agg[q] = lane_tree<MODE, MM / kLpl>(t, G);
+    }
+    double base = (double)a.fbar[k] * agg[0];
+    if (n_oth == 2) base *= agg[1];
+    double u[MM];
+#pragma unroll
+    for (int x = 0; x < MM; ++x) {
+        double acc = 0.0;  // labels beyond M count 0 in the normaliser
+        if (x < M) {
+            acc = base;
+            const int e1 = row[x + 1];
+#pragma unroll 4
+            for (int e = row[x]; e < e1; ++e) {
+                const int2 o = a.ent_o[e];
+                double p = MODE == kSum ? a.ent_w[e] : (double)a.ent_f[e];
+                p *= (double)n0[o.x];
+                if (n_oth == 2) p *= (double)n1[o.y];
+                acc = MODE == kSum ? acc + p : fmax(acc, p);
+            }
+        }
+        u[x] = acc;
+    }
+    // normalise_d: each lane's 4 labels summed in order from 0, then the tree
+    double t[MM / kLpl];
+#pragma unroll
+    for (int c = 0; c < MM / kLpl; ++c) {
+        double z = 0.0;
+#pragma unroll
+        for (int l = 0; l < kLpl; ++l) z += u[c * kLpl + l];
+        t[c] = z;
+    }
+    const double inv = recip_d(lane_tree<kSum, MM / kLpl>(t, G));
+    if (!live) return;
+    float* dst = a.m_fv + (size_t)item * M;
+#pragma unroll
+    for (int c = 0; c < MM / kLpl; ++c) {
+        if (c * kLpl >= M) break;
+        float m[kLpl];
+#pragma unroll
+        for (int l = 0; l < kLpl; ++l) m[l] = (float)(u[c * kLpl + l] * inv);
+        if (vec) {
+            *reinterpret_cast<v4f*>(dst + c * kLpl) = v4f{m[0], m[1], m[2], m[3]};
+        } else {
+#pragma unroll
+            for (int l = 0; l < kLpl; ++l)
+                if (c * kLpl + l < M) dst[c * kLpl + l] = m[l];
+        }
+    }
 }
 
 // Beliefs (g times every incoming factor message, normalised in double) and
