@@ -822,10 +822,11 @@ __global__ __launch_bounds__(dense_block(G)) void dense_update_kernel(UpdateArgs
 // are H F, H the wave's h rows [message][x] and F the M x M table.  The
 // products run on v_mfma_f64_16x16x4 (FP64 operands, FP64 accumulation;
 // no algebraic shortcut, every F[x][y] h(x) product is formed), 16 messages
-// by 16 labels by 4 sender labels per instruction: F stays in LDS and each
-// lane reads one double of H and one of F per instruction, a quarter of the
-// operand traffic of the one-FMA-per-lane form above.  h, the
-// normalisation and the store are those of the other kernels.
+// by 16 labels by 4 sender labels per instruction: each lane holds its F
+// operands in registers and reads one double of H from LDS per step of four
+// instructions.  h, the normalisation and the store are those of the other
+// kernels.  The 16 steps are unrolled so that the accumulators stay in the
+// matrix registers for the whole product.
 // Operand layout of the instruction (measured on gfx950): A[i][k] in lane
 // i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i mod 4),
 // element i / 4.
@@ -834,7 +835,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <int G>
 constexpr size_t dense_mfma_lds_bytes() {
     constexpr int M = 4 * G;
-    return ((size_t)M * M + kMaxTab + (size_t)(kBlock / 64) * (4 * (64 / G)) * (M + 1)) * sizeof(double);
+    return ((size_t)kMaxTab + (size_t)(kBlock / 64) * (4 * (64 / G)) * (M + 1)) * sizeof(double);
 }
 
 template <int G>
@@ -847,22 +848,28 @@ __global__ __launch_bounds__(kBlock) void dense_mfma_kernel(UpdateArgs a) {
     constexpr int RPB = kBlock / G;    // pixels per workgroup tile
     static_assert(MPW % 16 == 0, "whole 16-message batches");
     extern __shared__ double lds_d[];
-    double* F = lds_d;                                        // [M][M]: F[x][y]
-    double* fd = F + M * M;                                   // f(d) = exp(-alpha d), d <= T
+    double* fd = lds_d;                                       // f(d) = exp(-alpha d), d <= T
     double* rows = fd + kMaxTab + (threadIdx.x / 64) * MPW * LD;  // this wave's [MPW][LD]
     for (int d = threadIdx.x; d < kMaxTab; d += kBlock) fd[d] = d <= a.T ? exp(-a.alpha_d * d) : 0.0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < M * M; i += kBlock) {
-        const int x = i / M, y = i - x * M;
-        const int d = x > y ? x - y : y - x;
-        F[i] = d <= a.T ? fd[d] : a.fbar_d;
-    }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int pos = threadIdx.x & (G - 1);
     const int gw = lane / G;      // pixel group within the wave
     const int x0 = pos * kLpl;
     const int li = lane & 15, lk = lane >> 4;
+    // This lane's B operands for every product: F[4t + lk][16c + li], F[x][y]
+    // = f(|x - y|) within the window and fbar outside, the same for every
+    // tile, so they are formed once and kept in registers (64 doubles at
+    // M = 64; read from an LDS copy of F in each product they cost about 2%).
+    double bop[KS][CT];
+#pragma unroll
+    for (int t = 0; t < KS; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int x = 4 * t + lk, y = 16 * c + li;
+            const int d = x > y ? x - y : y - x;
+            bop[t][c] = d <= a.T ? fd[d] : a.fbar_d;
+        }
     const int n_tiles = (a.n_slots + RPB - 1) / RPB;
     const size_t plane = (size_t)a.N * M;
     // the next tile's inputs are loaded before this tile's products run
@@ -887,13 +894,15 @@ __global__ __launch_bounds__(kBlock) void dense_mfma_kernel(UpdateArgs a) {
 #pragma unroll
             for (int c = 0; c < CT; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
             const double* arow = rows + (nb * 16 + li) * LD + lk;
-#pragma unroll 4
+            // fully unrolled: the accumulators stay in the matrix registers (a
+            // loop back-edge moved them to VGPRs and back, each move waiting for
+            // the last product: 270 -> 254 us per iteration at 480x640x64)
+#pragma unroll
             for (int t = 0; t < KS; ++t) {
                 const double av = arow[4 * t];
-                const double* brow = F + (4 * t + lk) * M + li;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, brow[16 * c], acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bop[t][c], acc[c], 0, 0, 0);
             }
             wave_sync();  // every read of this batch's h rows is done
 #pragma unroll
