@@ -211,36 +211,50 @@ __device__ __forceinline__ void general_lds_rows(double* lds_d, int groups, int 
     top_i = reinterpret_cast<int*>(lds_d + groups * CAP + groups * kTopMax) + grp * kTopMax;
 }
 
-template <int G, int MODE, bool EQ10, bool STAGE>
+// One tile of kBlock/G pixels per workgroup, or (PERSIST) a grid of
+// resident workgroups that each stage the tables once and stride over the
+// tiles: staging per tile costs one table copy per 16 pixels at M = 64
+// (for four types, about 440 MB of L2-to-LDS traffic per iteration beside
+// the 707 MB the update itself moves), while the loop costs about ten
+// registers (a wave per SIMD); the host takes PERSIST for large tables.
+template <int G, int MODE, bool EQ10, bool STAGE, bool PERSIST>
 __global__ __launch_bounds__(kBlock) void general_update_kernel(GenArgs a, int stage_bytes) {
     extern __shared__ double lds_d[];
     const GenView<STAGE> v = gen_view<STAGE, kBlock, G>(a, reinterpret_cast<char*>(lds_d));
     if constexpr (STAGE) __syncthreads();
+    constexpr int RPB = kBlock / G;
     const int pos = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int slot = (blockIdx.x * kBlock + threadIdx.x) / G;
-    const Pixel px = map_slot(slot, a.u);
     const int M = a.u.M;
     const int x0 = pos * kLpl;
     const bool full = M == G * kLpl;
     double* hs;
     double* top_v;
     int* top_i;
-    general_lds_rows<G>(lds_d + stage_bytes / sizeof(double), kBlock / G, grp, hs, top_v, top_i);
-    PixelInputs in;
-    if (px.ok) load_pixel(a.u, px, x0, full, in); else dummy_pixel(in);
-    double h[4][kLpl];
-    make_h_d(in, h);
+    general_lds_rows<G>(lds_d + stage_bytes / sizeof(double), RPB, grp, hs, top_v, top_i);
     const size_t plane = (size_t)a.u.N * M;
-    // unrolled: indexed by a loop counter, h[o] and px.has[o] would live in
-    // scratch memory
+    auto run_tile = [&](int tile) {
+        const Pixel px = map_slot(tile * RPB + grp, a.u);
+        PixelInputs in;
+        if (px.ok) load_pixel(a.u, px, x0, full, in); else dummy_pixel(in);
+        double h[4][kLpl];
+        make_h_d(in, h);
+        // unrolled: indexed by a loop counter, h[o] and px.has[o] would live
+        // in scratch memory
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const bool live = px.ok && px.has[o];
-        const int k = live ? edge_type(a, px, o) : 0;
-        float m[kLpl];
-        general_message<G, MODE, EQ10, STAGE>(a, v, k, o, h[o], hs, top_v, top_i, pos, m);
-        store_message(a.u.out, plane, M, a.u.W, px, o, x0, full, m);
+        for (int o = 0; o < 4; ++o) {
+            const bool live = px.ok && px.has[o];
+            const int k = live ? edge_type(a, px, o) : 0;
+            float m[kLpl];
+            general_message<G, MODE, EQ10, STAGE>(a, v, k, o, h[o], hs, top_v, top_i, pos, m);
+            store_message(a.u.out, plane, M, a.u.W, px, o, x0, full, m);
+        }
+    };
+    if constexpr (PERSIST) {
+        const int n_tiles = (a.u.n_slots + RPB - 1) / RPB;
+        for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
+    } else {
+        run_tile((int)blockIdx.x);
     }
 }
 

@@ -58,6 +58,9 @@ hipError_t launch_batch_pair_sumf(int arm, bool full, const BatchLaunch& L, unsi
 // most n of its workgroups fit in one CU's LDS (an occupancy cap) on the
 // current device; 0 when the device cannot be queried.
 size_t lds_cap_bytes(int n);
+// Compute units of the current device (queried once per device); 0 when
+// the device cannot be queried.
+int cu_count();
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

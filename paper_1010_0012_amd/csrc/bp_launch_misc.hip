@@ -119,6 +119,19 @@ size_t lds_cap_bytes(int n) {
     return bytes;
 }
 
+int cu_count() {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<int> cus[kMaxDevices];  // 0: not yet queried
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 0;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 size_t dense_lds_need(int M, int mode) {
     if (mode == kSum && M == 32) return dense_mfma_lds_bytes<8>();
     if (mode == kSum && M == 64) return dense_mfma_lds_bytes<16>();
