@@ -54,12 +54,13 @@ KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_pair_rows_f32_stereo480x640.json")
 
 
-def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0):
+def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, row_blocks=True):
     """Template instance of the sparse update that runs (M, T): lanes per pixel
     G is the smallest power of two >= ceil(M/4) in [4, 64]; the window width is
     the smallest compiled half-width >= T; pair: the two-iteration launch,
     whose row-block form runs when M = 4G and the messages of one direction
-    fit 32-bit byte offsets (mode 2: sum-product in float32 arithmetic)."""
+    fit 32-bit byte offsets, unless the launch mapping is one group per
+    pixel slot (mode 2: sum-product in float32 arithmetic, row blocks only)."""
     G = 4
     while G * 4 < M and G < 64:
         G *= 2
@@ -67,7 +68,7 @@ def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0):
     tw = next((t for t in tws if t >= T), None)
     if tw is None:
         return f"sparse_update_wide_kernel<{G}, {mode}>"
-    if pair and M == 4 * G and n_pixels * M * 4 < 2 ** 32:
+    if pair and row_blocks and M == 4 * G and n_pixels * M * 4 < 2 ** 32:
         return f"sparse_update2_rows_kernel<{G}, {tw}, {mode}>"
     if pair:
         return f"sparse_update2_kernel<{G}, {tw}, {mode}, {'true' if M == 4 * G else 'false'}>"
@@ -140,6 +141,30 @@ def time_launches(grid, mode, n, schedule, dense, reps, iters_per_launch=1):
         e1.synchronize()
         total += e0.elapsed_time(e1)
     return total * iters_per_launch / (reps * n)  # ms per launch
+
+
+def run_meta(g32):
+    """What the record was measured on: the input digest, the host CPU and
+    its cores, the ROCm, HIP and torch versions."""
+    import hashlib
+    import platform
+
+    import torch
+    cpu = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    rocm = None
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            rocm = fh.read().strip()
+    except OSError:
+        pass
+    return {"input_sha256": hashlib.sha256(g32.tobytes()).hexdigest(), "host_cpu": cpu,
+            "host_cores": os.cpu_count(), "rocm": rocm, "hip": torch.version.hip, "torch": torch.__version__,
+            "device": torch.cuda.get_device_name(0)}
 
 
 def cpu_baseline(cfg, g32, n_iters=5):
@@ -555,6 +580,11 @@ def main():
     grid.set_potential(cfg.M, cfg.T, cfg.alpha)
     grid.set_arithmetic(args.arith)
     grid.set_unary(g)
+    # the two-iteration launch's mapping, timed on this grid (bp_autotune)
+    tune_us = grid.autotune("sum", "sync", 4)
+    tuning = grid.get_launch_tuning()
+    launch_tuning = {args.arith: {"layout": tuning[0], "cap": tuning[1], "autotune_us_per_iteration": tune_us}}
+    log(f"bench: autotuned launch mapping {tuning} ({tune_us:.1f} us per iteration in the trial)")
     beliefs = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device=dev)
     labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device=dev)
     updates_per_iter = cfg.n_directed_edges * cfg.M
@@ -592,7 +622,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                 "kernel": sparse_kernel_name(cfg.M, cfg.T, 2 if args.arith == "f32" else 0, pair=True,
-                                             n_pixels=cfg.n_pixels),
+                                             n_pixels=cfg.n_pixels,
+                                             row_blocks=args.arith == "f32" or tuning[0] != "slots"),
+                "launch_mapping": {"layout": tuning[0], "cap": tuning[1]},
                 "arithmetic": args.arith,
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3,
                 "iterations_per_launch": 2,
@@ -604,7 +636,7 @@ def main():
     log(f"bench: sparse sum pair launch {ms_launch * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
 
-    extra = {"sparse_sum_sync_pair_launch_us": ms_launch * 1e3, "accuracy": accuracy}
+    extra = {"sparse_sum_sync_pair_launch_us": ms_launch * 1e3, "accuracy": accuracy, "run": run_meta(g32)}
     # one iteration per launch, for comparison
     grid.set_sync_fusion(False)
     ms_single = time_launches(grid, "sum", cfg.iters, "sync", False, reps)
@@ -623,6 +655,10 @@ def main():
     # the other arithmetic beside it (double: every message its exact value rounded once)
     other = "f64" if args.arith == "f32" else "f32"
     grid.set_arithmetic(other)
+    o_us = grid.autotune("sum", "sync", 4)
+    o_tuning = grid.get_launch_tuning()
+    launch_tuning[other] = {"layout": o_tuning[0], "cap": o_tuning[1], "autotune_us_per_iteration": o_us}
+    extra["launch_tuning"] = launch_tuning
     ms_o = time_launches(grid, "sum", cfg.iters, "sync", False, reps, iters_per_launch=2)
     grid.readout(beliefs, labels)
     extra[f"sparse_sum_sync_{other}_pair_launch_us"] = ms_o * 1e3
@@ -634,6 +670,7 @@ def main():
                                                                       reps) * 1e3
     grid.set_sync_fusion(True)
     grid.set_arithmetic(args.arith)
+    grid.set_launch_tuning(*tuning)
     log(f"bench: {other} arithmetic: pair launch {ms_o * 1e3:.1f} us, single launch "
         f"{extra[f'sparse_sum_sync_{other}_single_launch_us']:.1f} us")
     legs = set() if args.no_legs else {x for x in args.legs.split(",") if x}

@@ -29,6 +29,12 @@
  *   Argument and call-order errors are detected synchronously, before any
  *   work is enqueued.  Launch failures are reported as BP_EHIP.
  * - Threads: a handle must not be used by two threads at once.
+ * - Tracing: with the environment variable BP_ROCTX=1 (read once), the
+ *   calls that enqueue updates or readouts (bp_iterate, bp_iterate_dense,
+ *   bp_readout and the other readouts, bp_autotune, bp_iterate_multiscale,
+ *   bp_forward_ckpt, bp_backward, bp_batch_iterate, bp_fg_iterate) each
+ *   open a roctx range named after the call (rocprofv3 --marker-trace);
+ *   roctx is looked up at run time, and without it nothing is traced.
  * - Layouts (row-major, float32, labels contiguous):
  *     unary g        [H][W][M]      g >= 0, finite, every pixel's row nonzero
  *     beliefs        [H][W][M]      each row sums to 1
@@ -162,6 +168,51 @@ int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
  * (bp_batch_set_arithmetic).  BP_EINVAL for another value. */
 enum bp_arith { BP_ARITH_F64 = 0, BP_ARITH_F32 = 1 };
 int bp_set_arithmetic(bp_grid* grid, int32_t arith);
+
+/* Launch mapping of the two-iteration launches (synchronous iterations and
+ * checkerboard pass pairs of the window potential, Eq. 7 / Eq. 11; see
+ * bp_set_sync_fusion).  layout: BP_PAIR_STRIPS (the default) runs one
+ * workgroup per block of consecutive pixels of a grid row, the blocks of a
+ * row padded to a multiple of the 8 XCDs so that each XCD holds the same
+ * column strips in every row; BP_PAIR_BANDS the same blocks remapped so that
+ * each XCD holds a contiguous band of rows; BP_PAIR_SLOTS one pixel group
+ * per slot in row-major order (the only form when M is not 4 * ceil-pow2(M /
+ * 4) or a message plane reaches 2^32 bytes, where the first two fall back to
+ * it; float32 arithmetic has the row blocks only, where BP_PAIR_SLOTS runs
+ * BP_PAIR_STRIPS).  cap: the most workgroups per compute unit the launch's
+ * LDS request allows (0 none, 1..64, -1 the default: 4 with float32
+ * arithmetic, none with double).  Every setting computes the same messages
+ * bit for bit; only the speed differs.  BP_EINVAL for a null handle, a
+ * layout outside the enum or a cap outside -1..64.  Kept per grid; used by
+ * every launch of the grid, including bp_forward_ckpt and multi-scale. */
+/* Convergence and failure check of the message state (Sec. 3: the messages
+ * of one iteration computed from those of the previous).  *max_change
+ * (device float, may be null): the largest |m - m'| over the inbox entries
+ * finite in both, m the current messages and m' the grid's other message
+ * buffer, which after a synchronous launch holds the state that launch
+ * read (one iteration back after a one-iteration launch, two after a
+ * two-iteration launch; after bp_reset_messages, bp_set_messages or
+ * in-place checkerboard passes it holds an older state).  *non_finite
+ * (device int32, may be null): the number of entries of m that are NaN or
+ * infinite.  Both are written on the grid's stream (no host sync; no
+ * memset, so a graph may capture the call).  BP_EINVAL for a null handle or
+ * no output, BP_ESTATE without a potential or a workspace. */
+int bp_message_stats(bp_grid* grid, float* max_change, int32_t* non_finite);
+
+enum bp_pair_layout { BP_PAIR_STRIPS = 0, BP_PAIR_BANDS = 1, BP_PAIR_SLOTS = 2 };
+int bp_set_launch_tuning(bp_grid* grid, int32_t layout, int32_t cap);
+int bp_get_launch_tuning(const bp_grid* grid, int32_t* layout, int32_t* cap);
+
+/* Time every (layout, cap) pair above, caps 0, 4 and 3, on this grid's own
+ * state and keep the fastest for `mode` and `schedule` (BP_SCHED_SYNC or
+ * BP_SCHED_CHECKERBOARD): trial_iters iterations (even, >= 2) per candidate
+ * after two warm-up iterations, timed with events on the grid's stream
+ * (synchronises with it).  Needs the potential, the unary and the workspace;
+ * the messages are reset to uniform afterwards (the trials iterate them).
+ * *best_us (if not null): microseconds per iteration of the winner.
+ * BP_EINVAL for a bad mode, schedule or trial_iters; BP_ESTATE when the grid
+ * is not ready; BP_EHIP on a device error (the previous setting is kept). */
+int bp_autotune(bp_grid* grid, int32_t mode, int32_t schedule, int32_t trial_iters, float* best_us);
 
 /* Synchronous iterations and checkerboard passes of the window potential
  * run two per launch by default (where a register window is compiled: T <=

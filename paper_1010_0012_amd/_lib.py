@@ -22,6 +22,7 @@ BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD, BP_SCHED_SWEEP = 0, 1, 2
 BP_MAX_LABELS = 256
 BP_FBAR_TIED = -1.0
 BP_ARITH_F64, BP_ARITH_F32 = 0, 1
+BP_PAIR_STRIPS, BP_PAIR_BANDS, BP_PAIR_SLOTS = 0, 1, 2
 
 _c_int, _c_i32, _c_i64, _c_f, _vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
 
@@ -79,6 +80,10 @@ _PROTOS = {
     "bp_reset_messages": (_c_int, [_vp]),
     "bp_set_sync_fusion": (_c_int, [_vp, _c_i32]),
     "bp_set_arithmetic": (_c_int, [_vp, _c_i32]),
+    "bp_set_launch_tuning": (_c_int, [_vp, _c_i32, _c_i32]),
+    "bp_message_stats": (_c_int, [_vp, _vp, _vp]),
+    "bp_get_launch_tuning": (_c_int, [_vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "bp_autotune": (_c_int, [_vp, _c_i32, _c_i32, _c_i32, ctypes.POINTER(_c_f)]),
     "bp_iterate": (_c_int, [_vp, _c_i32, _c_i32, _c_i32]),
     "bp_solve_noalloc": (_c_int, [_vp, _c_i32, _c_i32, _c_i32, _c_i32, _c_f, _c_f, _c_i32, _c_i32, _c_i32, _vp, _vp,
                                   _vp]),
@@ -296,6 +301,28 @@ def bp_set_sync_fusion(handle, enable):
 
 def bp_set_arithmetic(handle, arith):
     _check(lib().bp_set_arithmetic(handle, arith), "bp_set_arithmetic")
+
+
+def bp_message_stats(handle, max_change, non_finite):
+    """max_change / non_finite: device pointers (or None)."""
+    _check(lib().bp_message_stats(handle, _vp(max_change) if max_change else None,
+                                  _vp(non_finite) if non_finite else None), "bp_message_stats")
+
+
+def bp_set_launch_tuning(handle, layout, cap):
+    _check(lib().bp_set_launch_tuning(handle, layout, cap), "bp_set_launch_tuning")
+
+
+def bp_get_launch_tuning(handle):
+    layout, cap = _c_i32(), _c_i32()
+    _check(lib().bp_get_launch_tuning(handle, ctypes.byref(layout), ctypes.byref(cap)), "bp_get_launch_tuning")
+    return layout.value, cap.value
+
+
+def bp_autotune(handle, mode, schedule, trial_iters):
+    best = _c_f()
+    _check(lib().bp_autotune(handle, mode, schedule, trial_iters, ctypes.byref(best)), "bp_autotune")
+    return best.value
 
 
 def bp_iterate(handle, mode, n_iters, schedule):

@@ -1,5 +1,6 @@
 // C ABI of the grid BP library: handle state, argument and call-order checks,
 // potential tables, workspace carving and kernel dispatch.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -74,6 +75,8 @@ UpdateArgs base_args(const bp_grid* G, const float* in, float* out, int colour) 
     a.fbar_d = G->fbar_d;
     a.alpha_d = (double)G->alpha;
     memcpy(a.dtab, G->tab_wd, sizeof a.dtab);
+    a.pair_layout = G->pair_layout;
+    a.pair_cap = G->pair_cap;
     return a;
 }
 
@@ -197,6 +200,40 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
 
 size_t bp_align_up(size_t v, size_t a) { return bpi::align_up(v, a); }
 
+namespace bpi {
+namespace {
+struct Roctx {
+    int (*push)(const char*) = nullptr;
+    int (*pop)() = nullptr;
+};
+const Roctx& roctx() {
+    static const Roctx r = [] {
+        Roctx x;
+        const char* e = std::getenv("BP_ROCTX");
+        if (!e || std::strcmp(e, "1") != 0) return x;
+        // the rocprofiler-sdk roctx (what rocprofv3 records), then the older one
+        void* h = nullptr;
+        for (const char* lib : {"librocprofiler-sdk-roctx.so.1", "/opt/rocm/lib/librocprofiler-sdk-roctx.so.1",
+                                "libroctx64.so", "/opt/rocm/lib/libroctx64.so"})
+            if (!h) h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+        if (!h) return x;
+        x.push = reinterpret_cast<int (*)(const char*)>(dlsym(h, "roctxRangePushA"));
+        x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+        if (!x.push || !x.pop) x = Roctx{};
+        return x;
+    }();
+    return r;
+}
+}  // namespace
+
+TraceRange::TraceRange(const char* name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+}
+TraceRange::~TraceRange() {
+    if (on) roctx().pop();
+}
+}  // namespace bpi
+
 using namespace bpi;
 
 extern "C" {
@@ -205,6 +242,89 @@ int bp_set_sync_fusion(bp_grid* G, int32_t enable) {
     if (!G) return fail(BP_EINVAL, "null handle");
     G->fuse_sync = enable != 0;
     return BP_OK;
+}
+
+int bp_message_stats(bp_grid* G, float* max_change, int32_t* non_finite) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (!max_change && !non_finite) return fail(BP_EINVAL, "no output");
+    if (!G->pot_set || !G->ws) return fail(BP_ESTATE, "no potential or no workspace");
+    int st = with_device(G);
+    if (st) return st;
+    hipError_t e = bpk::launch_message_stats(G->msg[G->cur], G->msg[G->cur ^ 1], (size_t)4 * G->N * G->M,
+                                             max_change, non_finite, G->stream);
+    return e == hipSuccess ? BP_OK : hip_fail(e, "message stats launch");
+}
+
+static_assert(BP_PAIR_STRIPS == bpk::kPairStrips && BP_PAIR_BANDS == bpk::kPairBands &&
+                  BP_PAIR_SLOTS == bpk::kPairSlots,
+              "the header's layouts are the kernels'");
+
+int bp_set_launch_tuning(bp_grid* G, int32_t layout, int32_t cap) {
+    if (!G) return fail(BP_EINVAL, "null handle");
+    if (layout < BP_PAIR_STRIPS || layout > BP_PAIR_SLOTS) return fail(BP_EINVAL, "bad layout %d", layout);
+    if (cap < -1 || cap > 64) return fail(BP_EINVAL, "bad workgroups-per-CU cap %d", cap);
+    G->pair_layout = layout;
+    G->pair_cap = cap;
+    return BP_OK;
+}
+
+int bp_get_launch_tuning(const bp_grid* G, int32_t* layout, int32_t* cap) {
+    if (!G || !layout || !cap) return fail(BP_EINVAL, "null argument");
+    *layout = G->pair_layout;
+    *cap = G->pair_cap;
+    return BP_OK;
+}
+
+int bp_autotune(bp_grid* G, int32_t mode, int32_t schedule, int32_t trial_iters, float* best_us) {
+    TraceRange tr("bp_autotune");
+    int st = check_ready(G);
+    if (st) return st;
+    if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);
+    if (schedule != BP_SCHED_SYNC && schedule != BP_SCHED_CHECKERBOARD)
+        return fail(BP_EINVAL, "autotune covers the synchronous and checkerboard schedules");
+    if (trial_iters < 2 || trial_iters % 2) return fail(BP_EINVAL, "trial_iters must be even and >= 2");
+    if ((st = with_device(G))) return st;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const int layout0 = G->pair_layout, cap0 = G->pair_cap;
+    float best = 1e30f;
+    int best_layout = layout0, best_cap = cap0;
+    for (int layout : {BP_PAIR_STRIPS, BP_PAIR_BANDS, BP_PAIR_SLOTS}) {
+        for (int cap : {0, 4, 3}) {
+            G->pair_layout = layout;
+            G->pair_cap = cap;
+            if ((st = iterate(G, mode, 2, schedule, false))) break;  // warm
+            e = hipEventRecord(e0, G->stream);
+            if (e == hipSuccess) st = iterate(G, mode, trial_iters, schedule, false);
+            if (st) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, G->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "autotune trial");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_layout = layout;
+                best_cap = cap;
+            }
+        }
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    G->pair_layout = st ? layout0 : best_layout;
+    G->pair_cap = st ? cap0 : best_cap;
+    if (st) return st;
+    if (best_us) *best_us = best * 1000.0f / trial_iters;
+    return bp_reset_messages(G);
 }
 
 int bp_set_arithmetic(bp_grid* G, int32_t arith) {
@@ -340,14 +460,17 @@ int bp_reset_messages(bp_grid* G) {
 }
 
 int bp_iterate(bp_grid* G, int32_t mode, int32_t n_iters, int32_t schedule) {
+    TraceRange tr("bp_iterate");
     return iterate(G, mode, n_iters, schedule, false);
 }
 
 int bp_iterate_dense(bp_grid* G, int32_t mode, int32_t n_iters, int32_t schedule) {
+    TraceRange tr("bp_iterate_dense");
     return iterate(G, mode, n_iters, schedule, true);
 }
 
 static int readout(bp_grid* G, float* beliefs, int32_t* labels) {
+    TraceRange tr("bp_readout");
     int st = check_ready(G);
     if (st) return st;
     if ((st = with_device(G))) return st;

@@ -376,6 +376,7 @@ int bp_batch_reset_messages(bp_batch* B) {
 }
 
 int bp_batch_iterate(bp_batch* B, int32_t mode, int32_t n_iters) {
+    TraceRange tr("bp_batch_iterate");
     int st = ready(B);
     if (st) return st;
     if (mode != BP_SUM_PRODUCT && mode != BP_MAX_PRODUCT) return fail(BP_EINVAL, "bad mode %d", mode);

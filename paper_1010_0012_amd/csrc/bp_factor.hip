@@ -370,6 +370,7 @@ int bp_fg_reset_messages(bp_fgraph* F) {
 }
 
 int bp_fg_iterate(bp_fgraph* F, int32_t mode, int32_t n_iters, int32_t dense) {
+    bpi::TraceRange tr("bp_fg_iterate");
     int st = ready(F);
     if (st) return st;
     if (!F->g) return fail(BP_ESTATE, "bp_fg_set_unary has not been called");

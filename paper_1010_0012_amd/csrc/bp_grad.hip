@@ -78,6 +78,7 @@ int64_t bp_grad_workspace_bytes(const bp_grid* G, int32_t n_iters, int32_t ckpt_
 }
 
 int bp_forward_ckpt(bp_grid* G, int32_t n_iters, int32_t ckpt_every, void* gws, int64_t bytes) {
+    bpi::TraceRange tr("bp_forward_ckpt");
     int st = grad_checks(G, n_iters, ckpt_every);
     if (st) return st;
     if (!gws) return fail(BP_EINVAL, "null gradient workspace");
@@ -115,6 +116,7 @@ int bp_forward_ckpt(bp_grid* G, int32_t n_iters, int32_t ckpt_every, void* gws, 
 }
 
 int bp_backward(bp_grid* G, const float* dL_db, float* dtheta, float* dalpha) {
+    bpi::TraceRange tr("bp_backward");
     if (!G) return fail(BP_EINVAL, "null handle");
     if (!G->grad_ready) return fail(BP_ESTATE, "bp_backward needs a bp_forward_ckpt with no state change since");
     if (!dL_db || !dtheta || !dalpha) return fail(BP_EINVAL, "null pointer argument");

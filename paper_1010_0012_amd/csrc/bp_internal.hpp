@@ -29,6 +29,8 @@ struct bp_grid {
     int64_t cb_pass = 0;                  // checkerboard passes since reset
     bool fuse_sync = true;                // sync iterations run two per launch where compiled
     bool arith_f32 = false;               // BP_ARITH_F32: float32 arithmetic where compiled
+    int pair_layout = 0;                  // two-iteration launch mapping (bpk::PairLayout)
+    int pair_cap = -1;                    // its workgroups per CU (0: no cap, -1: the default)
     const float* g = nullptr;
     // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10
     // tables of the window potential built into the workspace's table region
@@ -100,4 +102,15 @@ int iterate_general(bp_grid* G, int kmode, int n, int schedule);
 hipError_t launch_general_update(const bp_grid* G, const bpk::UpdateArgs& u, int kmode);
 // Build the window potential's tables into the workspace table region.
 int build_window_tables(bp_grid* G);
+// A named roctx range for the life of the object, for rocprofv3
+// --marker-trace, when the process runs with BP_ROCTX=1; roctx is looked up
+// at run time (dlopen), so the library does not depend on it, and without
+// the variable (or without roctx) the range costs one branch.
+struct TraceRange {
+    explicit TraceRange(const char* name);
+    ~TraceRange();
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+    bool on;
+};
 }  // namespace bpi

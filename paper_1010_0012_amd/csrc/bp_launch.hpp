@@ -61,6 +61,12 @@ size_t lds_cap_bytes(int n);
 // Compute units of the current device (queried once per device); 0 when
 // the device cannot be queried.
 int cu_count();
+// max |cur - prev| over the n (a multiple of 4) entries finite in both into
+// *max_change, and the count of non-finite entries of cur into *non_finite
+// (either output may be null; prev may be null: no change); both zeroed
+// first on the stream.
+hipError_t launch_message_stats(const float* cur, const float* prev, size_t n, float* max_change, int* non_finite,
+                                hipStream_t s);
 // Beliefs and/or MAP labels (either output may be null).
 hipError_t launch_readout(const UpdateArgs& a, float* beliefs, int* labels, hipStream_t stream);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t stream);

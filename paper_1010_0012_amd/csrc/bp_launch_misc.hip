@@ -1,4 +1,5 @@
 // Dense comparison kernel, readout and fill launchers.
+#include <algorithm>
 #include <atomic>
 
 #include "bp_kernels.hpp"
@@ -117,6 +118,62 @@ size_t lds_cap_bytes(int n) {
     const size_t bytes = (size_t)(lds / n) / 256 * 256;
     if ((size_t)lds / ((size_t)n * (n + 1)) <= 256 || bytes > (size_t)per_block) return 0;
     return bytes;
+}
+
+namespace {
+
+// max |cur - prev| over the entries finite in both, and the count of
+// entries of cur that are NaN or infinite: per-thread partials, a wave
+// butterfly, one atomic per wave (the outputs start at 0; max on the bits
+// of non-negative floats orders them as the floats).
+__global__ __launch_bounds__(kBlock) void message_stats_kernel(const v4f* cur, const v4f* prev, size_t n4,
+                                                               float* max_change, int* non_finite) {
+    float mx = 0.0f;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += (size_t)gridDim.x * kBlock) {
+        const v4f a = cur[i];
+        const v4f b = prev ? prev[i] : a;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float x = a[k], y = b[k];
+            if (!__builtin_isfinite(x)) ++bad;
+            else if (__builtin_isfinite(y)) mx = fmaxf(mx, fabsf(x - y));
+        }
+    }
+#pragma unroll
+    for (int w = 32; w >= 1; w /= 2) {
+        mx = fmaxf(mx, __shfl_xor(mx, w));
+        bad += __shfl_xor(bad, w);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (max_change) atomicMax(reinterpret_cast<unsigned*>(max_change), __float_as_uint(mx));
+        if (non_finite && bad) atomicAdd(non_finite, bad);
+    }
+}
+
+__global__ void zero_kernel(unsigned* a, unsigned* b) {
+    if (threadIdx.x == 0) {
+        if (a) *a = 0u;
+        if (b) *b = 0u;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_message_stats(const float* cur, const float* prev, size_t n, float* max_change, int* non_finite,
+                                hipStream_t s) {
+    // zeroed by a kernel, not hipMemsetAsync: the call may be captured in a graph
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned*>(max_change),
+                       reinterpret_cast<unsigned*>(non_finite));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t n4 = n / 4;
+    const int cus = cu_count();
+    const size_t want = (n4 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)(cus > 0 ? cus : 256) * 8));
+    hipLaunchKernelGGL(message_stats_kernel, dim3(blocks), dim3(kBlock), 0, s, reinterpret_cast<const v4f*>(cur),
+                       reinterpret_cast<const v4f*>(prev), n4, max_change, non_finite);
+    return hipGetLastError();
 }
 
 int cu_count() {

@@ -159,6 +159,7 @@ int64_t bp_multiscale_workspace_bytes(const bp_grid* G, int32_t levels) {
 
 int bp_iterate_multiscale(bp_grid* G, int32_t mode, int32_t levels, const int32_t* iters, void* ms_ws,
                           int64_t ms_bytes) {
+    TraceRange tr("bp_iterate_multiscale");
     int st = check_ready(G);
     if (st) return st;
     invalidate_grad(G);

@@ -62,38 +62,54 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
 // Two synchronous iterations per launch (register windows only): the grid
 // is padded to a multiple of the XCD count for the band remap, and M = 4G
 // selects the branch-free full-row instance.
+// Two synchronous iterations per launch (register windows only), in the
+// mapping a.pair_layout asks for where it applies: row blocks (M = 4G and
+// an inbox plane below 2^32 bytes) in XCD column strips or row bands, or
+// one group per pixel slot (the grid padded to a multiple of the XCD count
+// for its band remap; M = 4G selects the branch-free instance).  All
+// mappings run the same per-pixel code, so they give the same bits.
+// a.pair_cap: workgroups per CU allowed through the LDS request (0 none;
+// -1 the default, 4 for float32 arithmetic, none for double).
 template <int G, int TW, int MODE>
 hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
     const bool rows = a.M == G * kLpl && (uint64_t)a.N * a.M * sizeof(float) < (uint64_t(1) << 32);
+    const int cap = a.pair_cap >= 0 ? a.pair_cap : (MODE == kSumF32 ? 4 : 0);
+    const size_t lds = cap > 0 ? lds_cap_bytes(cap) : 0;
     if constexpr (MODE == kSumF32) {
         if (!rows) return hipErrorInvalidValue;  // float32 arithmetic: row-block launches only
     }
-    if (rows) {
+    if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
         const int slots = a.colour < 0 ? a.W : a.half_w;
         const int gx = (slots + kBlock / G - 1) / (kBlock / G);
+        if (a.pair_layout == kPairBands) {
+            const int64_t total = (int64_t)gx * a.H;
+            const int per = (int)((total + kXcds - 1) / kXcds);
+            if ((int64_t)per * kXcds >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
+                               lds, s, a, gx, gx, per);
+            return hipGetLastError();
+        }
         const int gxp = (gx + kXcds - 1) / kXcds * kXcds;
         const int64_t total = (int64_t)gxp * a.H;
         if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-        // float32 arithmetic: at most 4 workgroups per CU (fewer rows in
-        // flight per XCD, so more of the neighbour rows are still in L2;
-        // measured 2% faster than 6 per CU; double arithmetic is faster
-        // uncapped)
-        const size_t lds = MODE == kSumF32 ? lds_cap_bytes(4) : 0;
         hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock), lds, s, a,
-                           gxp, gx);
+                           gxp, gx, 0);
         return hipGetLastError();
     }
-    const int nblk = (int)groups_blocks<G>(a.n_slots);
-    const int per = (nblk + kXcds - 1) / kXcds;
-    if constexpr (MODE == kSumF32) return hipErrorInvalidValue;
-    if (a.M == G * kLpl)
-        hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, true>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
-                           0, s, a, per);
-    else
-        hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, false>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
-                           0, s, a, per);
-    return hipGetLastError();
+    if constexpr (MODE == kSumF32) {
+        return hipErrorInvalidValue;
+    } else {
+        const int nblk = (int)groups_blocks<G>(a.n_slots);
+        const int per = (nblk + kXcds - 1) / kXcds;
+        if (a.M == G * kLpl)
+            hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, true>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
+                               lds, s, a, per);
+        else
+            hipLaunchKernelGGL((sparse_update2_kernel<G, TW, MODE, false>), dim3((unsigned)(per * kXcds)),
+                               dim3(kBlock), lds, s, a, per);
+        return hipGetLastError();
+    }
 }
 
 template <int G, int MODE, int I = 0>

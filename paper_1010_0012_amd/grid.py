@@ -99,6 +99,36 @@ class Grid:
         update where a float32 kernel is compiled (bp_set_arithmetic)."""
         L.bp_set_arithmetic(self.handle, {"f64": L.BP_ARITH_F64, "f32": L.BP_ARITH_F32}[arith])
 
+    def message_stats(self):
+        """(largest |m - m'| against the other message buffer, number of
+        non-finite entries) of the current messages (bp_message_stats);
+        waits for the stream."""
+        self._sync_stream()
+        out = torch.empty(2, dtype=torch.int32, device=self.device)
+        L.bp_message_stats(self.handle, out.data_ptr(), out.data_ptr() + 4)
+        torch.cuda.synchronize(self.device)
+        v = out.cpu()
+        return float(v[:1].view(torch.float32)[0]), int(v[1])
+
+    LAYOUTS = {"strips": 0, "bands": 1, "slots": 2}
+
+    def set_launch_tuning(self, layout="strips", cap=-1):
+        """Mapping of the two-iteration launches ("strips", "bands" or "slots")
+        and their workgroups per CU (0 none, -1 the default); every setting
+        gives the same bits (bp_set_launch_tuning)."""
+        L.bp_set_launch_tuning(self.handle, self.LAYOUTS[layout], cap)
+
+    def get_launch_tuning(self):
+        layout, cap = L.bp_get_launch_tuning(self.handle)
+        return {v: k for k, v in self.LAYOUTS.items()}[layout], cap
+
+    def autotune(self, mode="sum", schedule="sync", trial_iters=4):
+        """Time the launch mappings on this grid and keep the fastest
+        (bp_autotune); resets the messages.  Returns us per iteration."""
+        self._sync_stream()
+        return L.bp_autotune(self.handle, MODES[mode] if isinstance(mode, str) else int(mode),
+                             SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule), trial_iters)
+
     def iterate(self, mode="sum", n_iters=1, schedule="sync", dense=False):
         self._sync_stream()
         fn = L.bp_iterate_dense if dense else L.bp_iterate

@@ -48,6 +48,10 @@ static void null_handles() {
     EXPECT(bp_iterate_dense(nullptr, BP_SUM_PRODUCT, 1, BP_SCHED_SYNC) == BP_EINVAL);
     EXPECT(bp_set_sync_fusion(nullptr, 1) == BP_EINVAL);
     EXPECT(bp_set_arithmetic(nullptr, BP_ARITH_F32) == BP_EINVAL);
+    EXPECT(bp_set_launch_tuning(nullptr, BP_PAIR_STRIPS, -1) == BP_EINVAL);
+    EXPECT(bp_get_launch_tuning(nullptr, &i, &i) == BP_EINVAL);
+    EXPECT(bp_autotune(nullptr, BP_SUM_PRODUCT, BP_SCHED_SYNC, 2, &f) == BP_EINVAL);
+    EXPECT(bp_batch_set_arithmetic(nullptr, BP_ARITH_F32) == BP_EINVAL);
     EXPECT(bp_beliefs(nullptr, &f) == BP_EINVAL);
     EXPECT(bp_map_labels(nullptr, &i) == BP_EINVAL);
     EXPECT(bp_readout(nullptr, nullptr, nullptr) == BP_EINVAL);
@@ -116,6 +120,18 @@ static void potentials_and_layouts() {
                 EXPECT(bp_set_arithmetic(&G, BP_ARITH_F32) == BP_OK && G.arith_f32);
                 EXPECT(bp_set_arithmetic(&G, 7) == BP_EINVAL && G.arith_f32);
                 EXPECT(bp_set_arithmetic(&G, BP_ARITH_F64) == BP_OK && !G.arith_f32);
+                {
+                    int32_t lay = -7, cap = -7;
+                    EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_STRIPS && cap == -1);
+                    EXPECT(bp_set_launch_tuning(&G, BP_PAIR_SLOTS, 3) == BP_OK);
+                    EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_SLOTS && cap == 3);
+                    EXPECT(bp_set_launch_tuning(&G, 3, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
+                    EXPECT(bp_set_launch_tuning(&G, BP_PAIR_BANDS, 65) == BP_EINVAL && G.pair_cap == 3);
+                    EXPECT(bp_get_launch_tuning(&G, nullptr, &cap) == BP_EINVAL);
+                    // not ready (no unary): refused before any device work
+                    EXPECT(bp_autotune(&G, BP_SUM_PRODUCT, BP_SCHED_SYNC, 2, nullptr) == BP_ESTATE);
+                    EXPECT(bp_set_launch_tuning(&G, BP_PAIR_STRIPS, -1) == BP_OK);
+                }
                 // other potentials on the same handle
                 EXPECT(bp_set_potential(&G, M, T, 1.5f, 0.0f) == BP_OK);
                 EXPECT(bp_set_potential(&G, M, T, -0.3f, 0.5f) == BP_OK);

@@ -36,6 +36,11 @@ def test_host_side_argument_checks():
     assert lib.bp_beliefs(None, None) == L.BP_EINVAL
     assert lib.bp_readout(None, None, None) == L.BP_EINVAL
     assert lib.bp_readout(None, ctypes.c_void_p(16), None) == L.BP_EINVAL
+    assert lib.bp_set_launch_tuning(None, 0, -1) == L.BP_EINVAL
+    lay, cap = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.bp_get_launch_tuning(None, ctypes.byref(lay), ctypes.byref(cap)) == L.BP_EINVAL
+    assert lib.bp_autotune(None, 0, 0, 2, None) == L.BP_EINVAL
+    assert lib.bp_batch_set_arithmetic(None, 1) == L.BP_EINVAL
     assert lib.bp_destroy(None) == L.BP_OK
 
 
