@@ -557,6 +557,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="skip every leg beside the headline")
     ap.add_argument("--legs", default=",".join(LEGS),
                     help=f"comma-separated legs to run beside the headline, of {','.join(LEGS)}")
+    ap.add_argument("--tuning", default=None,
+                    help="LAYOUT:CAP launch mapping of the headline (e.g. wide:-1) instead of autotuning it")
     ap.add_argument("--arith", choices=("f32", "f64"), default="f32",
                     help="arithmetic of the headline sum-product update (bp_set_arithmetic)")
     args = ap.parse_args()
@@ -580,11 +582,17 @@ def main():
     grid.set_potential(cfg.M, cfg.T, cfg.alpha)
     grid.set_arithmetic(args.arith)
     grid.set_unary(g)
-    # the two-iteration launch's mapping, timed on this grid (bp_autotune)
-    tune_us = grid.autotune("sum", "sync", 4)
+    # the two-iteration launch's mapping: timed on this grid (bp_autotune), or given
+    if args.tuning:
+        layout, cap = args.tuning.split(":")
+        grid.set_launch_tuning(layout, int(cap))
+        tune_us = None
+    else:
+        tune_us = grid.autotune("sum", "sync", 10)
     tuning = grid.get_launch_tuning()
     launch_tuning = {args.arith: {"layout": tuning[0], "cap": tuning[1], "autotune_us_per_iteration": tune_us}}
-    log(f"bench: autotuned launch mapping {tuning} ({tune_us:.1f} us per iteration in the trial)")
+    log(f"bench: launch mapping {tuning}" + (f" (autotuned: {tune_us:.1f} us per iteration in the trial)"
+                                               if tune_us is not None else " (given)"))
     beliefs = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device=dev)
     labels = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device=dev)
     updates_per_iter = cfg.n_directed_edges * cfg.M
@@ -655,7 +663,7 @@ def main():
     # the other arithmetic beside it (double: every message its exact value rounded once)
     other = "f64" if args.arith == "f32" else "f32"
     grid.set_arithmetic(other)
-    o_us = grid.autotune("sum", "sync", 4)
+    o_us = grid.autotune("sum", "sync", 10) if not args.tuning else None
     o_tuning = grid.get_launch_tuning()
     launch_tuning[other] = {"layout": o_tuning[0], "cap": o_tuning[1], "autotune_us_per_iteration": o_us}
     extra["launch_tuning"] = launch_tuning

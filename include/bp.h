@@ -171,11 +171,13 @@ int bp_set_arithmetic(bp_grid* grid, int32_t arith);
 
 /* Launch mapping of the two-iteration launches (synchronous iterations and
  * checkerboard pass pairs of the window potential, Eq. 7 / Eq. 11; see
- * bp_set_sync_fusion).  layout: BP_PAIR_STRIPS (the default) runs one
+ * bp_set_sync_fusion).  layout: BP_PAIR_STRIPS runs one
  * workgroup per block of consecutive pixels of a grid row, the blocks of a
  * row padded to a multiple of the 8 XCDs so that each XCD holds the same
  * column strips in every row; BP_PAIR_BANDS the same blocks remapped so that
- * each XCD holds a contiguous band of rows; BP_PAIR_SLOTS one pixel group
+ * each XCD holds a contiguous band of rows; BP_PAIR_WIDE the same blocks
+ * remapped so that each XCD holds one contiguous strip of 1/8 of the
+ * columns, every row (the default); BP_PAIR_SLOTS one pixel group
  * per slot in row-major order (the only form when M is not 4 * ceil-pow2(M /
  * 4) or a message plane reaches 2^32 bytes, where the first two fall back to
  * it; float32 arithmetic has the row blocks only, where BP_PAIR_SLOTS runs
@@ -199,12 +201,14 @@ int bp_set_arithmetic(bp_grid* grid, int32_t arith);
  * no output, BP_ESTATE without a potential or a workspace. */
 int bp_message_stats(bp_grid* grid, float* max_change, int32_t* non_finite);
 
-enum bp_pair_layout { BP_PAIR_STRIPS = 0, BP_PAIR_BANDS = 1, BP_PAIR_SLOTS = 2 };
+enum bp_pair_layout { BP_PAIR_STRIPS = 0, BP_PAIR_BANDS = 1, BP_PAIR_SLOTS = 2, BP_PAIR_WIDE = 3 };
 int bp_set_launch_tuning(bp_grid* grid, int32_t layout, int32_t cap);
 int bp_get_launch_tuning(const bp_grid* grid, int32_t* layout, int32_t* cap);
 
-/* Time every (layout, cap) pair above, caps 0, 4 and 3, on this grid's own
- * state and keep the fastest for `mode` and `schedule` (BP_SCHED_SYNC or
+/* Time the current setting and every (layout, cap) pair above, caps 0, 4
+ * and 3, on this grid's own state, and keep the fastest (another setting
+ * replaces the best only when at least 1% faster) for `mode` and `schedule`
+ * (BP_SCHED_SYNC or
  * BP_SCHED_CHECKERBOARD): trial_iters iterations (even, >= 2) per candidate
  * after two warm-up iterations, timed with events on the grid's stream
  * (synchronises with it).  Needs the potential, the unary and the workspace;

@@ -52,8 +52,8 @@ struct InstDesc {
 // below 2^32 bytes also carry the row-block layout of
 // batch_update2_rows_kernel: instance k gets gxp[k] * H workgroups, gx[k] of
 // kBlock/G pixels per grid row padded to gxp[k], a multiple of the XCD
-// count, so every instance starts on XCD 0 and each XCD holds the same column
-// strips in every row (as in the single-grid row-block launch).
+// count, so every instance starts on XCD 0 and each XCD holds one contiguous
+// strip of columns in every row (as in the single-grid row-block launch).
 constexpr int kLaunchInst = 8;
 struct BatchLaunch {
     int n_inst;
@@ -165,9 +165,14 @@ __global__ __launch_bounds__(kBlock) void batch_update2_rows_kernel(const BatchL
     int k = 0;
     while (k + 1 < L.n_inst && b >= L.rows_end[k]) ++k;  // uniform over the workgroup
     const InstDesc& d = L.inst[k];
+    // XCD x (workgroup b runs on XCD b mod 8, and every instance's range
+    // starts at a multiple of 8) holds the contiguous column blocks
+    // [x gxp/8, (x+1) gxp/8) of every row of the instance
     const int lb = b - (k ? L.rows_end[k - 1] : 0);
-    const int r = lb / L.gxp[k];
-    const int cb = lb - r * L.gxp[k];
+    const int wide = L.gxp[k] / kXcds;
+    const int kx = lb / kXcds;
+    const int r = kx / wide;
+    const int cb = (lb % kXcds) * wide + (kx - r * wide);
     if (cb >= L.gx[k]) return;  // padding: whole workgroup
     const int c = cb * PPB + (int)(threadIdx.x / G);
     if (c >= d.W) return;  // whole groups only

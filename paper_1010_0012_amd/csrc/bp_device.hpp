@@ -30,7 +30,7 @@ constexpr int kMaxTab = 256;        // potential table entries (|d| < BP_MAX_LAB
 constexpr int kDTab = 32;           // double window weights carried in the arguments (|d| <= 31)
 
 // Mappings of the two-iteration launch (UpdateArgs::pair_layout).
-enum PairLayout { kPairStrips = 0, kPairBands = 1, kPairSlots = 2 };
+enum PairLayout { kPairStrips = 0, kPairBands = 1, kPairSlots = 2, kPairWide = 3 };
 
 // kSumF32: sum-product with float32 arithmetic (BP_ARITH_F32), used by the
 // synchronous and checkerboard window kernels only.
@@ -72,8 +72,8 @@ struct UpdateArgs {
     int both;              // sweep: 1 = the second half of the grid runs the opposite direction
     int eq10;              // max-product: some f(d) < fbar, so Eq. 10 (not Eq. 11) holds
     float* mid;            // two-iteration launches: where the first iteration's messages go, or null
-    int pair_layout;       // two-iteration launch mapping (host side): 0 row blocks in XCD column strips,
-                           // 1 row blocks in XCD row bands, 2 one group per pixel slot (kPairLayout*)
+    int pair_layout;       // two-iteration launch mapping (host side, PairLayout): row blocks in XCD
+                           // column strips, in XCD row bands or in one wide strip per XCD; one group per slot
     int pair_cap;          // workgroups per CU allowed by the launch's LDS request: 0 none, -1 the default
     float fbar;            // potential outside the window (float32, max-product)
     float tab[kMaxTab];    // max-product: f(d) for d <= T, 0 beyond (float32)

@@ -29,7 +29,7 @@ struct bp_grid {
     int64_t cb_pass = 0;                  // checkerboard passes since reset
     bool fuse_sync = true;                // sync iterations run two per launch where compiled
     bool arith_f32 = false;               // BP_ARITH_F32: float32 arithmetic where compiled
-    int pair_layout = 0;                  // two-iteration launch mapping (bpk::PairLayout)
+    int pair_layout = bpk::kPairWide;     // two-iteration launch mapping (bpk::PairLayout)
     int pair_cap = -1;                    // its workgroups per CU (0: no cap, -1: the default)
     const float* g = nullptr;
     // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10

@@ -636,13 +636,24 @@ __device__ __forceinline__ void pair_rows_pixel(const float* g, const float* in,
 // read through that XCD's own L2, and all XCDs sweep the grid top to bottom
 // together.  With per > 0 the workgroups are remapped as in
 // sparse_update2_kernel instead (gxp = gx), so that each XCD holds a
-// contiguous band of rows; at 480 x 640 x 64 that measured 6% slower.
+// contiguous band of rows (at 480 x 640 x 64 that measured 6% slower);
+// with per < 0 XCD x holds the contiguous column blocks [x gxp/8, (x+1)
+// gxp/8) of every row, one wide strip, so that only the strips' edge
+// columns are read by two XCDs.
 template <int G, int TW, int MODE>
 __global__ __launch_bounds__(kBlock) void sparse_update2_rows_kernel(UpdateArgs a, int gxp, int gx, int per) {
     constexpr int PPB = kBlock / G;
-    const int b = per > 0 ? xcd_band_block((int)blockIdx.x, per) : (int)blockIdx.x;
-    const int r = b / gxp;
-    const int cb = b - r * gxp;
+    int r, cb;
+    if (per < 0) {
+        const int wide = gxp / kXcds;  // column blocks per XCD strip
+        const int x = (int)blockIdx.x % kXcds, k = (int)blockIdx.x / kXcds;
+        r = k / wide;
+        cb = x * wide + (k - r * wide);
+    } else {
+        const int b = per > 0 ? xcd_band_block((int)blockIdx.x, per) : (int)blockIdx.x;
+        r = b / gxp;
+        cb = b - r * gxp;
+    }
     if (cb >= gx) return;  // padding: whole workgroup
     const int j = cb * PPB + (int)(threadIdx.x / G);
     const int pos = threadIdx.x & (G - 1);

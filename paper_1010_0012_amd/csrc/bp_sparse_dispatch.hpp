@@ -64,7 +64,8 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
 // selects the branch-free full-row instance.
 // Two synchronous iterations per launch (register windows only), in the
 // mapping a.pair_layout asks for where it applies: row blocks (M = 4G and
-// an inbox plane below 2^32 bytes) in XCD column strips or row bands, or
+// an inbox plane below 2^32 bytes) in XCD column strips, row bands or one
+// wide strip per XCD, or
 // one group per pixel slot (the grid padded to a multiple of the XCD count
 // for its band remap; M = 4G selects the branch-free instance).  All
 // mappings run the same per-pixel code, so they give the same bits.
@@ -94,7 +95,7 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
         const int64_t total = (int64_t)gxp * a.H;
         if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock), lds, s, a,
-                           gxp, gx, 0);
+                           gxp, gx, a.pair_layout == kPairWide ? -1 : 0);
         return hipGetLastError();
     }
     if constexpr (MODE == kSumF32) {

@@ -110,10 +110,10 @@ class Grid:
         v = out.cpu()
         return float(v[:1].view(torch.float32)[0]), int(v[1])
 
-    LAYOUTS = {"strips": 0, "bands": 1, "slots": 2}
+    LAYOUTS = {"strips": 0, "bands": 1, "slots": 2, "wide": 3}
 
-    def set_launch_tuning(self, layout="strips", cap=-1):
-        """Mapping of the two-iteration launches ("strips", "bands" or "slots")
+    def set_launch_tuning(self, layout="wide", cap=-1):
+        """Mapping of the two-iteration launches ("strips", "wide", "bands" or "slots")
         and their workgroups per CU (0 none, -1 the default); every setting
         gives the same bits (bp_set_launch_tuning)."""
         L.bp_set_launch_tuning(self.handle, self.LAYOUTS[layout], cap)

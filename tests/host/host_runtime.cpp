@@ -122,15 +122,15 @@ static void potentials_and_layouts() {
                 EXPECT(bp_set_arithmetic(&G, BP_ARITH_F64) == BP_OK && !G.arith_f32);
                 {
                     int32_t lay = -7, cap = -7;
-                    EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_STRIPS && cap == -1);
+                    EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_WIDE && cap == -1);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_SLOTS, 3) == BP_OK);
                     EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_SLOTS && cap == 3);
-                    EXPECT(bp_set_launch_tuning(&G, 3, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
+                    EXPECT(bp_set_launch_tuning(&G, 4, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_BANDS, 65) == BP_EINVAL && G.pair_cap == 3);
                     EXPECT(bp_get_launch_tuning(&G, nullptr, &cap) == BP_EINVAL);
                     // not ready (no unary): refused before any device work
                     EXPECT(bp_autotune(&G, BP_SUM_PRODUCT, BP_SCHED_SYNC, 2, nullptr) == BP_ESTATE);
-                    EXPECT(bp_set_launch_tuning(&G, BP_PAIR_STRIPS, -1) == BP_OK);
+                    EXPECT(bp_set_launch_tuning(&G, BP_PAIR_WIDE, -1) == BP_OK);
                 }
                 // other potentials on the same handle
                 EXPECT(bp_set_potential(&G, M, T, 1.5f, 0.0f) == BP_OK);

@@ -10,7 +10,7 @@ from synth_mrf import random_unary
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["strips", "bands", "slots"]
+LAYOUTS = ["strips", "wide", "bands", "slots"]
 CAPS = [-1, 0, 4, 3, 1]
 CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (37, 70, 64, 4, 0.5, "sum", "sync", "f64"),
@@ -48,10 +48,11 @@ def test_every_mapping_gives_the_same_bits(case):
             grid.set_launch_tuning(layout, cap)
             assert grid.get_launch_tuning() == (layout, cap)
             np.testing.assert_array_equal(messages(grid, mode, schedule), ref)
+    grid.set_launch_tuning("wide", -1)  # the autotuner starts from the current setting
     best = grid.autotune(mode, schedule, 2)
     layout, cap = grid.get_launch_tuning()
     say(f"{case}: autotuned {layout}, cap {cap}, {best:.1f} us per iteration")
-    assert best > 0 and layout in LAYOUTS and cap in (0, 4, 3)
+    assert best > 0 and layout in LAYOUTS and cap in (-1, 0, 4, 3)
     np.testing.assert_array_equal(messages(grid, mode, schedule), ref)
     grid.close()
 
@@ -63,7 +64,7 @@ def test_tuning_argument_errors():
     grid = Grid(8, 8)
     grid.set_potential(16, 2, 1.0)
     grid.set_unary(torch.from_numpy(random_unary(8, 8, 16, 1)).cuda())
-    for layout, cap in ((3, -1), (-1, 0), (0, -2), (0, 65)):
+    for layout, cap in ((4, -1), (-1, 0), (0, -2), (0, 65)):
         with pytest.raises(L.BPError) as e:
             L.bp_set_launch_tuning(grid.handle, layout, cap)
         assert e.value.status == L.BP_EINVAL
@@ -71,6 +72,6 @@ def test_tuning_argument_errors():
         with pytest.raises(L.BPError) as e:
             L.bp_autotune(grid.handle, mode, schedule, trials)
         assert e.value.status == L.BP_EINVAL
-    assert grid.get_launch_tuning() == ("strips", -1)
+    assert grid.get_launch_tuning() == ("wide", -1)
     torch.cuda.synchronize()
     grid.close()
