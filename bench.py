@@ -37,7 +37,7 @@ def log(*a):
 # Legs beside the headline: other schedules and modes of the sparse update,
 # the dense O(M^2) update, sweeps, coarse-to-fine, general potentials,
 # factor graphs, the fbar = 0 experiment, forward + backward, batches.
-LEGS = ("sparse", "dense", "sweep", "multiscale", "general", "factor", "fbar0", "grad", "batch")
+LEGS = ("sparse", "dense", "sweep", "multiscale", "general", "factor", "fbar0", "grad", "batch", "walk")
 
 
 def alg_bytes_per_sync_iter(cfg):
@@ -47,20 +47,22 @@ def alg_bytes_per_sync_iter(cfg):
 
 
 KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
-                  "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp",
+                  "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp", "paper_1010_0012_amd/csrc/bp_walk.hpp",
                   "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip",
                   "paper_1010_0012_amd/csrc/bp_launch_sparse_sumf.hip",
                   "paper_1010_0012_amd/csrc/bp_launch_misc.hip"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_pair_rows_f32_stereo480x640.json")
 
 
-def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, row_blocks=True):
+def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, layout="wide"):
     """Template instance of the sparse update that runs (M, T): lanes per pixel
     G is the smallest power of two >= ceil(M/4) in [4, 64]; the window width is
     the smallest compiled half-width >= T; pair: the two-iteration launch,
     whose row-block form runs when M = 4G and the messages of one direction
     fit 32-bit byte offsets, unless the launch mapping is one group per
-    pixel slot (mode 2: sum-product in float32 arithmetic, row blocks only)."""
+    pixel slot (mode 2: sum-product in float32 arithmetic, row blocks only);
+    the column walk (synchronous, M = 32 or 64, planes below 2^31 bytes)
+    where the mapping is the walk."""
     G = 4
     while G * 4 < M and G < 64:
         G *= 2
@@ -68,6 +70,9 @@ def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, row_blocks=True):
     tw = next((t for t in tws if t >= T), None)
     if tw is None:
         return f"sparse_update_wide_kernel<{G}, {mode}>"
+    if pair and layout == "walk" and M == 4 * G and G in (8, 16) and n_pixels * M * 4 <= 2 ** 31:
+        return f"sparse_walk2_kernel<{G}, {tw}, {mode}, 2>"
+    row_blocks = mode == 2 or layout != "slots"
     if pair and row_blocks and M == 4 * G and n_pixels * M * 4 < 2 ** 32:
         return f"sparse_update2_rows_kernel<{G}, {tw}, {mode}>"
     if pair:
@@ -75,10 +80,11 @@ def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, row_blocks=True):
     return f"sparse_update_kernel<{G}, {tw}, {mode}>"
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (each scaled by the same counter on a plain
-    256 MiB copy), or None when the kernel sources changed since it was taken."""
+    256 MiB copy), or None when the kernel sources changed since it was taken
+    or the summary is of another kernel (another launch mapping)."""
     import hashlib
     try:
         rec = json.load(open(PMC_SUMMARY))
@@ -90,7 +96,8 @@ def measured_traffic():
             h.update(open(os.path.join(ROOT, f), "rb").read())
     except OSError:
         return None
-    return rec["traffic_bytes"] if rec.get("source_sha256") == h.hexdigest() else None
+    same = rec.get("source_sha256") == h.hexdigest() and kernel in rec.get("kernel", "")
+    return rec["traffic_bytes"] if same else None
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
@@ -448,6 +455,36 @@ def factor_leg(reps=3, n_iters=10):
     return out
 
 
+def walk_leg(reps=5, n_iters=20):
+    """The two-iteration launch on a 480 x 640 grid with M = 32 (T = 3,
+    alpha = 0.5, float32 arithmetic, seeded uniform unary): wide column
+    strips against the column walk (each grid row staged once in LDS), per
+    launch, and what the autotuner picks.  Algorithmic bytes 4 M (2E + N)."""
+    import torch
+
+    from paper_1010_0012_amd.grid import Grid
+    from synth_mrf import random_unary
+    H, W, M, T = 480, 640, 32, 3
+    grid = Grid(H, W)
+    grid.set_potential(M, T, 0.5)
+    grid.set_arithmetic("f32")
+    grid.set_unary(torch.from_numpy(random_unary(H, W, M, 3)).cuda())
+    alg = 4 * M * (2 * (2 * H * W - H - W) * 2 + H * W)
+    out = {"walk_workload": f"{H}x{W}, M={M}, T={T}, sum-product sync, float32 arithmetic, pair launches"}
+    for layout in ("wide", "walk"):
+        grid.set_launch_tuning(layout, -1)
+        best = min(time_launches(grid, "sum", n_iters, "sync", False, 1, iters_per_launch=2) for _ in range(reps))
+        out[f"walk_leg_{layout}_pair_launch_us"] = best * 1e3
+        out[f"walk_leg_{layout}_GBs"] = alg / (best * 1e-3) / 1e9
+        log(f"bench: {H}x{W}x{M} pair launch, {layout}: {best * 1e3:.1f} us ({alg / (best * 1e-3) / 1e9:.0f} GB/s)")
+    grid.set_launch_tuning("wide", -1)
+    grid.autotune("sum", "sync", 4)
+    out["walk_leg_autotuned"] = list(grid.get_launch_tuning())
+    out["walk_leg_wide_over_walk"] = out["walk_leg_wide_pair_launch_us"] / out["walk_leg_walk_pair_launch_us"]
+    grid.close()
+    return out
+
+
 def batch_leg(arith="f64", n_iters=30, reps=3):
     """The 32-instance batch (H, W in [64, 512], M in {16, 32, 64, 128}, T in
     [1, 8]) in the given arithmetic: autotuned plan, n_iters sum-product
@@ -627,11 +664,11 @@ def main():
     bytes_launch = alg_bytes_per_sync_iter(cfg)
     achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
     per_iter_equiv = bytes_launch / (ms_launch / 2 * 1e-3) / 1e9
+    kernel = sparse_kernel_name(cfg.M, cfg.T, 2 if args.arith == "f32" else 0, pair=True, n_pixels=cfg.n_pixels,
+                                layout=tuning[0])
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                "kernel": sparse_kernel_name(cfg.M, cfg.T, 2 if args.arith == "f32" else 0, pair=True,
-                                             n_pixels=cfg.n_pixels,
-                                             row_blocks=args.arith == "f32" or tuning[0] != "slots"),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel),
+                "kernel": kernel,
                 "launch_mapping": {"layout": tuning[0], "cap": tuning[1]},
                 "arithmetic": args.arith,
                 "alg_bytes_per_launch": bytes_launch, "avg_launch_us": ms_launch * 1e3,
@@ -740,7 +777,7 @@ def main():
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
     for name, leg in (("sweep", lambda: sweep_leg(grid, cfg)), ("multiscale", lambda: multiscale_leg(grid, cfg)),
                       ("general", lambda: general_leg(g, cfg)), ("factor", factor_leg), ("fbar0", fbar_zero_leg),
-                      ("grad", grad_leg), ("batch", batch_leg)):
+                      ("grad", grad_leg), ("batch", batch_leg), ("walk", walk_leg)):
         if name in legs:
             extra.update(leg())
 

@@ -406,37 +406,34 @@ __device__ __forceinline__ void message_d(const double (&h)[kLpl], const double*
     else max_message_d<G, TW>(h, tab, fbar, pos, M, x0, full, m);
 }
 
-// The arithmetic of both iterations for one receiver p: rows[k] are the
-// unary and the three inbox rows of the neighbour in direction k that its
-// message to p uses ({g, the two partial-product rows, the far-side row}),
-// gp is p's unary, has[k] whether that neighbour exists.  put_mid(k, m)
-// takes each first-iteration message into p (the factor 1 where there is no
-// neighbour), put_out(o, u) each second-iteration message p sends.
-template <int G, int TW, int MODE, bool FULL, class PutMid, class PutOut>
-__device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], const float (&gp)[kLpl],
-                                             const bool (&has)[4], int pos, int M, const double* dtab,
-                                             double fbar_d, const float* tab, float fbar, PutMid put_mid,
-                                             PutOut put_out) {
+// One first-iteration message into a receiver: rows are the sender's unary
+// and the three inbox rows its message uses ({g, the two partial-product
+// rows, the far-side row}); has says whether the sender exists (the factor 1
+// where it does not).
+template <int G, int TW, int MODE>
+__device__ __forceinline__ void pair_first(const float (&rows)[4][kLpl], bool has, int pos, int M, bool full,
+                                           const double* dtab, double fbar_d, const float* tab, float fbar,
+                                           float (&m)[kLpl]) {
     const int x0 = pos * kLpl;
-    PixelInputs mid;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if constexpr (MODE == kSumF32) {
-            float h[kLpl];
-            sender_h_f(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
-            sum_message_f<G, TW>(h, tab, fbar, pos, M, x0, FULL, mid.m[k]);
-        } else {
-            double h[kLpl];
-            sender_h_d(rows[k][0], rows[k][1], rows[k][2], rows[k][3], h);
-            message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, FULL, mid.m[k]);
-        }
-#pragma unroll
-        for (int i = 0; i < kLpl; ++i) mid.m[k][i] = has[k] ? mid.m[k][i] : 1.0f;
-        put_mid(k, mid.m[k]);
+    if constexpr (MODE == kSumF32) {
+        float h[kLpl];
+        sender_h_f(rows[0], rows[1], rows[2], rows[3], h);
+        sum_message_f<G, TW>(h, tab, fbar, pos, M, x0, full, m);
+    } else {
+        double h[kLpl];
+        sender_h_d(rows[0], rows[1], rows[2], rows[3], h);
+        message_d<G, TW, MODE>(h, dtab, fbar_d, tab, fbar, pos, M, x0, full, m);
     }
-    // Second iteration, sender side, from the messages just computed.
 #pragma unroll
-    for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
+    for (int i = 0; i < kLpl; ++i) m[i] = has ? m[i] : 1.0f;
+}
+
+// The second iteration, sender side: p's four outgoing messages from its
+// unary (mid.g) and the first-iteration messages into it (mid.m).
+template <int G, int TW, int MODE, bool FULL, class PutOut>
+__device__ __forceinline__ void pair_second(const PixelInputs& mid, int pos, int M, const double* dtab, double fbar_d,
+                                            const float* tab, float fbar, PutOut put_out) {
+    const int x0 = pos * kLpl;
     if constexpr (MODE == kSumF32) {
         float h[4][kLpl];
         make_h(mid, h);
@@ -456,6 +453,28 @@ __device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], co
             put_out(o, u);
         }
     }
+}
+
+// The arithmetic of both iterations for one receiver p: rows[k] are the
+// unary and the three inbox rows of the neighbour in direction k that its
+// message to p uses, gp is p's unary, has[k] whether that neighbour exists.
+// put_mid(k, m) takes each first-iteration message into p (the factor 1
+// where there is no neighbour), put_out(o, u) each second-iteration message
+// p sends.
+template <int G, int TW, int MODE, bool FULL, class PutMid, class PutOut>
+__device__ __forceinline__ void pair_compute(const float (&rows)[4][4][kLpl], const float (&gp)[kLpl],
+                                             const bool (&has)[4], int pos, int M, const double* dtab,
+                                             double fbar_d, const float* tab, float fbar, PutMid put_mid,
+                                             PutOut put_out) {
+    PixelInputs mid;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pair_first<G, TW, MODE>(rows[k], has[k], pos, M, FULL, dtab, fbar_d, tab, fbar, mid.m[k]);
+        put_mid(k, mid.m[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) mid.g[i] = gp[i];
+    pair_second<G, TW, MODE, FULL>(mid, pos, M, dtab, fbar_d, tab, fbar, put_out);
 }
 
 // Inbox rows of the neighbour q in direction k that q's message to p uses:

@@ -58,6 +58,10 @@ hipError_t launch_batch_pair_sumf(int arm, bool full, const BatchLaunch& L, unsi
 // most n of its workgroups fit in one CU's LDS (an occupancy cap) on the
 // current device; 0 when the device cannot be queried.
 size_t lds_cap_bytes(int n);
+// Workgroups with `bytes` of dynamic LDS that fit in one CU of the current
+// device (0 when they do not fit in a workgroup's LDS or the device cannot
+// be queried).
+int lds_blocks_per_cu(size_t bytes);
 // Compute units of the current device (queried once per device); 0 when
 // the device cannot be queried.
 int cu_count();

@@ -176,6 +176,16 @@ hipError_t launch_message_stats(const float* cur, const float* prev, size_t n, f
     return hipGetLastError();
 }
 
+int lds_blocks_per_cu(size_t bytes) {
+    int dev = 0, per_cu = 0, per_block = 0;
+    if (bytes == 0 || hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    if (bytes > (size_t)per_block) return 0;
+    return (int)((size_t)per_cu / bytes);
+}
+
 int cu_count() {
     constexpr int kMaxDevices = 64;
     static std::atomic<int> cus[kMaxDevices];  // 0: not yet queried

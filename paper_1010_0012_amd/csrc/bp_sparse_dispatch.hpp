@@ -4,6 +4,9 @@
 
 #include "bp_kernels.hpp"
 #include "bp_launch.hpp"
+#include "bp_walk.hpp"
+
+#include <algorithm>
 
 namespace bpk {
 
@@ -59,18 +62,38 @@ hipError_t go_sparse_wide(const UpdateArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Two synchronous iterations per launch (register windows only): the grid
-// is padded to a multiple of the XCD count for the band remap, and M = 4G
-// selects the branch-free full-row instance.
+// The column walk: strips of kBlock/G columns, split into row chunks so
+// that the workgroups fill the GPU once (as many as fit at once, given the
+// ring's LDS).
+template <int G, int TW, int MODE>
+hipError_t go_walk(const UpdateArgs& a, hipStream_t s) {
+    const size_t lds = walk_lds_bytes<G>();
+    const int per_cu = lds_blocks_per_cu(lds);
+    const int cus = cu_count();
+    if (per_cu < 1 || cus < 1) return hipErrorInvalidValue;
+    const int ns = (a.W + kBlock / G - 1) / (kBlock / G);
+    int nc = std::max(1, std::min(a.H, cus * per_cu / ns));
+    const int rc = (a.H + nc - 1) / nc;
+    nc = (a.H + rc - 1) / rc;
+    const int64_t total = (int64_t)ns * nc;
+    const int64_t per = (total + kXcds - 1) / kXcds;
+    if (per * kXcds >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sparse_walk2_kernel<G, TW, MODE, kWalkRows>), dim3((unsigned)(per * kXcds)), dim3(kBlock),
+                       lds, s, a, ns, nc, rc, (int)per);
+    return hipGetLastError();
+}
+
 // Two synchronous iterations per launch (register windows only), in the
 // mapping a.pair_layout asks for where it applies: row blocks (M = 4G and
 // an inbox plane below 2^32 bytes) in XCD column strips, row bands or one
 // wide strip per XCD, or
 // one group per pixel slot (the grid padded to a multiple of the XCD count
-// for its band remap; M = 4G selects the branch-free instance).  All
-// mappings run the same per-pixel code, so they give the same bits.
-// a.pair_cap: workgroups per CU allowed through the LDS request (0 none;
-// -1 the default, 4 for float32 arithmetic, none for double).
+// for its band remap; M = 4G selects the branch-free instance), or the
+// column walk (synchronous, M = 32 or 64; elsewhere the wide strips).  All
+// mappings run the same per-message code, so they give the same bits.
+// a.pair_cap: workgroups per CU allowed through the LDS request (0 none; -1
+// the default, 4 for float32 arithmetic, none for double; the walk's ring
+// sets its own).
 template <int G, int TW, int MODE>
 hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
     const bool rows = a.M == G * kLpl && (uint64_t)a.N * a.M * sizeof(float) < (uint64_t(1) << 32);
@@ -78,6 +101,10 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
     const size_t lds = cap > 0 ? lds_cap_bytes(cap) : 0;
     if constexpr (MODE == kSumF32) {
         if (!rows) return hipErrorInvalidValue;  // float32 arithmetic: row-block launches only
+    }
+    if constexpr (G == 8 || G == 16) {
+        const bool walk = (uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31);
+        if (rows && walk && a.pair_layout == kPairWalk && a.colour < 0) return go_walk<G, TW, MODE>(a, s);
     }
     if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
@@ -95,7 +122,7 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
         const int64_t total = (int64_t)gxp * a.H;
         if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock), lds, s, a,
-                           gxp, gx, a.pair_layout == kPairWide ? -1 : 0);
+                           gxp, gx, a.pair_layout == kPairWide || a.pair_layout == kPairWalk ? -1 : 0);
         return hipGetLastError();
     }
     if constexpr (MODE == kSumF32) {

@@ -15,7 +15,7 @@ from synth_mrf import CONFIGS, make_config, make_stereo, random_unary
 pytestmark = pytest.mark.gpu
 
 
-def gpu_grad(g32, y, M, T, alpha, n, k, fbar=None):
+def gpu_grad(g32, y, M, T, alpha, n, k, fbar=None, tuning=None):
     import torch
     from paper_1010_0012_amd import _lib as L
     from paper_1010_0012_amd.grid import Grid
@@ -24,6 +24,8 @@ def gpu_grad(g32, y, M, T, alpha, n, k, fbar=None):
     grid.set_potential(M, T, alpha, fbar)
     g = torch.from_numpy(np.ascontiguousarray(g32)).cuda()
     grid.set_unary(g)
+    if tuning:
+        grid.set_launch_tuning(*tuning)
     nbytes = L.bp_grad_workspace_bytes(grid.handle, n, k)
     gws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     L.bp_forward_ckpt(grid.handle, n, k, gws, nbytes)
@@ -96,6 +98,21 @@ def test_adjoint_deterministic_and_checkpoint_invariant():
     np.testing.assert_array_equal(a[1], c[1])
     np.testing.assert_array_equal(a[1], d[1])
     assert a[2] == c[2] == d[2]
+
+
+@pytest.mark.parametrize("M,T", [(32, 3), (64, 4), (128, 6)])
+def test_adjoint_same_bits_under_every_launch_mapping(M, T):
+    """The forward's two-iteration launches keep their first iteration's
+    state (the recompute buffers) in every mapping, the column walk's
+    included: the gradient is bitwise the same."""
+    g32, y, _, _ = make_stereo(37, 45, M, 0.05, 4.0, "rectangles", 5 + M)
+    ref = gpu_grad(g32, y, M, T, 0.8, 9, 4)
+    for tuning in (("walk", -1), ("strips", 0), ("bands", 3), ("slots", 0)):
+        say(f"M={M}: {tuning}")
+        got = gpu_grad(g32, y, M, T, 0.8, 9, 4, tuning=tuning)
+        np.testing.assert_array_equal(got[3], ref[3])
+        np.testing.assert_array_equal(got[1], ref[1])
+        assert got[2] == ref[2]
 
 
 def test_autograd_function():

@@ -10,8 +10,8 @@ from synth_mrf import random_unary
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["strips", "wide", "bands", "slots"]
-CAPS = [-1, 0, 4, 3, 1]
+LAYOUTS = ["strips", "wide", "bands", "slots", "walk"]
+CAPS = [-1, 0, 4, 3, 2, 1]  # the walk ignores the cap (its LDS ring sets two workgroups per CU)
 CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (37, 70, 64, 4, 0.5, "sum", "sync", "f64"),
     (37, 70, 64, 4, 0.5, "max", "sync", "f64"),
@@ -20,6 +20,14 @@ CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (30, 50, 48, 3, 0.7, "sum", "sync", "f64"),   # M not 4G: one group per slot whatever the layout
     (33, 90, 64, 4, 0.5, "sum", "sync", "f32"),
     (21, 34, 128, 6, 0.3, "sum", "sync", "f32"),
+    # column walk (M = 32, 64; M = 128 runs the wide strips): strips of 256/G
+    # columns (a ragged last strip), row chunks with halo rows, a single row,
+    # and rows of missing senders at every border
+    (5, 37, 32, 3, 0.8, "sum", "sync", "f64"),
+    (1, 20, 64, 4, 0.5, "max", "sync", "f64"),
+    (64, 16, 128, 8, 0.4, "max", "sync", "f64"),
+    (300, 40, 64, 4, 0.5, "sum", "sync", "f32"),
+    (97, 530, 32, 2, 1.1, "sum", "sync", "f32"),
 ]
 
 
@@ -52,7 +60,7 @@ def test_every_mapping_gives_the_same_bits(case):
     best = grid.autotune(mode, schedule, 2)
     layout, cap = grid.get_launch_tuning()
     say(f"{case}: autotuned {layout}, cap {cap}, {best:.1f} us per iteration")
-    assert best > 0 and layout in LAYOUTS and cap in (-1, 0, 4, 3)
+    assert best > 0 and layout in LAYOUTS and cap in (-1, 0, 4, 3, 2)
     np.testing.assert_array_equal(messages(grid, mode, schedule), ref)
     grid.close()
 
@@ -64,7 +72,7 @@ def test_tuning_argument_errors():
     grid = Grid(8, 8)
     grid.set_potential(16, 2, 1.0)
     grid.set_unary(torch.from_numpy(random_unary(8, 8, 16, 1)).cuda())
-    for layout, cap in ((4, -1), (-1, 0), (0, -2), (0, 65)):
+    for layout, cap in ((5, -1), (-1, 0), (0, -2), (0, 65)):
         with pytest.raises(L.BPError) as e:
             L.bp_set_launch_tuning(grid.handle, layout, cap)
         assert e.value.status == L.BP_EINVAL
