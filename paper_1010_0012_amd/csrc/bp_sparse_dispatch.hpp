@@ -103,8 +103,11 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
         if (!rows) return hipErrorInvalidValue;  // float32 arithmetic: row-block launches only
     }
     if constexpr (G == 8 || G == 16) {
-        const bool walk = (uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31);
-        if (rows && walk && a.pair_layout == kPairWalk && a.colour < 0) return go_walk<G, TW, MODE>(a, s);
+        // the walk where it applies and its LDS ring fits the device; else the wide strips
+        const bool walk = a.pair_layout == kPairWalk && a.colour < 0 &&
+                          (uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31);
+        if (rows && walk && lds_blocks_per_cu(walk_lds_bytes<G>()) >= 1 && cu_count() >= 1)
+            return go_walk<G, TW, MODE>(a, s);
     }
     if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
