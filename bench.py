@@ -254,11 +254,13 @@ def grad_leg(reps=3):
     return out
 
 
-def sweep_leg(grid, cfg, reps=2):
+def sweep_leg(grid, cfg, reps=2, arith="f32"):
     """Directional sweeps (Sec. 6): one sweep = passes left, right, up and down
     = every directed message once, sequential along each row or column.
     Time per sweep on the benchmark grid and at the paper's 144 x 192 shape
-    (sparse vs dense there, beside the paper's CPU ratio of about 3.1)."""
+    (sparse vs dense there, beside the paper's CPU ratio of about 3.1), in
+    double arithmetic, and the sparse sum-product sweep in float32 as well
+    (_f32 keys).  The benchmark grid gets `arith` back afterwards."""
     import torch
 
     from paper_1010_0012_amd.grid import Grid
@@ -272,15 +274,19 @@ def sweep_leg(grid, cfg, reps=2):
             gr.set_potential(c.M, c.T, c.alpha)
             gr.set_unary(torch.from_numpy(g32).cuda())
         updates = c.n_directed_edges * c.M
-        for mode, dense in (("sum", False), ("max", False), ("sum", True)):
+        for mode, dense, ar in (("sum", False, "f64"), ("max", False, "f64"), ("sum", True, "f64"),
+                                ("sum", False, "f32")):
+            gr.set_arithmetic(ar)
             ms = time_launches(gr, mode, 2, "sweep", dense, reps)  # ms per sweep
-            key = f"sweep_{name}_{'dense' if dense else 'sparse'}_{mode}"
+            key = f"sweep_{name}_{'dense' if dense else 'sparse'}_{mode}" + ("_f32" if ar == "f32" else "")
             out[key + "_us"] = ms * 1e3
             out[key + "_updates_per_s"] = updates / (ms * 1e-3)
             log(f"bench: {key}: {ms * 1e3:.1f} us/sweep, {updates / (ms * 1e-3):.3e} updates/s")
         out[f"sweep_{name}_dense_over_sparse_sum"] = out[f"sweep_{name}_dense_sum_us"] / out[f"sweep_{name}_sparse_sum_us"]
         if own:
             gr.close()
+        else:
+            gr.set_arithmetic(arith)
     return out
 
 
@@ -775,7 +781,7 @@ def main():
                 f"{d_us / best[mode]:.2f}x best vs best; dense at {flops / (d_us * 1e-6) / 1e12:.1f} TF/s "
                 f"({100 * flops / (d_us * 1e-6) / 78.6e12:.0f}% of the FP64 peak)")
         extra["sparse_over_dense_target"] = cfg.M / (2 * cfg.T + 1) * 0.5
-    for name, leg in (("sweep", lambda: sweep_leg(grid, cfg)), ("multiscale", lambda: multiscale_leg(grid, cfg)),
+    for name, leg in (("sweep", lambda: sweep_leg(grid, cfg, arith=args.arith)), ("multiscale", lambda: multiscale_leg(grid, cfg)),
                       ("general", lambda: general_leg(g, cfg)), ("factor", factor_leg), ("fbar0", fbar_zero_leg),
                       ("grad", grad_leg), ("batch", batch_leg), ("walk", walk_leg)):
         if name in legs:

@@ -160,10 +160,10 @@ int bp_iterate(bp_grid* grid, int32_t mode, int32_t n_iters, int32_t schedule);
  * not bit for bit), where it is compiled: sum-product of the window
  * potential with fbar > 0 (with fbar = 0 messages reach zero and the
  * denormal range, where float32 products lose their precision), the
- * synchronous or checkerboard schedule, T within the
+ * synchronous, checkerboard or sweep schedule, T within the
  * register windows (T <= 16, 12 for M <= 16), M = 4 * ceil-pow2(M / 4) (16,
  * 32, 64, 128, 256) and 4*H*W*M bytes below 2^32.  Everything else (max-
- * product, sweeps, dense, general potentials, multi-scale, the gradient)
+ * product, dense, general potentials, multi-scale, the gradient)
  * computes in double whatever this says; batches have their own setting
  * (bp_batch_set_arithmetic).  BP_EINVAL for another value. */
 enum bp_arith { BP_ARITH_F64 = 0, BP_ARITH_F32 = 1 };

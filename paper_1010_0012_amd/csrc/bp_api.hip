@@ -134,9 +134,9 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
     const float* tab = (!dense && kmode == bpk::kSum) ? G->tab_w : G->tab_f;
     // float32 arithmetic (BP_ARITH_F32) where it is compiled: sum-product of
     // the window potential with fbar > 0 (every message entry then stays at
-    // or above fbar/M, so h cannot underflow), synchronous or checkerboard, a
-    // register window, full label rows (M = 4G), inbox planes below 2^32 bytes
-    const bool f32 = G->arith_f32 && kmode == bpk::kSum && !dense && schedule != BP_SCHED_SWEEP && G->fbar > 0.0f &&
+    // or above fbar/M, so h cannot underflow), any schedule, a register
+    // window, full label rows (M = 4G), inbox planes below 2^32 bytes
+    const bool f32 = G->arith_f32 && kmode == bpk::kSum && !dense && G->fbar > 0.0f &&
                      bpk::sparse_variant_tw(G->M, G->T) >= 0 && G->M == 4 * bpk::lanes_for(G->M) &&
                      (uint64_t)G->N * G->M * sizeof(float) < (uint64_t(1) << 32);
     const int kupd = f32 ? bpk::kSumF32 : kmode;
@@ -152,7 +152,7 @@ int iterate(bp_grid* G, int mode, int n, int schedule, bool dense) {
                 a.both = 1;
                 a.eq10 = eq10;
                 memcpy(a.tab, tab, sizeof a.tab);
-                hipError_t e = bpk::launch_sweep(a, kmode, dense, G->stream);
+                hipError_t e = bpk::launch_sweep(a, kupd, dense, G->stream);
                 if (e != hipSuccess) return hip_fail(e, "sweep pass launch");
             }
         }

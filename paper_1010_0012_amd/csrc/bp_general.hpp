@@ -290,8 +290,8 @@ __global__ __launch_bounds__(kSweepBlock) void general_sweep_kernel(GenArgs a, i
         }
         general_message<G, MODE, EQ10, STAGE>(a, v, k, dir, h, hs, top_v, top_i, pos, m);
     };
-    if (a.u.M == G * kLpl) sweep_walk<G, true>(a.u, msg);
-    else sweep_walk<G, false>(a.u, msg);
+    if (a.u.M == G * kLpl) sweep_walk<G, true, double>(a.u, msg);
+    else sweep_walk<G, false, double>(a.u, msg);
 }
 
 }  // namespace bpk

@@ -19,6 +19,8 @@
 // one launch.
 #pragma once
 
+#include <type_traits>
+
 #include "bp_kernels.hpp"
 
 namespace bpk {
@@ -57,7 +59,7 @@ __device__ __forceinline__ void sweep_block_dir(const UpdateArgs& a, int& blk, i
 // m; it may hold block barriers, since every group of the workgroup makes
 // the same number of steps (groups past the last scanline run on the last
 // scanline's inputs and store nothing).  FULL: M == 4G.
-template <int G, bool FULL, typename Msg>
+template <int G, bool FULL, typename HT, typename Msg>
 __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     constexpr int CAP = G * kLpl;
     constexpr int LPB = kSweepBlock / G;  // scanlines per workgroup
@@ -133,9 +135,9 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
         for (int j = 0; j < kAhead; ++j) {
             const int t = t0 + j;
             if (t >= steps) break;  // the same for every group of the workgroup
-            double h[kLpl];  // Eq. 5, in double as in the other updates
+            HT h[kLpl];  // Eq. 5, in the update's arithmetic (double, or float32 for kSumF32)
 #pragma unroll
-            for (int i = 0; i < kLpl; ++i) h[i] = (((double)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
+            for (int i = 0; i < kLpl; ++i) h[i] = (((HT)rg[j][i] * r0[j][i]) * r1[j][i]) * carry[i];
             load_raw(gp, s0p, s1p, rg[j], r0[j], r1[j]);
             advance(t + kAhead);
             float m[kLpl];
@@ -149,8 +151,12 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     }
 }
 
+// kSumF32: the float32 arithmetic of the synchronous and checkerboard
+// kernels (sum_message_f), register windows and M = 4G only.
 template <int G, int TW, int MODE, int KIND, bool FULL>
 __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
+    static_assert(MODE != kSumF32 || (KIND == kSweepReg && FULL), "float32 sweeps: register windows, M = 4G");
+    using HT = typename std::conditional<MODE == kSumF32, float, double>::type;
     constexpr int CAP = G * kLpl;
     extern __shared__ double lds_d[];
     const int pos = threadIdx.x & (G - 1);
@@ -192,8 +198,10 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
         __syncthreads();
     }
 
-    sweep_walk<G, FULL>(a, [&](const double (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
-        if constexpr (KIND == kSweepRegEq10) {
+    sweep_walk<G, FULL, HT>(a, [&](const HT (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
+        if constexpr (MODE == kSumF32) {
+            sum_message_f<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
+        } else if constexpr (KIND == kSweepRegEq10) {
             max_message_eq10_d<G, TW>(h, a.tab, a.fbar, a.T, pos, a.M, x0, full, lds_d + grp * eq10_row_doubles(G), m);
         } else if constexpr (KIND == kSweepReg) {
             if constexpr (MODE == kSum) sum_message_d<G, TW>(h, a.dtab, a.fbar_d, pos, a.M, x0, full, m);

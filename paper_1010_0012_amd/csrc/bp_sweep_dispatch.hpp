@@ -1,5 +1,6 @@
 // Instantiation table and dispatch of the sweep-pass kernels, included once
-// per mode (bp_launch_sweep_sum.hip, bp_launch_sweep_max.hip).
+// per mode (bp_launch_sweep_sum.hip, bp_launch_sweep_sumf.hip,
+// bp_launch_sweep_max.hip).
 #pragma once
 
 #include "bp_launch.hpp"
@@ -27,8 +28,12 @@ hipError_t go_sweep_full(const UpdateArgs& a, hipStream_t s) {
 // then carry no per-label bounds.
 template <int G, int TW, int MODE, int KIND>
 hipError_t go_sweep(const UpdateArgs& a, hipStream_t s) {
-    return a.M == G * kLpl ? go_sweep_full<G, TW, MODE, KIND, true>(a, s)
-                           : go_sweep_full<G, TW, MODE, KIND, false>(a, s);
+    if constexpr (MODE == kSumF32) {
+        return a.M == G * kLpl ? go_sweep_full<G, TW, MODE, KIND, true>(a, s) : hipErrorInvalidValue;
+    } else {
+        return a.M == G * kLpl ? go_sweep_full<G, TW, MODE, KIND, true>(a, s)
+                               : go_sweep_full<G, TW, MODE, KIND, false>(a, s);
+    }
 }
 
 template <int G, int MODE, int I = 0>
@@ -42,6 +47,8 @@ hipError_t sweep_tw(const UpdateArgs& a, int tw, hipStream_t s) {
             return go_sweep<G, TW, MODE, kSweepReg>(a, s);
         }
         return sweep_tw<G, MODE, I + 1>(a, tw, s);
+    } else if constexpr (MODE == kSumF32) {
+        return hipErrorInvalidValue;  // float32 arithmetic: register windows only
     } else {
         if (a.eq10) return hipErrorInvalidValue;  // Eq. 10 beyond the register windows runs the general kernel
         return go_sweep<G, 0, MODE, kSweepLds>(a, s);
@@ -51,7 +58,7 @@ hipError_t sweep_tw(const UpdateArgs& a, int tw, hipStream_t s) {
 template <int G, int MODE>
 hipError_t sweep_g(const UpdateArgs& a, bool dense, hipStream_t s) {
     if (dense) {
-        if constexpr (G <= 32) return go_sweep<G, 0, MODE, kSweepDense>(a, s);
+        if constexpr (G <= 32 && MODE != kSumF32) return go_sweep<G, 0, MODE, kSweepDense>(a, s);
         else return hipErrorInvalidValue;
     }
     return sweep_tw<G, MODE>(a, sparse_tw(a.M, a.T), s);

@@ -176,12 +176,13 @@ F32_SHAPES = [(5, 7, 16, 2, 1.0, None), (23, 41, 64, 4, 0.5, None), (19, 150, 16
               (12, 14, 32, 5, 0.6, 0.5), (1, 40, 16, 2, 1.0, None), (40, 1, 32, 3, 0.8, None)]
 
 
-@pytest.mark.parametrize("schedule", ["sync", "checkerboard"])
+@pytest.mark.parametrize("schedule", ["sync", "checkerboard", "sweep"])
 @pytest.mark.parametrize("shape", F32_SHAPES, ids=_id)
 def test_f32_arithmetic(shape, schedule):
     """Sum-product with float32 arithmetic: pair launches equal single
-    launches bit for bit, the parity rule against the oracle holds, and the
-    result is within 1e-6 of the double-arithmetic kernels."""
+    launches bit for bit (sweeps have no pairs), the parity rule against the
+    oracle holds, and the result is within 1e-6 of the double-arithmetic
+    kernels."""
     H, W, M, T, alpha, fbar = shape
     g32 = random_unary(H, W, M, 700 + F32_SHAPES.index(shape))
     tag = f"f32 arithmetic sum {schedule} {_id(shape)}"
