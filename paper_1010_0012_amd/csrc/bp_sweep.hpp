@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "bp_kernels.hpp"
+#include "bp_walk.hpp"
 
 namespace bpk {
 
@@ -151,6 +152,114 @@ __device__ __forceinline__ void sweep_walk(const UpdateArgs& a, Msg&& msg) {
     }
 }
 
+// sweep_walk for M = 4G and planes below 2^31 bytes, with the inputs
+// staged through LDS instead of registers.  In the register ring the
+// compiler cannot carry its load counts across the unrolled loop's back
+// edge and waits for every load in flight once per kAhead steps, a full
+// memory latency each time.  Here each step's three input rows (unary and
+// the two perpendicular inbox rows; 16 bytes per lane, one 1 KB load per
+// row for the wave) go by direct global-to-LDS loads into a ring of
+// kStage slots, kStage steps ahead, and the waits are explicit: every step
+// issues three loads and one buffer store (offset beyond the plane where
+// the group has no scanline, and in the prologue), and memory operations
+// complete in issue order, so a step's rows have landed once no more than
+// the operations issued after them are outstanding.  The arithmetic and the
+// order of the messages are sweep_walk's.
+template <int G, typename HT, typename Msg>
+__device__ __forceinline__ void sweep_walk_staged(const UpdateArgs& a, Msg&& msg) {
+    static_assert(kSweepBlock == 64, "one wave per workgroup");
+    constexpr int kStage = 16;
+    __shared__ __attribute__((aligned(1024))) char ring[kStage][3][1024];
+    constexpr int LPB = kSweepBlock / G;
+    const int pos = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int lane = threadIdx.x & 63;
+    int blk, dir;
+    sweep_block_dir(a, blk, dir);
+    const bool horiz = dir == kLeft || dir == kRight;
+    const bool forward = dir == kRight || dir == kDown;
+    const int n_lines = horiz ? a.H : a.W;
+    const int len = horiz ? a.W : a.H;
+    const bool live = blk * LPB + grp < n_lines;
+    const int line = live ? blk * LPB + grp : n_lines - 1;
+    const int M = 4 * G;
+    const size_t plane = (size_t)a.N * M;
+    const int side0 = horiz ? kUp : kLeft;
+    const int side1 = horiz ? kDown : kRight;
+    const float* in0 = line > 0 ? a.in + side0 * plane : kOnesRow.v;
+    const float* in1 = line + 1 < n_lines ? a.in + side1 * plane : kOnesRow.v;
+    const long stride0 = line > 0 ? M : 0, stride1 = line + 1 < n_lines ? M : 0;
+    const int step_q = dir == kLeft ? -1 : dir == kRight ? 1 : dir == kUp ? -a.W : a.W;
+    const int steps = len - 1;
+    if (steps <= 0) return;  // the same for every group
+    const long dpix = (forward ? 1L : -1L) * (horiz ? 1L : (long)a.W);
+    const long p0 = horiz ? (long)line * a.W + (forward ? 0 : len - 1) : (long)(forward ? 0 : len - 1) * a.W + line;
+    const int x0 = pos * kLpl;
+    // this lane's 16 bytes of the t-th sender's rows (t clamped to the last)
+    auto src = [&](int t, int k) -> const char* {
+        const long p = p0 + (long)min(t, steps - 1) * dpix;
+        const float* b = k == 0 ? a.g + p * M : k == 1 ? in0 + p * stride0 : in1 + p * stride1;
+        return (const char*)(b + x0);
+    };
+    const uint32_t plane_b = (uint32_t)(plane * sizeof(float));
+    const __amdgpu_buffer_rsrc_t out_r =
+        __builtin_amdgcn_make_buffer_rsrc(a.out + opposite(dir) * plane, 0, (int)plane_b, kWalkRsrcWord3);
+    const float zero[kLpl] = {0.0f, 0.0f, 0.0f, 0.0f};
+    auto issue = [&](int t) {
+        char* dst = &ring[t % kStage][0][0];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            __builtin_amdgcn_global_load_lds((walk_gptr)src(t, k), (walk_lptr)(dst + k * 1024), 16, 0, 0);
+    };
+    // The compiler barriers keep each step's loads ahead of its store (a
+    // store moved above a load would leave the wait one operation short).
+#pragma unroll
+    for (int t = 0; t < kStage; ++t) {
+        issue(t);
+        asm volatile("" ::: "memory");
+        walk_store(out_r, kWalkDrop, zero);
+        asm volatile("" ::: "memory");
+    }
+    float carry[kLpl];
+#pragma unroll
+    for (int i = 0; i < kLpl; ++i) carry[i] = 1.0f;  // first sender: no carry
+    // The rows of step t + 1 are read from LDS during step t, off the
+    // carried message's dependency chain.
+    float rg[kLpl], r0[kLpl], r1[kLpl];
+    auto read_rows = [&](int t) {
+        const char* sl = &ring[t % kStage][0][0] + lane * 16;
+        walk_read(sl, rg);
+        walk_read(sl + 1024, r0);
+        walk_read(sl + 2048, r1);
+    };
+    walk_wait<1 + 4 * (kStage - 1)>();  // step 0's loads
+    asm volatile("" ::: "memory");
+    read_rows(0);
+    for (int t = 0; t < steps; ++t) {
+        HT h[kLpl];  // Eq. 5, in the update's arithmetic, sweep_walk's factor order
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) h[i] = (((HT)rg[i] * r0[i]) * r1[i]) * carry[i];
+        // step t + 1's loads: after them, the store of their step and four
+        // operations for each of the kStage - 2 steps since
+        walk_wait<1 + 4 * (kStage - 2)>();
+        asm volatile("" ::: "memory");
+        read_rows(t + 1);
+        asm volatile("" ::: "memory");
+        issue(t + kStage);  // into step t's slot, read before h above
+        asm volatile("" ::: "memory");
+        const long p = p0 + (long)t * dpix;
+        const int s = horiz ? (int)(p - (long)line * a.W) : (int)(p / a.W);
+        float m[kLpl];
+        msg(h, horiz ? line : s, horiz ? s : line, dir, m);
+        const uint32_t off = (uint32_t)(((p + step_q) * M + x0) * sizeof(float));
+        walk_store(out_r, live ? off : kWalkDrop, m);
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < kLpl; ++i) carry[i] = m[i];
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at exit
+}
+
 // kSumF32: the float32 arithmetic of the synchronous and checkerboard
 // kernels (sum_message_f), register windows and M = 4G only.
 template <int G, int TW, int MODE, int KIND, bool FULL>
@@ -198,7 +307,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
         __syncthreads();
     }
 
-    sweep_walk<G, FULL, HT>(a, [&](const HT (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
+    auto msg = [&](const HT (&h)[kLpl], int, int, int, float (&m)[kLpl]) {
         if constexpr (MODE == kSumF32) {
             sum_message_f<G, TW>(h, a.tab, a.fbar, pos, a.M, x0, full, m);
         } else if constexpr (KIND == kSweepRegEq10) {
@@ -257,7 +366,14 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_pass_kernel(UpdateArgs a) {
             normalise_d<G>(u, a.M, x0, full, m);
             __syncthreads();  // every group done reading hs before the next step writes it
         }
-    });
+    };
+    if constexpr (FULL && KIND == kSweepReg) {
+        if ((uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31)) {
+            sweep_walk_staged<G, HT>(a, msg);
+            return;
+        }
+    }
+    sweep_walk<G, FULL, HT>(a, msg);
 }
 
 }  // namespace bpk

@@ -275,15 +275,19 @@ __global__ __launch_bounds__(kBlock) void sparse_walk2_kernel(UpdateArgs a, int 
 #pragma unroll
     for (int i = 0; i < kLpl; ++i) w.g_prev[i] = w.hl_prev[i] = w.hr_prev[i] = w.dn_prev[i] = w.dn_prev2[i] = 1.0f;
     const float zero[kLpl] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // The compiler barriers keep each step's loads ahead of its stores (a
+    // store moved above a load would leave the waits one operation short).
 #pragma unroll
     for (int t = 0; t < P; ++t) {
         issue_row(ws.r0 - 1 + t, t);
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int o = 0; o < 4; ++o) walk_store(ws.out_r[o], kWalkDrop, zero);
         if (with_mid) {
 #pragma unroll
             for (int o = 0; o < 4; ++o) walk_store(ws.mid_r[o], kWalkDrop, zero);
         }
+        asm volatile("" ::: "memory");
     }
     const int steps = ws.r1 - ws.r0 + 2;  // rows r0 - 1 .. r1
     for (int k = 0; k < steps; ++k) {
@@ -292,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void sparse_walk2_kernel(UpdateArgs a, int 
         else walk_wait<4 + (P - 1) * (S::NI + 4)>();
         walk_barrier();
         issue_row(j + P, (k + P) % D);
+        asm volatile("" ::: "memory");
         walk_step<G, TW, MODE>(a, walk_lds + (k % D) * S::SLOT + pos * 16, ws.ip, ws.c, j, k >= 2, true, ws.row_b,
                                ws.out_r, ws.mid_r, with_mid, w);
     }
