@@ -48,10 +48,11 @@ def alg_bytes_per_sync_iter(cfg):
 
 KERNEL_SOURCES = ["paper_1010_0012_amd/csrc/bp_device.hpp", "paper_1010_0012_amd/csrc/bp_kernels.hpp",
                   "paper_1010_0012_amd/csrc/bp_sparse_dispatch.hpp", "paper_1010_0012_amd/csrc/bp_walk.hpp",
+                  "paper_1010_0012_amd/csrc/bp_tile.hpp",
                   "paper_1010_0012_amd/csrc/bp_launch_sparse_sum.hip",
                   "paper_1010_0012_amd/csrc/bp_launch_sparse_sumf.hip",
                   "paper_1010_0012_amd/csrc/bp_launch_misc.hip"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_pair_rows_f32_stereo480x640.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sparse_pair_tile_f32_stereo480x640.json")
 
 
 def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, layout="wide"):
@@ -62,7 +63,8 @@ def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, layout="wide"):
     fit 32-bit byte offsets, unless the launch mapping is one group per
     pixel slot (mode 2: sum-product in float32 arithmetic, row blocks only);
     the column walk (synchronous, M = 32 or 64, planes below 2^31 bytes)
-    where the mapping is the walk."""
+    or the tile launch (synchronous, M = 32 or 64) where the mapping is
+    one of those."""
     G = 4
     while G * 4 < M and G < 64:
         G *= 2
@@ -72,6 +74,8 @@ def sparse_kernel_name(M, T, mode, pair=False, n_pixels=0, layout="wide"):
         return f"sparse_update_wide_kernel<{G}, {mode}>"
     if pair and layout == "walk" and M == 4 * G and G in (8, 16) and n_pixels * M * 4 <= 2 ** 31:
         return f"sparse_walk2_kernel<{G}, {tw}, {mode}, 2>"
+    if pair and layout == "tile" and M == 4 * G and G in (8, 16) and n_pixels * M * 4 < 2 ** 32:
+        return f"sparse_tile2_kernel<{G}, {tw}, {mode}>"
     row_blocks = mode == 2 or layout != "slots"
     if pair and row_blocks and M == 4 * G and n_pixels * M * 4 < 2 ** 32:
         return f"sparse_update2_rows_kernel<{G}, {tw}, {mode}>"
@@ -464,8 +468,9 @@ def factor_leg(reps=3, n_iters=10):
 def walk_leg(reps=5, n_iters=20):
     """The two-iteration launch on a 480 x 640 grid with M = 32 (T = 3,
     alpha = 0.5, float32 arithmetic, seeded uniform unary): wide column
-    strips against the column walk (each grid row staged once in LDS), per
-    launch, and what the autotuner picks.  Algorithmic bytes 4 M (2E + N)."""
+    strips, the column walk (each grid row staged once in LDS) and the tile
+    launch (4 x 8 pixel tiles and their halo staged in LDS), per launch, and
+    what the autotuner picks.  Algorithmic bytes 4 M (2E + N)."""
     import torch
 
     from paper_1010_0012_amd.grid import Grid
@@ -477,7 +482,7 @@ def walk_leg(reps=5, n_iters=20):
     grid.set_unary(torch.from_numpy(random_unary(H, W, M, 3)).cuda())
     alg = 4 * M * (2 * (2 * H * W - H - W) * 2 + H * W)
     out = {"walk_workload": f"{H}x{W}, M={M}, T={T}, sum-product sync, float32 arithmetic, pair launches"}
-    for layout in ("wide", "walk"):
+    for layout in ("wide", "walk", "tile"):
         grid.set_launch_tuning(layout, -1)
         best = min(time_launches(grid, "sum", n_iters, "sync", False, 1, iters_per_launch=2) for _ in range(reps))
         out[f"walk_leg_{layout}_pair_launch_us"] = best * 1e3
@@ -487,6 +492,7 @@ def walk_leg(reps=5, n_iters=20):
     grid.autotune("sum", "sync", 4)
     out["walk_leg_autotuned"] = list(grid.get_launch_tuning())
     out["walk_leg_wide_over_walk"] = out["walk_leg_wide_pair_launch_us"] / out["walk_leg_walk_pair_launch_us"]
+    out["walk_leg_wide_over_tile"] = out["walk_leg_wide_pair_launch_us"] / out["walk_leg_tile_pair_launch_us"]
     grid.close()
     return out
 
@@ -739,11 +745,15 @@ def main():
             # (checkerboard) each; dense launches run one
             n = cfg.iters if sched == "sync" else 2 * cfg.iters
             per_launch = 1 if dense else 2
+            key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
+            if not dense and args.tuning is None:
+                # the sparse launches' mapping, tuned for this mode and schedule
+                grid.autotune(mode, sched, 4)
+                extra[key + "_launch_mapping"] = list(grid.get_launch_tuning())
             ms = time_launches(grid, mode, n, sched, dense, 2, iters_per_launch=per_launch)
             step = ms / per_launch                                   # one iteration or one pass
             per_iter = step * (1 if sched == "sync" else 2)          # every message updated once
             unit = "iteration" if sched == "sync" else "pass"
-            key = f"{'dense' if dense else 'sparse'}_{mode}_{sched}"
             # the state is that of a whole solve from the uniform start
             grid.readout(beliefs, labels)
             extra[key + "_accuracy"] = golden_accuracy(f"{cfg.name}_{mode}_{sched}", beliefs.cpu().numpy(),
@@ -753,6 +763,7 @@ def main():
             extra[key + f"_us_per_{unit}"] = step * 1e3
             log(f"bench: {key}: {ms * 1e3:.1f} us per launch, {step * 1e3:.1f} us per {unit}, "
                 f"{updates_per_iter / (per_iter * 1e-3):.4e} updates/s")
+        grid.set_launch_tuning(*tuning)  # the headline's mapping for the legs that follow
     if {"sparse", "dense"} <= legs:
         # sparse O(mM) against dense O(M^2), like for like: one iteration per
         # launch on both sides, and each side's fastest form (the sparse pair

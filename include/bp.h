@@ -184,10 +184,13 @@ int bp_set_arithmetic(bp_grid* grid, int32_t arith);
  * BP_PAIR_STRIPS); BP_PAIR_WALK, for synchronous launches with M = 32 or 64,
  * one workgroup per strip of columns walking down a chunk of rows, each
  * grid row's unary and inbox staged once in LDS (checkerboard pairs and
- * other M run BP_PAIR_WIDE).  cap: the most workgroups per compute unit the
+ * other M run BP_PAIR_WIDE); BP_PAIR_TILE, for synchronous launches with
+ * M = 32 or 64, one workgroup per 4-row tile whose rows and halo are staged
+ * once in LDS (checkerboard pairs and other M run BP_PAIR_WIDE).  cap: the
+ * most workgroups per compute unit the
  * launch's LDS request allows (0 none, 1..64, -1 the default: 4 with float32
- * arithmetic, none with double; BP_PAIR_WALK's LDS ring sets its own, two
- * per CU, whatever the cap).  Every setting computes the same messages
+ * arithmetic, none with double; BP_PAIR_WALK's LDS ring and BP_PAIR_TILE's
+ * tile set their own, whatever the cap).  Every setting computes the same messages
  * bit for bit; only the speed differs.  BP_EINVAL for a null handle, a
  * layout outside the enum or a cap outside -1..64.  Kept per grid; used by
  * every launch of the grid, including bp_forward_ckpt and multi-scale. */
@@ -210,13 +213,14 @@ enum bp_pair_layout {
     BP_PAIR_BANDS = 1,
     BP_PAIR_SLOTS = 2,
     BP_PAIR_WIDE = 3,
-    BP_PAIR_WALK = 4
+    BP_PAIR_WALK = 4,
+    BP_PAIR_TILE = 5
 };
 int bp_set_launch_tuning(bp_grid* grid, int32_t layout, int32_t cap);
 int bp_get_launch_tuning(const bp_grid* grid, int32_t* layout, int32_t* cap);
 
 /* Time the current setting, every row-block and slot layout above with caps
- * 0, 4 and 3, and BP_PAIR_WALK, on this grid's own state, and keep the fastest (another setting
+ * 0, 4 and 3, BP_PAIR_WALK and BP_PAIR_TILE, on this grid's own state, and keep the fastest (another setting
  * replaces the best only when at least 1% faster) for `mode` and `schedule`
  * (BP_SCHED_SYNC or
  * BP_SCHED_CHECKERBOARD): trial_iters iterations (even, >= 2) per candidate

@@ -22,7 +22,7 @@ BP_SCHED_SYNC, BP_SCHED_CHECKERBOARD, BP_SCHED_SWEEP = 0, 1, 2
 BP_MAX_LABELS = 256
 BP_FBAR_TIED = -1.0
 BP_ARITH_F64, BP_ARITH_F32 = 0, 1
-BP_PAIR_STRIPS, BP_PAIR_BANDS, BP_PAIR_SLOTS, BP_PAIR_WIDE, BP_PAIR_WALK = 0, 1, 2, 3, 4
+BP_PAIR_STRIPS, BP_PAIR_BANDS, BP_PAIR_SLOTS, BP_PAIR_WIDE, BP_PAIR_WALK, BP_PAIR_TILE = 0, 1, 2, 3, 4, 5
 
 _c_int, _c_i32, _c_i64, _c_f, _vp = ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p
 

@@ -258,12 +258,12 @@ int bp_message_stats(bp_grid* G, float* max_change, int32_t* non_finite) {
 
 static_assert(BP_PAIR_STRIPS == bpk::kPairStrips && BP_PAIR_BANDS == bpk::kPairBands &&
                   BP_PAIR_SLOTS == bpk::kPairSlots && BP_PAIR_WIDE == bpk::kPairWide &&
-                  BP_PAIR_WALK == bpk::kPairWalk,
+                  BP_PAIR_WALK == bpk::kPairWalk && BP_PAIR_TILE == bpk::kPairTile,
               "the header's layouts are the kernels'");
 
 int bp_set_launch_tuning(bp_grid* G, int32_t layout, int32_t cap) {
     if (!G) return fail(BP_EINVAL, "null handle");
-    if (layout < BP_PAIR_STRIPS || layout > BP_PAIR_WALK) return fail(BP_EINVAL, "bad layout %d", layout);
+    if (layout < BP_PAIR_STRIPS || layout > BP_PAIR_TILE) return fail(BP_EINVAL, "bad layout %d", layout);
     if (cap < -1 || cap > 64) return fail(BP_EINVAL, "bad workgroups-per-CU cap %d", cap);
     G->pair_layout = layout;
     G->pair_cap = cap;
@@ -304,6 +304,7 @@ int bp_autotune(bp_grid* G, int32_t mode, int32_t schedule, int32_t trial_iters,
     for (int layout : {BP_PAIR_WIDE, BP_PAIR_STRIPS, BP_PAIR_BANDS, BP_PAIR_SLOTS})
         for (int cap : {0, 4, 3}) cands.push_back({layout, cap});
     cands.push_back({BP_PAIR_WALK, -1});
+    cands.push_back({BP_PAIR_TILE, -1});
     for (const Cand& c : cands) {
         G->pair_layout = c.layout;
         G->pair_cap = c.cap;

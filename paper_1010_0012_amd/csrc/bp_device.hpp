@@ -30,7 +30,7 @@ constexpr int kMaxTab = 256;        // potential table entries (|d| < BP_MAX_LAB
 constexpr int kDTab = 32;           // double window weights carried in the arguments (|d| <= 31)
 
 // Mappings of the two-iteration launch (UpdateArgs::pair_layout).
-enum PairLayout { kPairStrips = 0, kPairBands = 1, kPairSlots = 2, kPairWide = 3, kPairWalk = 4 };
+enum PairLayout { kPairStrips = 0, kPairBands = 1, kPairSlots = 2, kPairWide = 3, kPairWalk = 4, kPairTile = 5 };
 
 // kSumF32: sum-product with float32 arithmetic (BP_ARITH_F32), used by the
 // synchronous and checkerboard window kernels only.

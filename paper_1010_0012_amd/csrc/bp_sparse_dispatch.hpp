@@ -4,6 +4,7 @@
 
 #include "bp_kernels.hpp"
 #include "bp_launch.hpp"
+#include "bp_tile.hpp"
 #include "bp_walk.hpp"
 
 #include <algorithm>
@@ -83,6 +84,20 @@ hipError_t go_walk(const UpdateArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The tile launch: TR x TC pixel tiles, tile columns padded to a multiple
+// of the XCD count for the wide-strip order.
+template <int G, int TW, int MODE>
+hipError_t go_tile(const UpdateArgs& a, hipStream_t s) {
+    using S = TileShape<G>;
+    const int tiles_x = (a.W + S::TC - 1) / S::TC, tiles_y = (a.H + S::TR - 1) / S::TR;
+    const int txp = (tiles_x + kXcds - 1) / kXcds * kXcds;
+    const int64_t total = (int64_t)txp * tiles_y;
+    if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sparse_tile2_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock), tile_lds_bytes<G>(),
+                       s, a, txp, tiles_x);
+    return hipGetLastError();
+}
+
 // Two synchronous iterations per launch (register windows only), in the
 // mapping a.pair_layout asks for where it applies: row blocks (M = 4G and
 // an inbox plane below 2^32 bytes) in XCD column strips, row bands or one
@@ -108,6 +123,8 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
                           (uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31);
         if (rows && walk && lds_blocks_per_cu(walk_lds_bytes<G>()) >= 1 && cu_count() >= 1)
             return go_walk<G, TW, MODE>(a, s);
+        if (rows && a.pair_layout == kPairTile && a.colour < 0 && lds_blocks_per_cu(tile_lds_bytes<G>()) >= 1)
+            return go_tile<G, TW, MODE>(a, s);
     }
     if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup
@@ -125,7 +142,7 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
         const int64_t total = (int64_t)gxp * a.H;
         if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
         hipLaunchKernelGGL((sparse_update2_rows_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock), lds, s, a,
-                           gxp, gx, a.pair_layout == kPairWide || a.pair_layout == kPairWalk ? -1 : 0);
+                           gxp, gx, a.pair_layout == kPairWide || a.pair_layout >= kPairWalk ? -1 : 0);
         return hipGetLastError();
     }
     if constexpr (MODE == kSumF32) {

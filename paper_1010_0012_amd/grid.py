@@ -110,7 +110,7 @@ class Grid:
         v = out.cpu()
         return float(v[:1].view(torch.float32)[0]), int(v[1])
 
-    LAYOUTS = {"strips": 0, "bands": 1, "slots": 2, "wide": 3, "walk": 4}
+    LAYOUTS = {"strips": 0, "bands": 1, "slots": 2, "wide": 3, "walk": 4, "tile": 5}
 
     def set_launch_tuning(self, layout="wide", cap=-1):
         """Mapping of the two-iteration launches ("strips", "wide", "bands" or "slots")

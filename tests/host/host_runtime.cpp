@@ -125,7 +125,7 @@ static void potentials_and_layouts() {
                     EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_WIDE && cap == -1);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_SLOTS, 3) == BP_OK);
                     EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_SLOTS && cap == 3);
-                    EXPECT(bp_set_launch_tuning(&G, 5, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
+                    EXPECT(bp_set_launch_tuning(&G, 6, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_BANDS, 65) == BP_EINVAL && G.pair_cap == 3);
                     EXPECT(bp_get_launch_tuning(&G, nullptr, &cap) == BP_EINVAL);
                     // not ready (no unary): refused before any device work

@@ -40,7 +40,7 @@ def load(name):
     return {k: z[k] for k in z.files if k != "meta"}, json.loads(str(z["meta"]))
 
 
-def gpu_solve(meta, arith="f64"):
+def gpu_solve(meta, arith="f64", tuning=None):
     import torch
     src, mode, sched, n = meta["source"], meta["mode"], meta["schedule"], meta["n"]
     if src.startswith("batch:"):
@@ -63,6 +63,8 @@ def gpu_solve(meta, arith="f64"):
     grid.set_potential(cfg.M, cfg.T, cfg.alpha)
     grid.set_arithmetic(arith)
     grid.set_unary(torch.from_numpy(g32).cuda())
+    if tuning:
+        grid.set_launch_tuning(*tuning)
     grid.iterate(mode, n, sched)
     b = torch.empty((cfg.H, cfg.W, cfg.M), dtype=torch.float32, device="cuda")
     lab = torch.empty((cfg.H, cfg.W), dtype=torch.int32, device="cuda")
@@ -116,15 +118,18 @@ def test_end_to_end(name):
     assert not bad32, (name, bad32[:5])
 
 
-@pytest.mark.parametrize("name", ["stereo480x640_sum_sync", "stereo480x640_sum_checkerboard"])
-def test_end_to_end_f32_arithmetic(name):
+@pytest.mark.parametrize("name,layout", [("stereo480x640_sum_sync", "wide"), ("stereo480x640_sum_sync", "tile"),
+                                         ("stereo480x640_sum_sync", "walk"),
+                                         ("stereo480x640_sum_checkerboard", "wide")])
+def test_end_to_end_f32_arithmetic(name, layout):
     """The 480x640 sum-product solves with float32 arithmetic against the
     FP64 oracle's solve: the bar itself (beliefs within 1e-5, MAP equal where
-    the FP64 margin exceeds 1e-6)."""
+    the FP64 margin exceeds 1e-6), in the launch mappings the autotuner picks
+    between (the tile launch is the one the benchmark's autotuning keeps)."""
     ref, meta = load(name)
     H, W, M = meta["H"], meta["W"], meta["M"]
-    say(f"end-to-end {name}, float32 arithmetic")
-    g32, b, lab = gpu_solve(meta, arith="f32")
+    say(f"end-to-end {name}, float32 arithmetic, {layout}")
+    g32, b, lab = gpu_solve(meta, arith="f32", tuning=(layout, -1))
     np.testing.assert_array_equal(lab, np.argmax(b, axis=-1))
     err = float(np.max(np.abs(b.reshape(H * W, M)[ref["sample_idx"]] - ref["sample_b"])))
     bad = label_mismatches(lab, ref["labels"], ref["low_idx"], ref["low_margin"])

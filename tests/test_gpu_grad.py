@@ -107,7 +107,7 @@ def test_adjoint_same_bits_under_every_launch_mapping(M, T):
     included: the gradient is bitwise the same."""
     g32, y, _, _ = make_stereo(37, 45, M, 0.05, 4.0, "rectangles", 5 + M)
     ref = gpu_grad(g32, y, M, T, 0.8, 9, 4)
-    for tuning in (("walk", -1), ("strips", 0), ("bands", 3), ("slots", 0)):
+    for tuning in (("walk", -1), ("tile", -1), ("strips", 0), ("bands", 3), ("slots", 0)):
         say(f"M={M}: {tuning}")
         got = gpu_grad(g32, y, M, T, 0.8, 9, 4, tuning=tuning)
         np.testing.assert_array_equal(got[3], ref[3])

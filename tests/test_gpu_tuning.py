@@ -10,7 +10,7 @@ from synth_mrf import random_unary
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = ["strips", "wide", "bands", "slots", "walk"]
+LAYOUTS = ["strips", "wide", "bands", "slots", "walk", "tile"]
 CAPS = [-1, 0, 4, 3, 2, 1]  # the walk ignores the cap (its LDS ring sets two workgroups per CU)
 CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (37, 70, 64, 4, 0.5, "sum", "sync", "f64"),
@@ -72,7 +72,7 @@ def test_tuning_argument_errors():
     grid = Grid(8, 8)
     grid.set_potential(16, 2, 1.0)
     grid.set_unary(torch.from_numpy(random_unary(8, 8, 16, 1)).cuda())
-    for layout, cap in ((5, -1), (-1, 0), (0, -2), (0, 65)):
+    for layout, cap in ((6, -1), (-1, 0), (0, -2), (0, 65)):
         with pytest.raises(L.BPError) as e:
             L.bp_set_launch_tuning(grid.handle, layout, cap)
         assert e.value.status == L.BP_EINVAL
