@@ -98,6 +98,19 @@ hipError_t go_tile(const UpdateArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The checkerboard pass pair over tiles whose colour-c pixels compute.
+template <int G, int TW, int MODE>
+hipError_t go_tile_cb(const UpdateArgs& a, hipStream_t s) {
+    using S = TileCbShape<G>;
+    const int tiles_x = (a.W + S::TC - 1) / S::TC, tiles_y = (a.H + S::TR - 1) / S::TR;
+    const int txp = (tiles_x + kXcds - 1) / kXcds * kXcds;
+    const int64_t total = (int64_t)txp * tiles_y;
+    if (total >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sparse_tile2cb_kernel<G, TW, MODE>), dim3((unsigned)total), dim3(kBlock),
+                       tile_cb_lds_bytes<G>(), s, a, txp, tiles_x);
+    return hipGetLastError();
+}
+
 // Two synchronous iterations per launch (register windows only), in the
 // mapping a.pair_layout asks for where it applies: row blocks (M = 4G and
 // an inbox plane below 2^32 bytes) in XCD column strips, row bands or one
@@ -125,6 +138,8 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
             return go_walk<G, TW, MODE>(a, s);
         if (rows && a.pair_layout == kPairTile && a.colour < 0 && lds_blocks_per_cu(tile_lds_bytes<G>()) >= 1)
             return go_tile<G, TW, MODE>(a, s);
+        if (rows && a.pair_layout == kPairTile && a.colour >= 0 && lds_blocks_per_cu(tile_cb_lds_bytes<G>()) >= 1)
+            return go_tile_cb<G, TW, MODE>(a, s);
     }
     if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup

@@ -28,6 +28,11 @@ CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (64, 16, 128, 8, 0.4, "max", "sync", "f64"),
     (300, 40, 64, 4, 0.5, "sum", "sync", "f32"),
     (97, 530, 32, 2, 1.1, "sum", "sync", "f32"),
+    # the tile launch's checkerboard form: both colours' tile layouts, ragged
+    # tiles, halo pixels of either colour at every border
+    (37, 90, 32, 3, 0.6, "sum", "checkerboard", "f32"),
+    (21, 45, 64, 4, 0.5, "max", "checkerboard", "f64"),
+    (6, 9, 64, 4, 0.5, "sum", "checkerboard", "f32"),
 ]
 
 
