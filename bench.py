@@ -712,6 +712,8 @@ def main():
     # the other arithmetic beside it (double: every message its exact value rounded once)
     other = "f64" if args.arith == "f32" else "f32"
     grid.set_arithmetic(other)
+    if not args.tuning:
+        grid.set_launch_tuning("wide", -1)  # tuned from the default, not from the other arithmetic's choice
     o_us = grid.autotune("sum", "sync", 10) if not args.tuning else None
     o_tuning = grid.get_launch_tuning()
     launch_tuning[other] = {"layout": o_tuning[0], "cap": o_tuning[1], "autotune_us_per_iteration": o_us}

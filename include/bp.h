@@ -225,8 +225,9 @@ int bp_get_launch_tuning(const bp_grid* grid, int32_t* layout, int32_t* cap);
  * replaces the best only when at least 1% faster) for `mode` and `schedule`
  * (BP_SCHED_SYNC or
  * BP_SCHED_CHECKERBOARD): trial_iters iterations (even, >= 2) per candidate
- * after two warm-up iterations, timed with events on the grid's stream
- * (synchronises with it).  Needs the potential, the unary and the workspace;
+ * after two warm-up iterations, timed with events on the grid's stream, in
+ * two rounds over the candidates, each keeping its faster trial
+ * (synchronises with the stream).  Needs the potential, the unary and the workspace;
  * the messages are reset to uniform afterwards (the trials iterate them).
  * *best_us (if not null): microseconds per iteration of the winner.
  * BP_EINVAL for a bad mode, schedule or trial_iters; BP_ESTATE when the grid

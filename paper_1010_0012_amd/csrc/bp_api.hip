@@ -1,6 +1,8 @@
 // C ABI of the grid BP library: handle state, argument and call-order checks,
 // potential tables, workspace carving and kernel dispatch.
 #include <dlfcn.h>
+
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -305,24 +307,34 @@ int bp_autotune(bp_grid* G, int32_t mode, int32_t schedule, int32_t trial_iters,
         for (int cap : {0, 4, 3}) cands.push_back({layout, cap});
     cands.push_back({BP_PAIR_WALK, -1});
     cands.push_back({BP_PAIR_TILE, -1});
-    for (const Cand& c : cands) {
-        G->pair_layout = c.layout;
-        G->pair_cap = c.cap;
-        if ((st = iterate(G, mode, 2, schedule, false))) break;  // warm
-        e = hipEventRecord(e0, G->stream);
-        if (e == hipSuccess && (st = iterate(G, mode, trial_iters, schedule, false))) break;
-        if (e == hipSuccess) e = hipEventRecord(e1, G->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "autotune trial");
-            break;
+    // Two rounds over the candidates, each candidate keeping its faster
+    // trial: the clock drifts while the trials run, and a single pass lets
+    // that drift, rather than the mapping, decide between near-equal ones.
+    std::vector<float> trial(cands.size(), 1e30f);
+    for (int round = 0; round < 2 && !st; ++round) {
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Cand& c = cands[ci];
+            G->pair_layout = c.layout;
+            G->pair_cap = c.cap;
+            if ((st = iterate(G, mode, 2, schedule, false))) break;  // warm
+            e = hipEventRecord(e0, G->stream);
+            if (e == hipSuccess && (st = iterate(G, mode, trial_iters, schedule, false))) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, G->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "autotune trial");
+                break;
+            }
+            trial[ci] = std::min(trial[ci], ms);
         }
-        if (ms < 0.99f * best) {
-            best = ms;
-            best_layout = c.layout;
-            best_cap = c.cap;
+    }
+    for (size_t ci = 0; ci < cands.size() && !st; ++ci) {
+        if (trial[ci] < 0.99f * best) {
+            best = trial[ci];
+            best_layout = cands[ci].layout;
+            best_cap = cands[ci].cap;
         }
     }
     (void)hipEventDestroy(e0);
