@@ -90,23 +90,25 @@ def test_tuning_argument_errors():
     grid.close()
 
 
+@pytest.mark.parametrize("layout", ["walk", "tile"])
 @pytest.mark.parametrize("M,T,arith", [(32, 3, "f32"), (64, 4, "f64")])
-def test_multiscale_same_bits_under_the_walk(M, T, arith):
+def test_multiscale_same_bits_under_the_walk(M, T, arith, layout):
     """Multi-scale BP runs every level's synchronous pairs in the grid's
-    mapping: the walk (coarse levels included) gives the wide strips' bits."""
+    mapping: the walk and the tile launch (coarse levels included) give the
+    wide strips' bits."""
     import torch
     from paper_1010_0012_amd.grid import Grid
     H, W = 100, 130
     g = torch.from_numpy(random_unary(H, W, M, 11)).cuda()
     out = {}
-    for layout in ("wide", "walk"):
+    for lay in ("wide", layout):
         grid = Grid(H, W)
         grid.set_potential(M, T, 0.6)
         grid.set_arithmetic(arith)
         grid.set_unary(g)
-        grid.set_launch_tuning(layout, -1)
+        grid.set_launch_tuning(lay, -1)
         grid.iterate_multiscale("sum", (4, 6, 6))
-        out[layout] = grid.get_messages().cpu().numpy()
+        out[lay] = grid.get_messages().cpu().numpy()
         torch.cuda.synchronize()
         grid.close()
-    np.testing.assert_array_equal(out["walk"], out["wide"])
+    np.testing.assert_array_equal(out[layout], out["wide"])
