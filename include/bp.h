@@ -184,9 +184,10 @@ int bp_set_arithmetic(bp_grid* grid, int32_t arith);
  * BP_PAIR_STRIPS); BP_PAIR_WALK, for synchronous launches with M = 32 or 64,
  * one workgroup per strip of columns walking down a chunk of rows, each
  * grid row's unary and inbox staged once in LDS (checkerboard pairs and
- * other M run BP_PAIR_WIDE); BP_PAIR_TILE, for synchronous launches and
- * checkerboard pass pairs with M = 32 or 64, one workgroup per pixel tile
- * whose rows and halo are staged once in LDS (other M run BP_PAIR_WIDE).
+ * other M run BP_PAIR_WIDE); BP_PAIR_TILE, for synchronous launches with
+ * M = 16, 32, 64 or 128 and checkerboard pass pairs with M = 32, 64 or 128,
+ * one workgroup per pixel tile whose rows and halo are staged once in LDS
+ * (other M run BP_PAIR_WIDE).
  * cap: the
  * most workgroups per compute unit the
  * launch's LDS request allows (0 none, 1..64, -1 the default: 4 with float32

@@ -130,16 +130,21 @@ hipError_t go_sparse2(const UpdateArgs& a, hipStream_t s) {
     if constexpr (MODE == kSumF32) {
         if (!rows) return hipErrorInvalidValue;  // float32 arithmetic: row-block launches only
     }
+    if constexpr (G <= 32) {
+        // the tile launch (synchronous: M = 16 .. 128; checkerboard pairs: M = 32 .. 128)
+        if (rows && a.pair_layout == kPairTile && a.colour < 0 && lds_blocks_per_cu(tile_lds_bytes<G>()) >= 1)
+            return go_tile<G, TW, MODE>(a, s);
+        if constexpr (G >= 8) {
+            if (rows && a.pair_layout == kPairTile && a.colour >= 0 && lds_blocks_per_cu(tile_cb_lds_bytes<G>()) >= 1)
+                return go_tile_cb<G, TW, MODE>(a, s);
+        }
+    }
     if constexpr (G == 8 || G == 16) {
         // the walk where it applies and its LDS ring fits the device; else the wide strips
         const bool walk = a.pair_layout == kPairWalk && a.colour < 0 &&
                           (uint64_t)a.N * a.M * sizeof(float) <= (uint64_t(1) << 31);
         if (rows && walk && lds_blocks_per_cu(walk_lds_bytes<G>()) >= 1 && cu_count() >= 1)
             return go_walk<G, TW, MODE>(a, s);
-        if (rows && a.pair_layout == kPairTile && a.colour < 0 && lds_blocks_per_cu(tile_lds_bytes<G>()) >= 1)
-            return go_tile<G, TW, MODE>(a, s);
-        if (rows && a.pair_layout == kPairTile && a.colour >= 0 && lds_blocks_per_cu(tile_cb_lds_bytes<G>()) >= 1)
-            return go_tile_cb<G, TW, MODE>(a, s);
     }
     if (rows && (MODE == kSumF32 || a.pair_layout != kPairSlots)) {
         // row-block launch: kBlock/G pixels (or colour slots) of one row per workgroup

@@ -22,7 +22,7 @@ namespace bpk {
 template <int G>
 struct TileShape {
     static constexpr int NPX = kBlock / G;               // pixels per tile
-    static constexpr int TR = 4;                         // tile rows
+    static constexpr int TR = NPX >= 64 ? 8 : 4;         // tile rows (8 x 8 at M = 16)
     static constexpr int TC = NPX / TR;                  // tile columns
     static constexpr int NH = 2 * (TR + TC);             // halo pixels
     static constexpr int OWN_ROWS = 5 * NPX;             // own pixels: g, inbox L, R, U, D

@@ -33,6 +33,10 @@ CASES = [  # H, W, M, T, alpha, mode, schedule, arith
     (37, 90, 32, 3, 0.6, "sum", "checkerboard", "f32"),
     (21, 45, 64, 4, 0.5, "max", "checkerboard", "f64"),
     (6, 9, 64, 4, 0.5, "sum", "checkerboard", "f32"),
+    # tiles at M = 16 (8 x 8) and M = 128 (4 x 2, checkerboard 4 x 4)
+    (45, 70, 16, 2, 1.0, "sum", "sync", "f32"),
+    (19, 27, 16, 2, 1.0, "max", "sync", "f64"),
+    (23, 37, 128, 8, 0.3, "sum", "checkerboard", "f32"),
 ]
 
 
