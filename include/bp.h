@@ -192,7 +192,10 @@ int bp_set_arithmetic(bp_grid* grid, int32_t arith);
  * most workgroups per compute unit the
  * launch's LDS request allows (0 none, 1..64, -1 the default: 4 with float32
  * arithmetic, none with double; BP_PAIR_WALK's LDS ring and BP_PAIR_TILE's
- * tile set their own, whatever the cap).  Every setting computes the same messages
+ * tile set their own, whatever the cap).  Until this call or bp_autotune
+ * chooses one, the mapping follows the arithmetic (bp_set_arithmetic):
+ * BP_PAIR_TILE with float32 arithmetic, BP_PAIR_WIDE with double, cap -1.
+ * Every setting computes the same messages
  * bit for bit; only the speed differs.  BP_EINVAL for a null handle, a
  * layout outside the enum or a cap outside -1..64.  Kept per grid; used by
  * every launch of the grid, including bp_forward_ckpt and multi-scale. */

@@ -269,6 +269,7 @@ int bp_set_launch_tuning(bp_grid* G, int32_t layout, int32_t cap) {
     if (cap < -1 || cap > 64) return fail(BP_EINVAL, "bad workgroups-per-CU cap %d", cap);
     G->pair_layout = layout;
     G->pair_cap = cap;
+    G->pair_layout_set = true;
     return BP_OK;
 }
 
@@ -341,6 +342,7 @@ int bp_autotune(bp_grid* G, int32_t mode, int32_t schedule, int32_t trial_iters,
     (void)hipEventDestroy(e1);
     G->pair_layout = st ? layout0 : best_layout;
     G->pair_cap = st ? cap0 : best_cap;
+    if (!st) G->pair_layout_set = true;
     if (st) return st;
     if (best_us) *best_us = best * 1000.0f / trial_iters;
     return bp_reset_messages(G);
@@ -350,6 +352,9 @@ int bp_set_arithmetic(bp_grid* G, int32_t arith) {
     if (!G) return fail(BP_EINVAL, "null handle");
     if (arith != BP_ARITH_F64 && arith != BP_ARITH_F32) return fail(BP_EINVAL, "bad arithmetic %d", arith);
     G->arith_f32 = arith == BP_ARITH_F32;
+    // the default mapping follows the arithmetic: the tile launch for float32
+    // (where it applies; elsewhere it runs the wide strips), wide strips for double
+    if (!G->pair_layout_set) G->pair_layout = G->arith_f32 ? bpk::kPairTile : bpk::kPairWide;
     return BP_OK;
 }
 

@@ -30,6 +30,7 @@ struct bp_grid {
     bool fuse_sync = true;                // sync iterations run two per launch where compiled
     bool arith_f32 = false;               // BP_ARITH_F32: float32 arithmetic where compiled
     int pair_layout = bpk::kPairWide;     // two-iteration launch mapping (bpk::PairLayout)
+    bool pair_layout_set = false;         // chosen by bp_set_launch_tuning or bp_autotune (else it follows the arithmetic)
     int pair_cap = -1;                    // its workgroups per CU (0: no cap, -1: the default)
     const float* g = nullptr;
     // general sparse potentials (bp_set_sparse_potentials), or the Eq. 10

@@ -123,6 +123,9 @@ static void potentials_and_layouts() {
                 {
                     int32_t lay = -7, cap = -7;
                     EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_WIDE && cap == -1);
+                    // the default mapping follows the arithmetic until one is chosen
+                    EXPECT(bp_set_arithmetic(&G, BP_ARITH_F32) == BP_OK && G.pair_layout == BP_PAIR_TILE);
+                    EXPECT(bp_set_arithmetic(&G, BP_ARITH_F64) == BP_OK && G.pair_layout == BP_PAIR_WIDE);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_SLOTS, 3) == BP_OK);
                     EXPECT(bp_get_launch_tuning(&G, &lay, &cap) == BP_OK && lay == BP_PAIR_SLOTS && cap == 3);
                     EXPECT(bp_set_launch_tuning(&G, 6, 0) == BP_EINVAL && G.pair_layout == BP_PAIR_SLOTS);
@@ -130,6 +133,8 @@ static void potentials_and_layouts() {
                     EXPECT(bp_get_launch_tuning(&G, nullptr, &cap) == BP_EINVAL);
                     // not ready (no unary): refused before any device work
                     EXPECT(bp_autotune(&G, BP_SUM_PRODUCT, BP_SCHED_SYNC, 2, nullptr) == BP_ESTATE);
+                    EXPECT(bp_set_arithmetic(&G, BP_ARITH_F32) == BP_OK && G.pair_layout == BP_PAIR_SLOTS);
+                    EXPECT(bp_set_arithmetic(&G, BP_ARITH_F64) == BP_OK && G.pair_layout == BP_PAIR_SLOTS);
                     EXPECT(bp_set_launch_tuning(&G, BP_PAIR_WIDE, -1) == BP_OK);
                 }
                 // other potentials on the same handle
